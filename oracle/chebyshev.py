@@ -59,6 +59,14 @@ def d2_spectral_radius(N: int) -> float:
 
 
 @functools.lru_cache(maxsize=None)
+def d2_row_sum_bound(N: int) -> float:
+    """max_i sum_j |D2_ij|: an upper bound of the spectral radius of the interior
+    second-derivative matrix (Gershgorin), about 1.5 times the radius itself."""
+    _, D2 = diff_matrices(N)
+    return float(np.max(np.sum(np.abs(D2), axis=1)))
+
+
+@functools.lru_cache(maxsize=None)
 def cc_weights(N: int) -> np.ndarray:
     """Clenshaw-Curtis weights on all N+2 nodes, found from their defining
     property: the rule integrates T_m exactly on [-1, 1] for m = 0..n."""

@@ -192,11 +192,12 @@ def create(model, prior) -> State:
 
 def _rho(model, a: int) -> float:
     """Largest |wavenumber| per axis in index units: pi for Fourier (the Nyquist
-    mode), sqrt of the spectral radius of the interior second-derivative matrix
-    for Chebyshev."""
+    mode); for Chebyshev the square root of the row-sum bound of the interior
+    second-derivative matrix (a bound of its spectral radius that needs no
+    eigen-solver; the two largest eigenvalues nearly coincide)."""
     if model.grid == FOURIER:
         return math.pi
-    return math.sqrt(cheb.d2_spectral_radius(model.N[a]))
+    return math.sqrt(cheb.d2_row_sum_bound(model.N[a]))
 
 
 def lambda_bound(model, Dy: np.ndarray) -> float:
