@@ -1,0 +1,213 @@
+/*
+ * pmf.h -- C ABI of the MI355X spectral point-mass filter library (libpmf.so).
+ *
+ * The library carries grid-based probability densities of the state of a linear
+ * SDE  dx = A x dt + Q dw  (E[dw dw^T] = I dt; Sec. I, eq. dynam) through
+ *   - the time update: the Fokker-Planck equation of Sec. I.B (eq. fokker) on a
+ *     grid that moves with x' = A x (Sec. II.B, eqs. movFPEadv / easyFPE), solved
+ *     with spectral derivatives (Sec. IV, eqs. fourtrsf / interFreq / secDer;
+ *     Sec. V Algorithm) on a Fourier grid, or with Chebyshev differentiation
+ *     matrices (Sec. IV.B) on a Chebyshev grid;
+ *   - the measurement update: Bayes' rule of Sec. I.A (eq. filt) with the
+ *     measurement z = h(x) + v of eq. meas, the normalisation of Sec. III.A
+ *     (eq. PDF_pm), then a new grid and re-interpolation onto it.
+ * The diffusion matrix of the Fokker-Planck equation is D = Q Q^T.
+ *
+ * Conventions for every entry point:
+ *   - Plain pointers and sizes only.  Host pointers are owned by the caller and
+ *     are only read or written during the call (or, for `loglik`, by the
+ *     asynchronous copy that the call enqueues -- see pmf_update).
+ *   - Device memory is owned by the library; it is obtained through the
+ *     allocator given to pmf_ctx_create (NULL = hipMalloc/hipFree).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *     marked "async" only enqueue work on it.
+ *   - Errors found on the host are returned at once and leave all state as it
+ *     was.  Errors found on the device (a zero or non-finite normaliser) leave
+ *     the density and grid as they were and are reported by the next call that
+ *     synchronises (pmf_moments, pmf_get_state, pmf_sync_status).
+ *   - No C++ exception crosses this boundary.  One filter must not be used by
+ *     two threads at once; distinct filters and contexts are independent.
+ *   - pmf_last_error() returns a thread-local message for the last failure.
+ *
+ * Density layout in device memory: prod(N[0..nx-1]) values of the filter's
+ * precision, C order (last axis fastest).  Fourier grids: node j sits at
+ * x_j = c + M (j - N/2).  Chebyshev grids: x = c + M u, u_a = -cos(j_a pi/(N_a+1)),
+ * j_a = 1..N_a (the interior of a Chebyshev-Gauss-Lobatto set; the density is
+ * zero at u = +-1).  M's columns are the per-index step vectors (Fourier) or the
+ * half-width vectors (Chebyshev).
+ */
+#ifndef PMF_H
+#define PMF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMF_OK = 0,
+    PMF_E_INVALID = 1,     /* bad argument; nothing was changed */
+    PMF_E_NOMEM = 2,       /* device allocation failed */
+    PMF_E_DEVICE = 3,      /* a HIP call failed */
+    PMF_E_DEGENERATE = 4,  /* a measurement update met a zero / non-finite normaliser
+                              or grid; that update left density and grid unchanged */
+    PMF_E_BUSY = 5,        /* server: no slot or memory for the request now */
+    PMF_W_BOUNDARY = 64    /* warning bit: a posterior had more than 1e-4 of its mass
+                              on the outermost layer of grid nodes */
+} pmf_status;
+
+enum { PMF_GRID_FOURIER = 0, PMF_GRID_CHEBYSHEV = 1 };
+enum { PMF_INT_EXACT = 0, PMF_INT_RK4 = 1, PMF_INT_EULER = 2 };
+enum { PMF_INTERP_AUTO = 0, PMF_INTERP_LAGRANGE = 1 };
+enum { PMF_H_LINEAR = 0, PMF_H_CUBIC1 = 1, PMF_H_NORM = 2 };
+enum { PMF_FP64 = 0, PMF_FP32 = 1 };
+
+#define PMF_MAX_NX 3
+#define PMF_MAX_MIX 4
+
+typedef struct {
+    /* alloc(bytes, user, stream) -> device pointer or NULL; free(ptr, user, stream) */
+    void* (*alloc)(size_t, void* user, void* stream);
+    void (*free)(void*, void* user, void* stream);
+    void* user;
+} pmf_allocator;
+
+/* Model of one filter (Sec. I, eqs. dynam/meas). */
+typedef struct {
+    int nx;                     /* state dimension, 1..3 */
+    double A[9];                /* row-major nx x nx drift matrix */
+    double Q[9];                /* row-major nx x nx noise gain; D = Q Q^T */
+    int grid;                   /* PMF_GRID_FOURIER or PMF_GRID_CHEBYSHEV */
+    int N[3];                   /* points per axis.  Fourier: even, 2^a 3^b, 4..256.
+                                   Chebyshev: 4..256 */
+    double span_sigmas;         /* grid half-width in standard deviations (e.g. 8) */
+    double t_nominal;           /* interval used by the grid design, > 0 */
+    int integrator;             /* PMF_INT_EXACT | PMF_INT_RK4 | PMF_INT_EULER
+                                   (Chebyshev grids: RK4 only) */
+    int substeps;               /* minimum number of substeps l (>= 1) */
+    int precision;              /* PMF_FP64 or PMF_FP32 density; reductions are FP64 */
+    int interp;                 /* PMF_INTERP_AUTO: spectral (trigonometric or
+                                   Chebyshev polynomial) per axis when the old grid is
+                                   axis aligned, else cubic Lagrange; PMF_INTERP_LAGRANGE:
+                                   always cubic Lagrange */
+    int meas_kind;              /* PMF_H_LINEAR: h = H x;  PMF_H_CUBIC1: h = a1 x1 + a3 x1^3
+                                   (hparam[0], hparam[1]);  PMF_H_NORM: h = ||x|| */
+    int nz;                     /* measurement dimension (1 for CUBIC1 and NORM), 1..3 */
+    double H[9];                /* row-major nz x nx (PMF_H_LINEAR) */
+    double hparam[4];
+    int noise_ncomp;            /* Gaussian-mixture components of v, 1..4 */
+    double noise_w[4];          /* weights (normalised by the library) */
+    double noise_mean[4 * 3];   /* component g: noise_mean[3g .. 3g+nz) */
+    double noise_cov[4 * 9];    /* component g: row-major nz x nz at noise_cov[9g] */
+} pmf_model;
+
+/* Gaussian-mixture prior p(x0) (Sec. I). */
+typedef struct {
+    int ncomp;                  /* 1..4 */
+    double w[4];
+    double mean[4 * 3];         /* component g at mean[3g] */
+    double cov[4 * 9];          /* component g: row-major nx x nx at cov[9g] */
+} pmf_prior;
+
+/* Header of the host image written by pmf_get_state; the density follows it
+ * (prod(N) values of the filter's precision, C order). */
+typedef struct {
+    unsigned int magic;         /* PMF_STATE_MAGIC */
+    int version;                /* 1 */
+    int nx, grid, precision, status;
+    int N[3];
+    int pad;
+    double c[3];
+    double M[9];                /* row-major */
+    double t;
+} pmf_state_header;
+#define PMF_STATE_MAGIC 0x504d4631u
+
+typedef struct pmf_ctx pmf_ctx;
+typedef struct pmf_filter pmf_filter;
+
+/* Context bound to one HIP device.  `a` may be NULL (hipMalloc/hipFree).
+ * The allocator struct is copied. */
+pmf_status pmf_ctx_create(int device, const pmf_allocator* a, pmf_ctx** out);
+void pmf_ctx_destroy(pmf_ctx* ctx);
+
+/* New filter: validates the model, designs the first grid from the prior's
+ * mean and covariance (centre = mean, half-widths span_sigmas * sqrt(diag(cov +
+ * W(t_nominal))), W(T) = int_0^T e^{-As} D e^{-A^T s} ds), evaluates the prior PDF
+ * at the nodes and normalises (Sec. III.A).  Synchronous; uses the null stream. */
+pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* prior,
+                      pmf_filter** out);
+void pmf_destroy(pmf_filter* f);
+
+/* Time update over an interval T >= 0 (Sec. I.B; Sec. V Algorithm).  Async.
+ * Fourier grids: forward FFT, per-mode gain, inverse FFT; the gain is
+ *   exact:  exp(-1/2 kappa^T W_y kappa),  W_y = M^-1 W(T) M^-T;
+ *   rk4:    the product over l substeps of the classic RK4 amplification of
+ *           lambda(t) = -1/2 kappa^T D_y(t) kappa,  D_y(t) = M(t)^-1 D M(t)^-T;
+ *   euler:  the product of 1 / (1 + h/2 kappa^T D_y(t_n) kappa), n = 0..l-1
+ *           (implicit diffusion, Sec. V.A);
+ * times e^{-tr(A) T} (the trace term of eq. easyFPE).  Mixed derivatives use the
+ * first-derivative symbol (no Nyquist term), squares keep it (eq. secDer).
+ * Chebyshev grids: classic RK4 with dense differentiation matrices.
+ * RK4 uses l = max(substeps, ceil(T lambda_max / 2.5)) substeps; lambda_max bounds
+ * 1/2 sum_ab |D_y,ab| rho_a rho_b at t = 0, T/2, T (rho = pi for Fourier axes, the
+ * square root of the spectral radius of the second-derivative matrix for
+ * Chebyshev axes).  Then c <- e^{AT} c, M <- e^{AT} M, t <- t + T. */
+pmf_status pmf_predict(pmf_filter* f, double T, void* stream);
+
+/* Measurement update with z[0..nz) (Sec. I.A).  Async.  log p(z_k | z^{k-1})
+ * is written to *loglik by an asynchronous copy enqueued on `stream` when loglik
+ * is not NULL: the caller must synchronise the stream before reading it (pinned
+ * host memory keeps the copy asynchronous).  Non-finite z -> PMF_E_INVALID.
+ * Steps: log-likelihood at the nodes, shift by its maximum, multiply, FP64
+ * normaliser and moments, new grid (centre = posterior mean, half-widths from the
+ * posterior covariance + W(t_nominal)), interpolation onto it (zero outside the
+ * old grid), renormalisation.  A zero or non-finite normaliser leaves the filter
+ * unchanged and sets PMF_E_DEGENERATE in its status word. */
+pmf_status pmf_update(pmf_filter* f, const double* z, double* loglik, void* stream);
+
+/* Mean (nx) and covariance (row-major nx x nx) of the current density, FP64.
+ * Synchronises `stream`.  Returns the status word collected since the last
+ * synchronising call (PMF_E_DEGENERATE and/or PMF_W_BOUNDARY bits) and clears it. */
+pmf_status pmf_moments(pmf_filter* f, double* mean, double* cov, void* stream);
+
+/* Synchronise `stream` and return / clear the status word as pmf_moments does. */
+pmf_status pmf_sync_status(pmf_filter* f, void* stream);
+
+/* Substeps the last pmf_predict used (synchronises the null stream). */
+pmf_status pmf_last_substeps(pmf_filter* f, int* l);
+
+/* Copy grid + density to a host image.  If host_buf is NULL, only *bytes is set.
+ * Synchronous (device synchronise). */
+pmf_status pmf_get_state(pmf_filter* f, void* host_buf, size_t* bytes);
+
+/* Replace grid + density from a host image written by pmf_get_state of a filter
+ * with the same nx, grid kind, N and precision.  Synchronous. */
+pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
+
+/* One predict(T) + update(z) cycle for n filters in one fused launch (Fourier
+ * grids, FP32, nx <= 2, N_a <= 128 per axis for nx = 2, N <= 256 for nx = 1;
+ * other filters are rejected with PMF_E_INVALID before anything runs).
+ * z: n * nz_max doubles, row f holds filter f's measurement (nz_max = largest nz).
+ * loglik: NULL or n doubles written by an asynchronous copy (as pmf_update).
+ * The step is recorded once as a HIP graph per (filter set, T, stream) and
+ * replayed; results equal n separate pmf_predict + pmf_update calls up to FP32
+ * rounding of the likelihood shift.  Async. */
+pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
+                          const double* z, double* loglik, void* stream);
+
+/* Device pointer of the density (for zero-copy inspection in tests); valid until
+ * the next call on the filter.  Returns NULL on error. */
+void* pmf_density_ptr(pmf_filter* f);
+
+/* Wait for all work enqueued on `stream` (NULL = null stream). */
+pmf_status pmf_stream_sync(void* stream);
+
+const char* pmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMF_H */

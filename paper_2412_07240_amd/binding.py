@@ -1,0 +1,285 @@
+"""Thin ctypes binding of libpmf (include/pmf.h): same names, argument marshalling
+only.  Every step of the filter runs in the HIP library; nothing here computes.
+
+Models and priors are taken from any object with the fields of ``pmf_model`` /
+``pmf_prior`` (``nx, A, Q, N, grid, ...``; ``w, mean, cov``).  Streams are HIP
+stream handles: a ``torch.cuda.Stream``, its integer ``cuda_stream``, or None.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmf.so")
+
+PMF_OK, PMF_E_INVALID, PMF_E_NOMEM, PMF_E_DEVICE, PMF_E_DEGENERATE, PMF_E_BUSY = 0, 1, 2, 3, 4, 5
+PMF_W_BOUNDARY = 64
+PMF_FP64, PMF_FP32 = 0, 1
+PMF_STATE_MAGIC = 0x504D4631
+
+
+class pmf_model(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("A", C.c_double * 9), ("Q", C.c_double * 9), ("grid", C.c_int),
+        ("N", C.c_int * 3), ("span_sigmas", C.c_double), ("t_nominal", C.c_double),
+        ("integrator", C.c_int), ("substeps", C.c_int), ("precision", C.c_int), ("interp", C.c_int),
+        ("meas_kind", C.c_int), ("nz", C.c_int), ("H", C.c_double * 9), ("hparam", C.c_double * 4),
+        ("noise_ncomp", C.c_int), ("noise_w", C.c_double * 4), ("noise_mean", C.c_double * 12),
+        ("noise_cov", C.c_double * 36),
+    ]
+
+
+class pmf_prior(C.Structure):
+    _fields_ = [("ncomp", C.c_int), ("w", C.c_double * 4), ("mean", C.c_double * 12),
+                ("cov", C.c_double * 36)]
+
+
+class pmf_state_header(C.Structure):
+    _fields_ = [("magic", C.c_uint), ("version", C.c_int), ("nx", C.c_int), ("grid", C.c_int),
+                ("precision", C.c_int), ("status", C.c_int), ("N", C.c_int * 3), ("pad", C.c_int),
+                ("c", C.c_double * 3), ("M", C.c_double * 9), ("t", C.c_double)]
+
+
+class PmfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pmf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libpmf.so; fails loudly when the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2412_07240_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
+        sig = {
+            "pmf_ctx_create": (ip, [ip, vp, C.POINTER(vp)]),
+            "pmf_ctx_destroy": (None, [vp]),
+            "pmf_create": (ip, [vp, C.POINTER(pmf_model), C.POINTER(pmf_prior), C.POINTER(vp)]),
+            "pmf_destroy": (None, [vp]),
+            "pmf_predict": (ip, [vp, C.c_double, vp]),
+            "pmf_update": (ip, [vp, dp, dp, vp]),
+            "pmf_moments": (ip, [vp, dp, dp, vp]),
+            "pmf_sync_status": (ip, [vp, vp]),
+            "pmf_last_substeps": (ip, [vp, C.POINTER(C.c_int)]),
+            "pmf_get_state": (ip, [vp, vp, C.POINTER(C.c_size_t)]),
+            "pmf_set_state": (ip, [vp, vp, C.c_size_t]),
+            "pmf_batch_step": (ip, [vp, C.POINTER(vp), ip, C.c_double, dp, dp, vp]),
+            "pmf_density_ptr": (vp, [vp]),
+            "pmf_stream_sync": (ip, [vp]),
+            "pmf_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("pmf_ctx_create", "pmf_ctx_destroy", "pmf_create", "pmf_destroy", "pmf_predict",
+            "pmf_update", "pmf_moments", "pmf_sync_status", "pmf_last_substeps", "pmf_get_state",
+            "pmf_set_state", "pmf_batch_step", "pmf_density_ptr", "pmf_stream_sync", "pmf_last_error")
+
+
+def pmf_last_error() -> str:
+    return lib().pmf_last_error().decode()
+
+
+def _check(status: int, ok=(PMF_OK,)):
+    if status not in ok:
+        raise PmfError(status, pmf_last_error())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _fill(arr, values):
+    flat = np.asarray(values, dtype=float).ravel()
+    for i, v in enumerate(flat):
+        arr[i] = float(v)
+
+
+def make_model(spec) -> pmf_model:
+    m = pmf_model()
+    nx = int(spec.nx)
+    m.nx = nx
+    _fill(m.A, np.asarray(spec.A, float).reshape(nx, nx))
+    _fill(m.Q, np.asarray(spec.Q, float).reshape(nx, nx))
+    m.grid = int(spec.grid)
+    _fill_int = list(spec.N) + [1] * (3 - nx)
+    for i in range(3):
+        m.N[i] = int(_fill_int[i])
+    m.span_sigmas = float(spec.span_sigmas)
+    m.t_nominal = float(spec.t_nominal)
+    m.integrator = int(spec.integrator)
+    m.substeps = int(spec.substeps)
+    m.precision = int(spec.precision)
+    m.interp = int(spec.interp)
+    m.meas_kind = int(spec.meas_kind)
+    m.nz = int(spec.nz)
+    if int(spec.meas_kind) == 0:
+        _fill(m.H, np.asarray(spec.H, float).reshape(m.nz, nx))
+    _fill(m.hparam, np.asarray(spec.hparam, float).ravel()[:4])
+    w = np.asarray(spec.noise_w, float).ravel()
+    m.noise_ncomp = len(w)
+    _fill(m.noise_w, w)
+    means = np.asarray(spec.noise_mean, float).reshape(len(w), -1)
+    covs = np.asarray(spec.noise_cov, float).reshape(len(w), m.nz, m.nz)
+    for g in range(len(w)):
+        for i in range(m.nz):
+            m.noise_mean[3 * g + i] = means[g, i]
+            for j in range(m.nz):
+                m.noise_cov[9 * g + i * m.nz + j] = covs[g, i, j]
+    return m
+
+
+def make_prior(spec, nx: int) -> pmf_prior:
+    p = pmf_prior()
+    w = np.asarray(spec.w, float).ravel()
+    p.ncomp = len(w)
+    _fill(p.w, w)
+    means = np.asarray(spec.mean, float).reshape(len(w), nx)
+    covs = np.asarray(spec.cov, float).reshape(len(w), nx, nx)
+    for g in range(len(w)):
+        for i in range(nx):
+            p.mean[3 * g + i] = means[g, i]
+            for j in range(nx):
+                p.cov[9 * g + i * nx + j] = covs[g, i, j]
+    return p
+
+
+def pmf_ctx_create(device: int = 0):
+    out = C.c_void_p()
+    _check(lib().pmf_ctx_create(device, None, C.byref(out)))
+    return out
+
+
+def pmf_ctx_destroy(ctx) -> None:
+    lib().pmf_ctx_destroy(ctx)
+
+
+def pmf_create(ctx, model, prior):
+    out = C.c_void_p()
+    m = make_model(model)
+    p = make_prior(prior, int(model.nx))
+    _check(lib().pmf_create(ctx, C.byref(m), C.byref(p), C.byref(out)))
+    return out
+
+
+def pmf_destroy(f) -> None:
+    lib().pmf_destroy(f)
+
+
+def pmf_predict(f, T: float, stream=None) -> None:
+    _check(lib().pmf_predict(f, float(T), _stream(stream)))
+
+
+def pmf_update(f, z, stream=None, want_loglik: bool = False):
+    """Enqueue the update; with want_loglik the stream is synchronised and
+    log p(z | past) is returned."""
+    zz = np.ascontiguousarray(np.atleast_1d(np.asarray(z, float)))
+    zp = zz.ctypes.data_as(C.POINTER(C.c_double))
+    if not want_loglik:
+        _check(lib().pmf_update(f, zp, None, _stream(stream)))
+        return None
+    ll = C.c_double(float("nan"))
+    _check(lib().pmf_update(f, zp, C.byref(ll), _stream(stream)))
+    _check(lib().pmf_stream_sync(_stream(stream)))
+    return ll.value
+
+
+def pmf_moments(f, nx: int, stream=None):
+    """(mean, cov, status) of the current density; status carries the warning bits."""
+    mean = np.zeros(nx)
+    cov = np.zeros((nx, nx))
+    st = lib().pmf_moments(f, mean.ctypes.data_as(C.POINTER(C.c_double)),
+                           cov.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream))
+    if st & ~(PMF_W_BOUNDARY | PMF_E_DEGENERATE):
+        raise PmfError(st, pmf_last_error())
+    return mean, cov, st
+
+
+def pmf_sync_status(f, stream=None) -> int:
+    st = lib().pmf_sync_status(f, _stream(stream))
+    if st & ~(PMF_W_BOUNDARY | PMF_E_DEGENERATE):
+        raise PmfError(st, pmf_last_error())
+    return st
+
+
+def pmf_last_substeps(f) -> int:
+    l = C.c_int()
+    _check(lib().pmf_last_substeps(f, C.byref(l)))
+    return l.value
+
+
+def pmf_get_state(f):
+    """(header, c, M, t, density ndarray) of the current state."""
+    nbytes = C.c_size_t(0)
+    _check(lib().pmf_get_state(f, None, C.byref(nbytes)))
+    buf = (C.c_ubyte * nbytes.value)()
+    _check(lib().pmf_get_state(f, buf, C.byref(nbytes)))
+    h = pmf_state_header.from_buffer_copy(buf)
+    nx = h.nx
+    shape = tuple(h.N[i] for i in range(nx))
+    dt = np.float64 if h.precision == PMF_FP64 else np.float32
+    off = C.sizeof(pmf_state_header)
+    P = np.frombuffer(bytes(buf)[off:], dtype=dt, count=int(np.prod(shape))).reshape(shape).copy()
+    c = np.array(h.c[:nx])
+    M = np.array(h.M[:]).reshape(3, 3)[:nx, :nx].copy()
+    return h, c, M, h.t, P
+
+
+def pmf_set_state(f, c, M, t, P, grid: int, precision: int) -> None:
+    """Replace grid (c, M, t) and density P of a filter of the same kind."""
+    P = np.ascontiguousarray(P, dtype=np.float64 if precision == PMF_FP64 else np.float32)
+    nx = P.ndim
+    h = pmf_state_header()
+    h.magic = PMF_STATE_MAGIC
+    h.version = 1
+    h.nx = nx
+    h.grid = int(grid)
+    h.precision = int(precision)
+    for i in range(3):
+        h.N[i] = P.shape[i] if i < nx else 1
+    Mm = np.asarray(M, float).reshape(nx, nx)
+    for i in range(nx):
+        h.c[i] = float(c[i])
+        for j in range(nx):
+            h.M[3 * i + j] = float(Mm[i, j])
+    h.t = float(t)
+    blob = bytes(h) + P.tobytes()
+    buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
+    _check(lib().pmf_set_state(f, buf, len(blob)))
+
+
+def pmf_batch_step(ctx, filters, T: float, z, stream=None, want_loglik: bool = False):
+    n = len(filters)
+    arr = (C.c_void_p * n)(*[f.value for f in filters])
+    zz = np.ascontiguousarray(np.asarray(z, float).reshape(n, -1))
+    ll = np.full(n, np.nan) if want_loglik else None
+    _check(lib().pmf_batch_step(ctx, arr, n, float(T), zz.ctypes.data_as(C.POINTER(C.c_double)),
+                                ll.ctypes.data_as(C.POINTER(C.c_double)) if want_loglik else None,
+                                _stream(stream)))
+    if want_loglik:
+        _check(lib().pmf_stream_sync(_stream(stream)))
+    return ll
+
+
+def pmf_density_ptr(f) -> int:
+    return lib().pmf_density_ptr(f)

@@ -1,0 +1,68 @@
+// Host-side objects behind the opaque handles of include/pmf.h.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pmf_internal.h"
+
+struct BatchCache;
+
+struct pmf_ctx {
+    int device = 0;
+    bool has_alloc = false;
+    pmf_allocator alloc{};
+    BatchCache* batch = nullptr;
+};
+
+struct pmf_filter {
+    pmf_ctx* ctx = nullptr;
+    pmf_model model{};
+    pmf::KModel km{};
+    double Wnom[9] = {0};
+    int ntot = 0;
+    size_t es = 0;                 // bytes per density value
+    void* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+    int cur = 0;                   // buffer holding the current density
+    void* cbuf = nullptr;          // complex work array (Fourier)
+    double* part = nullptr;        // reduction partials
+    double* bfac = nullptr;        // per-block scale factors
+    double* coef = nullptr;        // per-stage diffusion coefficients
+    double* W = nullptr;           // separable interpolation weights
+    double* tab = nullptr;         // per-axis tables
+    pmf::DevDesc* desc = nullptr;
+    void* D1 = nullptr;            // Chebyshev differentiation matrices (density precision)
+    void* D2 = nullptr;
+    void* rk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // Chebyshev RK4 scratch
+    bool cheb_d32_ready = false;
+    int nb = 0, chunk = 0;         // reduction partition
+    bool have_pa = false;
+    pmf::PredictArgs pa{};
+};
+
+namespace pmf {
+
+constexpr int MAX_RED_BLOCKS = 512;
+
+extern thread_local std::string g_last_error;
+pmf_status fail(pmf_status s, const std::string& msg);
+pmf_status hip_fail(hipError_t e, const char* where);
+void* ctx_alloc(pmf_ctx* ctx, size_t bytes, hipStream_t st);
+void ctx_free(pmf_ctx* ctx, void* p, hipStream_t st);
+
+hipError_t normalise_current(pmf_filter* f, hipStream_t st);
+pmf_status take_status(pmf_filter* f);
+const PredictArgs& predict_args(pmf_filter* f, double T);
+pmf_status cheb_predict(pmf_filter* f, hipStream_t st);
+void cheb_matrices(int N, std::vector<double>& D1, std::vector<double>& D2);
+
+// Chebyshev products on MFMA (cheb_mfma.hip)
+bool cheb_mfma_available(pmf_filter* f);
+pmf_status cheb_predict_mfma(pmf_filter* f, int l, hipStream_t st);
+
+// fused batched step (batch.hip)
+void batch_cache_release(pmf_ctx* ctx);
+void batch_forget_filter(pmf_ctx* ctx, pmf_filter* f);
+
+}  // namespace pmf

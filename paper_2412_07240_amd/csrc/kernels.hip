@@ -1,0 +1,1082 @@
+// Generic kernels of libpmf: any grid kind, nx <= 3, FP32 or FP64 density.
+// Every filter can take this path; the fused batched kernel (fused.hip) and the
+// MFMA Chebyshev products (cheb_mfma.hip) are faster forms of parts of it.
+#include "kernels.h"
+
+namespace pmf {
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+template <typename C> __device__ inline C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __device__ inline C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C> __device__ inline C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// multiply by s*i, s = +-1
+template <typename C> __device__ inline C cmul_si(C a, int s) {
+    C r;
+    r.x = -s * a.y;
+    r.y = s * a.x;
+    return r;
+}
+template <typename C, typename T> __device__ inline C cscale(C a, T f) { C r; r.x = a.x * f; r.y = a.y * f; return r; }
+
+__device__ inline void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ inline void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
+__device__ inline float exp_t(float x) { return expf(x); }
+__device__ inline double exp_t(double x) { return exp(x); }
+
+// R-point DFTs, X_k = sum_r a_r e^{s 2 pi i r k / R}
+template <typename C, typename T> __device__ inline void dft2(C* a) {
+    C t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+}
+template <typename C, typename T> __device__ inline void dft3(C* a, int s) {
+    const T h = (T)0.86602540378443864676;
+    C t = cadd(a[1], a[2]);
+    C d = csub(a[1], a[2]);
+    C m = csub(a[0], cscale(t, (T)0.5));
+    a[0] = cadd(a[0], t);
+    C rot = cscale(cmul_si(d, s), h);
+    a[1] = cadd(m, rot);
+    a[2] = csub(m, rot);
+}
+template <typename C, typename T> __device__ inline void dft4(C* a, int s) {
+    C t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    C t2 = cadd(a[1], a[3]), t3 = cmul_si(csub(a[1], a[3]), s);
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+}
+template <typename C, typename T> __device__ inline void dft8(C* a, int s) {
+    C e[4] = {a[0], a[2], a[4], a[6]};
+    C o[4] = {a[1], a[3], a[5], a[7]};
+    dft4<C, T>(e, s);
+    dft4<C, T>(o, s);
+    const T r = (T)0.70710678118654752440;
+    C w1;
+    w1.x = r;
+    w1.y = s * r;
+    C w3;
+    w3.x = -r;
+    w3.y = s * r;
+    C o1 = cmul(o[1], w1), o2 = cmul_si(o[2], s), o3 = cmul(o[3], w3);
+    a[0] = cadd(e[0], o[0]);
+    a[4] = csub(e[0], o[0]);
+    a[1] = cadd(e[1], o1);
+    a[5] = csub(e[1], o1);
+    a[2] = cadd(e[2], o2);
+    a[6] = csub(e[2], o2);
+    a[3] = cadd(e[3], o3);
+    a[7] = csub(e[3], o3);
+}
+
+// One Stockham autosort pass over `nlines` lines held in LDS (pitch `pitch`).
+template <typename T, int R>
+__device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* out, int n, int Ns,
+                              int nlines, int pitch, int sign) {
+    using C = typename V2<T>::t;
+    const int nb = n / R;
+    for (int w = threadIdx.x; w < nlines * nb; w += blockDim.x) {
+        const int line = w / nb, j = w - line * nb;
+        const C* src = in + line * pitch;
+        C* dst = out + line * pitch;
+        C v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+        const int k = j % Ns;
+        if (k) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                T sn, cs;
+                sincospi_t((T)(2 * sign * k * r) / (T)(Ns * R), &sn, &cs);
+                C w2;
+                w2.x = cs;
+                w2.y = sn;
+                v[r] = cmul(v[r], w2);
+            }
+        }
+        if (R == 2) dft2<C, T>(v);
+        if (R == 3) dft3<C, T>(v, sign);
+        if (R == 4) dft4<C, T>(v, sign);
+        if (R == 8) dft8<C, T>(v, sign);
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+    }
+}
+
+// ------------------------------------------------------------------ FFT along one axis
+// Lines of the C-order array: line L = (o, i) with o < prod(N[<a]), i < s = prod(N[>a]);
+// element k of the line at o*n*s + i + k*s.  A block transforms TL consecutive lines.
+template <typename T>
+__global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, int s,
+                           int nlines, int sign, FftPlan plan, int TL) {
+    using C = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char smem_fft[];
+    const int pitch = n + 1;
+    C* A = reinterpret_cast<C*>(smem_fft);
+    C* B = A + TL * pitch;
+    const int L0 = blockIdx.x * TL;
+    const int ntl = min(TL, nlines - L0);
+    for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
+        int t, k;
+        size_t addr;
+        if (s == 1) {
+            t = e / n;
+            k = e - t * n;
+            addr = (size_t)(L0 + t) * n + k;
+        } else {
+            t = e % ntl;
+            k = e / ntl;
+            const int L = L0 + t;
+            addr = (size_t)(L / s) * n * s + (L % s) + (size_t)k * s;
+        }
+        C v;
+        if (rsrc) {
+            v.x = rsrc[addr];
+            v.y = (T)0;
+        } else {
+            v = X[addr];
+        }
+        A[t * pitch + k] = v;
+    }
+    __syncthreads();
+    int Ns = 1;
+    C* in = A;
+    C* out = B;
+    for (int p = 0; p < plan.np; ++p) {
+        const int R = plan.r[p];
+        if (R == 8) stockham_pass<T, 8>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 4) stockham_pass<T, 4>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 3) stockham_pass<T, 3>(in, out, n, Ns, ntl, pitch, sign);
+        else stockham_pass<T, 2>(in, out, n, Ns, ntl, pitch, sign);
+        __syncthreads();
+        C* tmp = in;
+        in = out;
+        out = tmp;
+        Ns *= R;
+    }
+    for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
+        int t, k;
+        size_t addr;
+        if (s == 1) {
+            t = e / n;
+            k = e - t * n;
+            addr = (size_t)(L0 + t) * n + k;
+        } else {
+            t = e % ntl;
+            k = e / ntl;
+            const int L = L0 + t;
+            addr = (size_t)(L / s) * n * s + (L % s) + (size_t)k * s;
+        }
+        const C v = in[t * pitch + k];
+        if (rdst) rdst[addr] = v.x;
+        else X[addr] = v;
+    }
+}
+
+// ------------------------------------------------------------------ predict planning
+// One thread: substep count, per-stage diffusion in index coordinates, grid move.
+
+__device__ double lambda_bound_dev(const double* Dy, const double* rho, int n) {
+    double s = 0.0;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) s += fabs(Dy[a * 3 + b]) * rho[a] * rho[b];
+    return 0.5 * s;
+}
+
+__global__ void k_plan(PredictArgs a, DevDesc* d, double* coef) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int n = a.nx;
+    double Mi[9];
+    mat_copy(Mi, d->g.Mi);
+    int l = a.lmin;
+    if (a.integ == PMF_INT_RK4 && a.T > 0.0) {
+        double lam = 0.0;
+        const double* Es[3] = {nullptr, a.emh, a.emT};
+        for (int q = 0; q < 3; ++q) {
+            double E[9], t1[9], Dy[9];
+            if (q == 0) {
+                mat_copy(E, a.D);
+            } else {
+                mat_mul(t1, Es[q], a.D, n);
+                mat_mul_bt(E, t1, Es[q], n);
+            }
+            sandwich_inv(Dy, Mi, E, n);
+            const double lb = lambda_bound_dev(Dy, a.rho, n);
+            lam = lb > lam ? lb : lam;
+        }
+        const double need = ceil(a.T * lam / RK4_STABLE_STEP);
+        if (need > (double)l) l = need > (double)a.lmax ? a.lmax + 1 : (int)need;
+    }
+    if (l > a.lmax) {
+        l = a.lmax;
+        d->status |= PMF_E_INVALID;   // substep limit reached: result is not trustworthy
+    }
+    const double h = a.T / l;
+    if (a.integ == PMF_INT_EXACT) {
+        double Wy[9];
+        sandwich_inv(Wy, Mi, a.W, n);
+        pack_sym(coef, Wy);
+    } else {
+        const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
+        const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
+        double Estep[9], Ek[9], t1[9], E[9], Dy[9], nxt[9];
+        expm3(Estep, a.A, -dt, n);
+        mat_eye(Ek, n);
+        for (int k = 0; k < cnt; ++k) {
+            mat_mul(t1, Ek, a.D, n);
+            mat_mul_bt(E, t1, Ek, n);
+            sandwich_inv(Dy, Mi, E, n);
+            pack_sym(coef + 6 * k, Dy);
+            mat_mul(nxt, Ek, Estep, n);
+            mat_copy(Ek, nxt);
+        }
+    }
+    d->l = l;
+    d->h = h;
+    d->etr = a.etr;
+    // grid follows x' = A x over T
+    double c2[3], M2[9];
+    mat_vec(c2, a.Phi, d->g.c, n);
+    mat_mul(M2, a.Phi, d->g.M, n);
+    for (int i = 0; i < n; ++i) d->g.c[i] = c2[i];
+    mat_copy(d->g.M, M2);
+    grid_finish(d->g, n);
+    d->t += a.T;
+}
+
+// ------------------------------------------------------------------ spectral gain
+
+template <typename T>
+__device__ inline T sigma_of(const double* p, const T* k1, const T* k2) {
+    return (T)p[0] * k2[0] + (T)p[1] * k2[1] + (T)p[2] * k2[2] +
+           (T)2 * ((T)p[3] * k1[0] * k1[1] + (T)p[4] * k1[0] * k1[2] + (T)p[5] * k1[1] * k1[2]);
+}
+
+template <typename T>
+__device__ T mode_gain(int integ, int l, T h, const double* coef, const T* k1, const T* k2) {
+    if (integ == PMF_INT_EXACT) return exp_t((T)-0.5 * sigma_of<T>(coef, k1, k2));
+    T g = (T)1;
+    if (integ == PMF_INT_EULER) {
+        for (int n = 0; n < l; ++n) g = g / ((T)1 + (T)0.5 * h * sigma_of<T>(coef + 6 * n, k1, k2));
+        return g;
+    }
+    for (int n = 0; n < l; ++n) {
+        const T la = (T)-0.5 * sigma_of<T>(coef + 12 * n, k1, k2);
+        const T lb = (T)-0.5 * sigma_of<T>(coef + 12 * n + 6, k1, k2);
+        const T lc = (T)-0.5 * sigma_of<T>(coef + 12 * n + 12, k1, k2);
+        const T hh = (T)0.5 * h;
+        const T y2 = (T)1 + hh * la;
+        const T y3 = (T)1 + hh * lb * y2;
+        const T y4 = (T)1 + h * lb * y3;
+        g *= (T)1 + h / (T)6 * (la + (T)2 * lb * y2 + (T)2 * lb * y3 + lc * y4);
+    }
+    return g;
+}
+
+template <typename T>
+__device__ inline void mode_kappa(int s, int n, T* k1, T* k2) {
+    const int k = (s < n / 2) ? s : s - n;
+    const T kap = (T)(2.0 * M_PI) * (T)k / (T)n;
+    *k2 = kap * kap;
+    *k1 = (2 * s == n) ? (T)0 : kap;
+}
+
+template <typename T>
+__global__ void k_gain(KModel m, const DevDesc* d, const double* coef, typename V2<T>::t* X) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m.ntot) return;
+    T k1[3] = {0, 0, 0}, k2[3] = {0, 0, 0};
+    int rem = e;
+    for (int a = m.nx - 1; a >= 0; --a) {
+        const int s = rem % m.N[a];
+        rem /= m.N[a];
+        mode_kappa<T>(s, m.N[a], &k1[a], &k2[a]);
+    }
+    const T g = mode_gain<T>(m.integ, d->l, (T)d->h, coef, k1, k2) * (T)(d->etr / (double)m.ntot);
+    typename V2<T>::t v = X[e];
+    v.x *= g;
+    v.y *= g;
+    X[e] = v;
+}
+
+// ------------------------------------------------------------------ grid coordinates
+
+// axis tables: per axis a at tab + a*TAB_STRIDE: u[N] (computational coordinate),
+// qw[N] (quadrature weight in u), v[N+2] (full CGL nodes), beta[N+2] (barycentric)
+__device__ inline void node_coords(const KModel& m, const double* tab, int j, double* u, int* idx) {
+    int rem = j;
+    for (int a = m.nx - 1; a >= 0; --a) {
+        const int s = rem % m.N[a];
+        rem /= m.N[a];
+        idx[a] = s;
+        u[a] = tab[a * TAB_STRIDE + s];
+    }
+}
+
+__device__ inline double node_qw(const KModel& m, const double* tab, const int* idx) {
+    if (m.grid == PMF_GRID_FOURIER) return 1.0;
+    double q = 1.0;
+    for (int a = 0; a < m.nx; ++a) q *= tab[a * TAB_STRIDE + TAB_QW + idx[a]];
+    return q;
+}
+
+__device__ inline bool node_on_boundary(const KModel& m, const int* idx) {
+    for (int a = 0; a < m.nx; ++a)
+        if (idx[a] == 0 || idx[a] == m.N[a] - 1) return true;
+    return false;
+}
+
+__device__ inline void to_phys(const Grid& g, int nx, const double* u, double* x) {
+    for (int i = 0; i < nx; ++i) {
+        double s = g.c[i];
+        for (int k = 0; k < nx; ++k) s += g.M[i * 3 + k] * u[k];
+        x[i] = s;
+    }
+}
+
+// log p_v(z - h(x)) for a Gaussian-mixture v
+__device__ double loglik_at(const KModel& m, const double* x, const double* z) {
+    double hx[3] = {0, 0, 0};
+    if (m.meas == PMF_H_LINEAR) {
+        for (int i = 0; i < m.nz; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < m.nx; ++k) s += m.H[i * 3 + k] * x[k];
+            hx[i] = s;
+        }
+    } else if (m.meas == PMF_H_CUBIC1) {
+        hx[0] = m.hp[0] * x[0] + m.hp[1] * x[0] * x[0] * x[0];
+    } else {
+        double s = 0.0;
+        for (int k = 0; k < m.nx; ++k) s += x[k] * x[k];
+        hx[0] = sqrt(s);
+    }
+    double best = -INFINITY, terms[MAXMIX];
+    for (int g = 0; g < m.ncomp; ++g) {
+        double r[3];
+        for (int i = 0; i < m.nz; ++i) r[i] = z[i] - hx[i] - m.nmean[g][i];
+        double q = 0.0;
+        for (int i = 0; i < m.nz; ++i)
+            for (int k = 0; k < m.nz; ++k) q += r[i] * m.nRi[g][i * 3 + k] * r[k];
+        terms[g] = m.lw[g] - 0.5 * q;
+        best = terms[g] > best ? terms[g] : best;
+    }
+    if (m.ncomp == 1) return terms[0];
+    double acc = 0.0;
+    for (int g = 0; g < m.ncomp; ++g) acc += exp(terms[g] - best);
+    return best + log(acc);
+}
+
+// fixed-order block reduction of NV doubles per thread (RED_THREADS threads)
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double* sh) {
+    for (int q = 0; q < NV; ++q) sh[q * RED_THREADS + threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < NV; ++q)
+                sh[q * RED_THREADS + threadIdx.x] += sh[q * RED_THREADS + threadIdx.x + w];
+        __syncthreads();
+    }
+    for (int q = 0; q < NV; ++q) v[q] = sh[q * RED_THREADS];
+    __syncthreads();
+}
+
+__device__ double block_max(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    v = sh[0];
+    __syncthreads();
+    return v;
+}
+
+// ------------------------------------------------------------------ likelihood + sums
+// mode 0: sums of the density only; mode 1: P_out = P * exp(loglik - s_b) and its sums.
+// Partial b: {s_b, S0, S1[3], S2[6] (00,11,22,01,02,12), Sboundary}, block-relative.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T* Pout,
+            double* part, int chunk, int mode) {
+    __shared__ double sh[11 * RED_THREADS];
+    const int b = blockIdx.x;
+    const int lo = b * chunk;
+    const int hi = min(m.ntot, lo + chunk);
+    const Grid& g = d->g;
+    double sb = 0.0;
+    if (mode == 1) {
+        double mx = -INFINITY;
+        for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
+            double u[3] = {0, 0, 0}, x[3];
+            int idx[3];
+            node_coords(m, tab, j, u, idx);
+            to_phys(g, m.nx, u, x);
+            mx = fmax(mx, loglik_at(m, x, z.v));
+        }
+        sb = block_max(mx, sh);
+    }
+    double acc[11];
+    for (int q = 0; q < 11; ++q) acc[q] = 0.0;
+    for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
+        double u[3] = {0, 0, 0};
+        int idx[3] = {0, 0, 0};
+        node_coords(m, tab, j, u, idx);
+        T v = P[j];
+        if (mode == 1) {
+            double x[3];
+            to_phys(g, m.nx, u, x);
+            const double L = loglik_at(m, x, z.v);
+            v = v * exp_t((T)(L - sb));
+            Pout[j] = v;
+        }
+        const double w = node_qw(m, tab, idx) * (double)v;
+        acc[0] += w;
+        acc[1] += w * u[0];
+        acc[2] += w * u[1];
+        acc[3] += w * u[2];
+        acc[4] += w * u[0] * u[0];
+        acc[5] += w * u[1] * u[1];
+        acc[6] += w * u[2] * u[2];
+        acc[7] += w * u[0] * u[1];
+        acc[8] += w * u[0] * u[2];
+        acc[9] += w * u[1] * u[2];
+        if (node_on_boundary(m, idx)) acc[10] += w;
+    }
+    block_sum<11>(acc, sh);
+    if (threadIdx.x == 0) {
+        double* p = part + (size_t)b * NPART;
+        p[0] = sb;
+        for (int q = 0; q < 11; ++q) p[1 + q] = acc[q];
+    }
+}
+
+// Combine partials in block order: returns S0..Sb relative to the global shift.
+__device__ void combine_partials(const double* part, int nb, double* s_out, double* S) {
+    double s = -INFINITY;
+    for (int b = 0; b < nb; ++b) s = fmax(s, part[b * NPART]);
+    for (int q = 0; q < 11; ++q) S[q] = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double f = (s == -INFINITY) ? 0.0 : exp(part[b * NPART] - s);
+        for (int q = 0; q < 11; ++q) S[q] += f * part[b * NPART + 1 + q];
+    }
+    *s_out = s;
+}
+
+// mean and covariance from sums in computational coordinates u (x = c + M u)
+__device__ void moments_from_sums(const Grid& g, int nx, const double* S, double* mean, double* cov) {
+    const double S0 = S[0];
+    double ub[3] = {S[1] / S0, S[2] / S0, S[3] / S0};
+    double Cu[9];
+    mat_zero(Cu);
+    const int i2[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < nx; ++b) Cu[a * 3 + b] = S[i2[a][b]] / S0 - ub[a] * ub[b];
+    double mu[3];
+    mat_vec(mu, g.M, ub, nx);
+    for (int a = 0; a < nx; ++a) mean[a] = g.c[a] + mu[a];
+    double t1[9], C[9];
+    mat_mul(t1, g.M, Cu, nx);
+    mat_mul_bt(C, t1, g.M, nx);
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < nx; ++b) cov[a * 3 + b] = 0.5 * (C[a * 3 + b] + C[b * 3 + a]);
+}
+
+__device__ bool design_grid_dev(const KModel& m, const double* mean, const double* cov, Grid& gn) {
+    mat_zero(gn.M);
+    for (int a = 0; a < m.nx; ++a) {
+        const double v = cov[a * 3 + a] + m.Wnom[a * 3 + a];
+        if (!(v > 0.0) || !isfinite(v)) return false;
+        const double h = m.span * sqrt(v);
+        gn.M[a * 3 + a] = (m.grid == PMF_GRID_FOURIER) ? 2.0 * h / m.N[a] : h;
+        gn.c[a] = mean[a];
+    }
+    grid_finish(gn, m.nx);
+    return true;
+}
+
+// After k_like_pass(mode 1): normaliser, log-likelihood, moments, block factors,
+// new grid.  On failure: ok = 0 and the DEGENERATE bit.
+__global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s, S[11];
+    combine_partials(part, nb, &s, S);
+    const double mass = d->g.vol * S[0];
+    d->ok = 1;
+    if (!isfinite(s) || !isfinite(mass) || !(mass > 0.0)) {
+        d->ok = 0;
+    } else {
+        d->s = s;
+        d->mass = mass;
+        d->loglik = s + log(mass);
+        moments_from_sums(d->g, m.nx, S, d->mean, d->cov);
+        d->bfrac = S[10] / S[0];
+        if (d->bfrac > BOUNDARY_TOL) d->status |= ST_BOUNDARY;
+        for (int b = 0; b < nb; ++b) bfac[b] = exp(part[b * NPART] - s) / mass;
+        if (!design_grid_dev(m, d->mean, d->cov, d->gn)) d->ok = 0;
+        // separable spectral interpolation when the old grid is axis aligned
+        // (the new one always is); otherwise cubic Lagrange
+        bool aligned = true;
+        for (int a = 0; a < m.nx; ++a)
+            for (int b = 0; b < m.nx; ++b)
+                if (a != b && d->g.M[a * 3 + b] != 0.0) aligned = false;
+        d->sep = (m.interp == PMF_INTERP_AUTO && aligned) ? 1 : 0;
+    }
+    if (!d->ok) {
+        d->status |= ST_DEGENERATE;
+        d->loglik = NAN;
+    }
+}
+
+// After k_like_pass(mode 0): mass, moments and 1/mass (in bfac[0..nb)).
+__global__ void k_sums_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s, S[11];
+    combine_partials(part, nb, &s, S);
+    const double mass = d->g.vol * S[0];
+    d->mass = mass;
+    moments_from_sums(d->g, m.nx, S, d->mean, d->cov);
+    for (int b = 0; b < nb; ++b) bfac[b] = 1.0 / mass;
+}
+
+template <typename T>
+__global__ void k_scale_blocks(T* P, int ntot, int chunk, const double* bfac) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntot) return;
+    P[j] = (T)((double)P[j] * bfac[j / chunk]);
+}
+
+// ------------------------------------------------------------------ re-interpolation
+
+// Separable spectral weights, one matrix per axis at W + a*256*256 (row j' = new node):
+// Fourier: periodic interpolation kernel sin(pi d) / (N tan(pi d / N)) of the
+// trigonometric interpolant, zero when the new node is outside [0, N-1] in old
+// index units; Chebyshev: barycentric form of the polynomial through the N+2
+// Chebyshev-Gauss-Lobatto values (zero at +-1), zero outside [-1, 1].
+__global__ void k_interp_weights(KModel m, const DevDesc* d, const double* tab, double* W) {
+    const int a = blockIdx.y;
+    const int n = m.N[a];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d->sep || a >= m.nx || e >= n * n) return;
+    const int jp = e / n, j = e - jp * n;
+    const Grid& go = d->g;
+    const Grid& gn = d->gn;
+    const double xn = gn.c[a] + gn.M[a * 3 + a] * tab[a * TAB_STRIDE + jp];
+    double w = 0.0;
+    if (m.grid == PMF_GRID_FOURIER) {
+        const double nu = (xn - go.c[a]) * go.Mi[a * 3 + a] + (double)(n / 2);
+        if (nu >= 0.0 && nu <= (double)(n - 1)) {
+            const double dd = nu - (double)j;
+            if (dd == 0.0) {
+                w = 1.0;
+            } else {
+                w = sinpi(dd) / ((double)n * tan(M_PI * dd / (double)n));
+            }
+        }
+    } else {
+        const double u = (xn - go.c[a]) * go.Mi[a * 3 + a];
+        if (u >= -1.0 && u <= 1.0) {
+            const double* v = tab + a * TAB_STRIDE + TAB_V;
+            const double* beta = tab + a * TAB_STRIDE + TAB_BETA;
+            int hit = -1;
+            double den = 0.0;
+            for (int k = 0; k < n + 2; ++k) {
+                const double dk = u - v[k];
+                if (dk == 0.0) {
+                    hit = k;
+                    break;
+                }
+                den += beta[k] / dk;
+            }
+            if (hit >= 0) {
+                w = (hit == j + 1) ? 1.0 : 0.0;
+            } else {
+                w = (beta[j + 1] / (u - v[j + 1])) / den;
+            }
+        }
+    }
+    W[(size_t)a * 256 * 256 + e] = w;
+}
+
+// out = (matrix W_a applied along axis a of in).  With want_sums the block also
+// produces the FP64 sums of the result (new grid, block-ordered partials).
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+k_interp_axis(KModel m, const DevDesc* d, const double* tab, const double* Wall, int a,
+              const T* in, T* out, double* part, int chunk, int want_sums) {
+    __shared__ double sh[11 * RED_THREADS];
+    if (!d->sep) return;
+    const int n = m.N[a];
+    int s = 1;
+    for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
+    const double* W = Wall + (size_t)a * 256 * 256;
+    const int lo = blockIdx.x * chunk;
+    const int hi = min(m.ntot, lo + chunk);
+    double acc[11];
+    for (int q = 0; q < 11; ++q) acc[q] = 0.0;
+    for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
+        const int i = j % s;
+        const int jp = (j / s) % n;
+        const int o = j / (s * n);
+        const T* src = in + (size_t)o * n * s + i;
+        double v = 0.0;
+        for (int k = 0; k < n; ++k) v += W[jp * n + k] * (double)src[(size_t)k * s];
+        out[j] = (T)v;
+        if (want_sums) {
+            double u[3] = {0, 0, 0};
+            int idx[3] = {0, 0, 0};
+            node_coords(m, tab, j, u, idx);
+            const double w = node_qw(m, tab, idx) * (double)(T)v;
+            acc[0] += w;
+            acc[1] += w * u[0];
+            acc[2] += w * u[1];
+            acc[3] += w * u[2];
+            acc[4] += w * u[0] * u[0];
+            acc[5] += w * u[1] * u[1];
+            acc[6] += w * u[2] * u[2];
+            acc[7] += w * u[0] * u[1];
+            acc[8] += w * u[0] * u[2];
+            acc[9] += w * u[1] * u[2];
+        }
+    }
+    if (want_sums) {
+        block_sum<11>(acc, sh);
+        if (threadIdx.x == 0) {
+            double* p = part + (size_t)blockIdx.x * NPART;
+            p[0] = 0.0;
+            for (int q = 0; q < 11; ++q) p[1 + q] = acc[q];
+        }
+    }
+}
+
+// cubic Lagrange weights through abscissae x0..x3 at t
+__device__ inline void lagrange4(double t, const double* x, double* w) {
+    for (int k = 0; k < 4; ++k) {
+        double p = 1.0;
+        for (int i = 0; i < 4; ++i)
+            if (i != k) p *= (t - x[i]) / (x[k] - x[i]);
+        w[k] = p;
+    }
+}
+
+// Tensor cubic Lagrange interpolation in the old grid's computational coordinates.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T* out,
+                  double* part, int chunk) {
+    __shared__ double sh[11 * RED_THREADS];
+    if (d->sep) return;
+    const Grid& go = d->g;
+    const Grid& gn = d->gn;
+    const int lo = blockIdx.x * chunk;
+    const int hi = min(m.ntot, lo + chunk);
+    double acc[11];
+    for (int q = 0; q < 11; ++q) acc[q] = 0.0;
+    for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
+        double u[3] = {0, 0, 0}, x[3], r[3], nu[3] = {0, 0, 0};
+        int idx[3] = {0, 0, 0};
+        node_coords(m, tab, j, u, idx);
+        to_phys(gn, m.nx, u, x);
+        for (int a = 0; a < m.nx; ++a) r[a] = x[a] - go.c[a];
+        mat_vec(nu, go.Mi, r, m.nx);
+        bool inside = true;
+        int base[3] = {0, 0, 0};
+        int tapidx[3][4];
+        double tw[3][4];
+        for (int a = 0; a < m.nx; ++a) {
+            const int n = m.N[a];
+            if (m.grid == PMF_GRID_FOURIER) {
+                const double q = nu[a] + (double)(n / 2);
+                if (!(q >= 0.0 && q <= (double)(n - 1))) {
+                    inside = false;
+                    break;
+                }
+                const int i0 = (int)floor(q);
+                const double xs[4] = {(double)(i0 - 1), (double)i0, (double)(i0 + 1), (double)(i0 + 2)};
+                lagrange4(q, xs, tw[a]);
+                for (int k = 0; k < 4; ++k) {
+                    const int ii = i0 - 1 + k;
+                    tapidx[a][k] = ii;
+                    if (ii < 0 || ii > n - 1) tw[a][k] = 0.0;
+                }
+            } else {
+                const double q = nu[a];
+                if (!(q >= -1.0 && q <= 1.0)) {
+                    inside = false;
+                    break;
+                }
+                const int nn = n + 1;
+                int k0 = (int)floor((double)nn * acos(-q) / M_PI);
+                k0 = k0 < 0 ? 0 : (k0 > nn - 1 ? nn - 1 : k0);
+                int ks = k0 - 1;
+                ks = ks < 0 ? 0 : (ks > nn - 3 ? nn - 3 : ks);
+                const double* v = tab + a * TAB_STRIDE + TAB_V;
+                lagrange4(q, v + ks, tw[a]);
+                for (int k = 0; k < 4; ++k) {
+                    const int kk = ks + k;
+                    tapidx[a][k] = kk - 1;
+                    if (kk < 1 || kk > n) tw[a][k] = 0.0;
+                }
+            }
+            (void)base;
+        }
+        double val = 0.0;
+        if (inside) {
+            if (m.nx == 1) {
+                for (int k = 0; k < 4; ++k)
+                    if (tw[0][k] != 0.0) val += tw[0][k] * (double)in[tapidx[0][k]];
+            } else if (m.nx == 2) {
+                for (int k0 = 0; k0 < 4; ++k0) {
+                    if (tw[0][k0] == 0.0) continue;
+                    double rs = 0.0;
+                    for (int k1 = 0; k1 < 4; ++k1)
+                        if (tw[1][k1] != 0.0)
+                            rs += tw[1][k1] * (double)in[(size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]];
+                    val += tw[0][k0] * rs;
+                }
+            } else {
+                for (int k0 = 0; k0 < 4; ++k0) {
+                    if (tw[0][k0] == 0.0) continue;
+                    double ps = 0.0;
+                    for (int k1 = 0; k1 < 4; ++k1) {
+                        if (tw[1][k1] == 0.0) continue;
+                        double rs = 0.0;
+                        for (int k2 = 0; k2 < 4; ++k2)
+                            if (tw[2][k2] != 0.0)
+                                rs += tw[2][k2] *
+                                      (double)in[((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2] +
+                                                 tapidx[2][k2]];
+                        ps += tw[1][k1] * rs;
+                    }
+                    val += tw[0][k0] * ps;
+                }
+            }
+        }
+        const T vt = (T)val;
+        out[j] = vt;
+        const double w = node_qw(m, tab, idx) * (double)vt;
+        acc[0] += w;
+        acc[1] += w * u[0];
+        acc[2] += w * u[1];
+        acc[3] += w * u[2];
+        acc[4] += w * u[0] * u[0];
+        acc[5] += w * u[1] * u[1];
+        acc[6] += w * u[2] * u[2];
+        acc[7] += w * u[0] * u[1];
+        acc[8] += w * u[0] * u[2];
+        acc[9] += w * u[1] * u[2];
+    }
+    block_sum<11>(acc, sh);
+    if (threadIdx.x == 0) {
+        double* p = part + (size_t)blockIdx.x * NPART;
+        p[0] = 0.0;
+        for (int q = 0; q < 11; ++q) p[1 + q] = acc[q];
+    }
+}
+
+// New grid's mass -> 1/mass, commit the grid.  A zero / non-finite mass rejects
+// the update (state unchanged).
+__global__ void k_interp_finalize(KModel m, DevDesc* d, const double* part, int nb) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!d->ok) return;
+    double s, S[11];
+    combine_partials(part, nb, &s, S);
+    const double mass2 = d->gn.vol * S[0];
+    if (!isfinite(mass2) || !(mass2 > 0.0)) {
+        d->ok = 0;
+        d->status |= ST_DEGENERATE;
+        d->loglik = NAN;
+        return;
+    }
+    d->mass2 = mass2;
+    d->g = d->gn;
+}
+
+// final density: out *= 1/mass2 when accepted, else out = old (state unchanged)
+template <typename T>
+__global__ void k_final_scale(T* out, const T* old, int ntot, const DevDesc* d) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntot) return;
+    if (d->ok) out[j] = (T)((double)out[j] / d->mass2);
+    else out[j] = old[j];
+}
+
+// ------------------------------------------------------------------ prior
+
+__global__ void k_prior(KModel m, KPrior pr, const DevDesc* d, const double* tab, void* Pv, int prec) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m.ntot) return;
+    double u[3] = {0, 0, 0}, x[3];
+    int idx[3];
+    node_coords(m, tab, j, u, idx);
+    to_phys(d->g, m.nx, u, x);
+    double best = -INFINITY, terms[MAXMIX];
+    for (int g = 0; g < pr.ncomp; ++g) {
+        double r[3];
+        for (int i = 0; i < m.nx; ++i) r[i] = x[i] - pr.mean[g][i];
+        double q = 0.0;
+        for (int i = 0; i < m.nx; ++i)
+            for (int k = 0; k < m.nx; ++k) q += r[i] * pr.Ci[g][i * 3 + k] * r[k];
+        terms[g] = pr.lw[g] - 0.5 * q;
+        best = terms[g] > best ? terms[g] : best;
+    }
+    double acc = 0.0;
+    for (int g = 0; g < pr.ncomp; ++g) acc += exp(terms[g] - best);
+    const double p = exp(best) * acc;
+    if (prec == PMF_FP64) static_cast<double*>(Pv)[j] = p;
+    else static_cast<float*>(Pv)[j] = (float)p;
+}
+
+// ------------------------------------------------------------------ Chebyshev RK4 pieces
+
+// out = beta*out + alpha*coef[cidx] * (Mat applied along axis a of in); Mat is n x n.
+template <typename T>
+__global__ void k_axis_mm(const T* Mat, const T* in, T* out, int n, int s, int ntot,
+                          const double* coef, int cidx, double alpha, int accumulate) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntot) return;
+    const int i = j % s;
+    const int r = (j / s) % n;
+    const int o = j / (s * n);
+    const T* src = in + (size_t)o * n * s + i;
+    T v = (T)0;
+    for (int k = 0; k < n; ++k) v += Mat[r * n + k] * src[(size_t)k * s];
+    const T f = (T)(alpha * (cidx >= 0 ? coef[cidx] : 1.0));
+    out[j] = accumulate ? out[j] + f * v : f * v;
+}
+
+// RK4 stage bookkeeping.  stage 1..4 with kf = f(y):
+//  1: acc = kf,     y = q + h/2 kf
+//  2: acc += 2 kf,  y = q + h/2 kf
+//  3: acc += 2 kf,  y = q + h kf
+//  4: q += h/6 (acc + kf)
+template <typename T>
+__global__ void k_rk4_stage(T* q, T* y, const T* kf, T* acc, int ntot, const DevDesc* d, int stage) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntot) return;
+    const T h = (T)d->h;
+    const T k = kf[j];
+    if (stage == 1) {
+        acc[j] = k;
+        y[j] = q[j] + (T)0.5 * h * k;
+    } else if (stage == 2) {
+        acc[j] += (T)2 * k;
+        y[j] = q[j] + (T)0.5 * h * k;
+    } else if (stage == 3) {
+        acc[j] += (T)2 * k;
+        y[j] = q[j] + h * k;
+    } else {
+        q[j] += h / (T)6 * (acc[j] + k);
+    }
+}
+
+template <typename T>
+__global__ void k_scale_by(T* q, int ntot, const DevDesc* d) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntot) return;
+    q[j] = (T)((double)q[j] * d->etr);
+}
+
+template <typename T>
+__global__ void k_copy(T* dst, const T* src, int ntot) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < ntot) dst[j] = src[j];
+}
+
+// ------------------------------------------------------------------ host launchers
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+template <typename T>
+hipError_t launch_fft_axis(const KModel& m, int a, const T* rsrc, void* X, T* rdst, int sign,
+                           hipStream_t st) {
+    const int n = m.N[a];
+    int s = 1;
+    for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
+    const int nlines = m.ntot / n;
+    // lines per block: about 2048 points, and the two LDS buffers within 64 KiB
+    const int cap = (int)(65536 / (2 * (size_t)(n + 1) * sizeof(typename V2<T>::t)));
+    int TL = 2048 / n;
+    if (TL > cap) TL = cap;
+    if (TL < 1) TL = 1;
+    if (TL > nlines) TL = nlines;
+    const size_t lds = 2 * (size_t)TL * (n + 1) * sizeof(typename V2<T>::t);
+    const FftPlan plan = make_plan(n);
+    hipLaunchKernelGGL(k_fft_axis<T>, dim3(cdiv(nlines, TL)), dim3(256), lds, st, rsrc,
+                       static_cast<typename V2<T>::t*>(X), rdst, n, s, nlines, sign, plan, TL);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_predict_fourier(const KModel& m, DevDesc* d, const double* coef, void* cbuf, T* P,
+                                  hipStream_t st) {
+    hipError_t e;
+    // forward: last (contiguous) axis first, reading the real density
+    for (int a = m.nx - 1; a >= 0; --a) {
+        e = launch_fft_axis<T>(m, a, a == m.nx - 1 ? P : nullptr, cbuf, nullptr, -1, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_gain<T>, dim3(cdiv(m.ntot, 256)), dim3(256), 0, st, m, d, coef,
+                       static_cast<typename V2<T>::t*>(cbuf));
+    for (int a = 0; a < m.nx; ++a) {
+        e = launch_fft_axis<T>(m, a, nullptr, cbuf, a == m.nx - 1 ? P : nullptr, +1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const PredictArgs& a, DevDesc* d, double* coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, a, d, coef);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_like(const KModel& m, const DevDesc* d, const double* tab, const double* z,
+                       const T* P, T* Pout, double* part, int nb, int chunk, int mode, hipStream_t st) {
+    ZArg za;
+    for (int i = 0; i < 3; ++i) za.v[i] = (z && i < m.nz) ? z[i] : 0.0;
+    hipLaunchKernelGGL(k_like_pass<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, za, P, Pout, part,
+                       chunk, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_finalize(const KModel& m, DevDesc* d, const double* part, int nb, double* bfac,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(k_update_finalize, dim3(1), dim3(1), 0, st, m, d, part, nb, bfac);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums_finalize(const KModel& m, DevDesc* d, const double* part, int nb, double* bfac,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_sums_finalize, dim3(1), dim3(1), 0, st, m, d, part, nb, bfac);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale_blocks(T* P, int ntot, int chunk, const double* bfac, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_blocks<T>, dim3(cdiv(ntot, 256)), dim3(256), 0, st, P, ntot, chunk, bfac);
+    return hipGetLastError();
+}
+
+// Re-interpolate `post` (normalised posterior on the old grid) onto the proposed
+// grid, unnormalised, into `res`.  The device chooses the separable spectral or
+// the Lagrange path (the other kernels return at once); `tmp` is scratch and
+// `post` may be overwritten.
+template <typename T>
+hipError_t launch_interp(const KModel& m, DevDesc* d, const double* tab, double* W, T* post, T* tmp, T* res,
+                         double* part, int nb, int chunk, hipStream_t st) {
+    int maxn = 0;
+    for (int a = 0; a < m.nx; ++a) maxn = m.N[a] > maxn ? m.N[a] : maxn;
+    hipLaunchKernelGGL(k_interp_weights, dim3(cdiv(maxn * maxn, 256), m.nx), dim3(256), 0, st, m, d, tab, W);
+    T* seq[4] = {post, res, nullptr, nullptr};
+    if (m.nx == 2) {
+        seq[1] = tmp;
+        seq[2] = res;
+    } else if (m.nx == 3) {
+        seq[1] = tmp;
+        seq[2] = post;
+        seq[3] = res;
+    }
+    for (int a = 0; a < m.nx; ++a)
+        hipLaunchKernelGGL(k_interp_axis<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, W, a, seq[a],
+                           seq[a + 1], part, chunk, a == m.nx - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_interp_lagrange<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, post, res, part,
+                       chunk);
+    hipLaunchKernelGGL(k_interp_finalize, dim3(1), dim3(1), 0, st, m, d, part, nb);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_final_scale(T* out, const T* old, int ntot, const DevDesc* d, hipStream_t st) {
+    hipLaunchKernelGGL(k_final_scale<T>, dim3(cdiv(ntot, 256)), dim3(256), 0, st, out, old, ntot, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_prior(const KModel& m, const KPrior& pr, const DevDesc* d, const double* tab, void* P,
+                        int prec, hipStream_t st) {
+    hipLaunchKernelGGL(k_prior, dim3(cdiv(m.ntot, 256)), dim3(256), 0, st, m, pr, d, tab, P, prec);
+    return hipGetLastError();
+}
+
+// f(y) = 1/2 sum_a Dy_aa D2_a y + sum_{a<b} Dy_ab D1_a (D1_b y)  (stage coefficient set k)
+template <typename T>
+hipError_t launch_cheb_rhs(const KModel& m, const T* D1, const T* D2, const double* coef, int k, const T* y,
+                           T* kf, T* t1, T* t2, hipStream_t st) {
+    const int nx = m.nx;
+    const int ntot = m.ntot;
+    const int g = cdiv(ntot, 256);
+    const int sidx[3] = {0, 1, 2};
+    const int cross[3][3] = {{-1, 3, 4}, {3, -1, 5}, {4, 5, -1}};
+    int strides[3];
+    for (int a = 0; a < nx; ++a) {
+        int s = 1;
+        for (int b = a + 1; b < nx; ++b) s *= m.N[b];
+        strides[a] = s;
+    }
+    for (int a = 0; a < nx; ++a) {
+        hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, D2 + (size_t)a * 256 * 256, y, kf, m.N[a],
+                           strides[a], ntot, coef, 6 * k + sidx[a], 0.5, a > 0 ? 1 : 0);
+    }
+    T* tb[3] = {nullptr, t1, t2};
+    for (int b = 1; b < nx; ++b) {
+        hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, D1 + (size_t)b * 256 * 256, y, tb[b], m.N[b],
+                           strides[b], ntot, coef, -1, 1.0, 0);
+    }
+    for (int a = 0; a < nx; ++a)
+        for (int b = a + 1; b < nx; ++b)
+            hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, D1 + (size_t)a * 256 * 256, tb[b], kf,
+                               m.N[a], strides[a], ntot, coef, 6 * k + cross[a][b], 1.0, 1);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rk4_stage(T* q, T* y, const T* kf, T* acc, int ntot, const DevDesc* d, int stage,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_rk4_stage<T>, dim3(cdiv(ntot, 256)), dim3(256), 0, st, q, y, kf, acc, ntot, d, stage);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale_etr(T* q, int ntot, const DevDesc* d, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_by<T>, dim3(cdiv(ntot, 256)), dim3(256), 0, st, q, ntot, d);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, int ntot, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy<T>, dim3(cdiv(ntot, 256)), dim3(256), 0, st, dst, src, ntot);
+    return hipGetLastError();
+}
+
+#define PMF_INSTANTIATE(T)                                                                                   \
+    template hipError_t launch_predict_fourier<T>(const KModel&, DevDesc*, const double*, void*, T*,         \
+                                                  hipStream_t);                                              \
+    template hipError_t launch_like<T>(const KModel&, const DevDesc*, const double*, const double*, const T*, \
+                                       T*, double*, int, int, int, hipStream_t);                             \
+    template hipError_t launch_scale_blocks<T>(T*, int, int, const double*, hipStream_t);                    \
+    template hipError_t launch_interp<T>(const KModel&, DevDesc*, const double*, double*, T*, T*, T*,        \
+                                         double*, int, int, hipStream_t);                                    \
+    template hipError_t launch_final_scale<T>(T*, const T*, int, const DevDesc*, hipStream_t);               \
+    template hipError_t launch_cheb_rhs<T>(const KModel&, const T*, const T*, const double*, int, const T*,  \
+                                           T*, T*, T*, hipStream_t);                                         \
+    template hipError_t launch_rk4_stage<T>(T*, T*, const T*, T*, int, const DevDesc*, int, hipStream_t);   \
+    template hipError_t launch_scale_etr<T>(T*, int, const DevDesc*, hipStream_t);                           \
+    template hipError_t launch_copy<T>(T*, const T*, int, hipStream_t);
+
+PMF_INSTANTIATE(float)
+PMF_INSTANTIATE(double)
+
+}  // namespace pmf

@@ -1,0 +1,62 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI and
+the oracle side by side on the same seeded inputs."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+from oracle import pmf as opmf
+
+
+def note(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def l1(model, M, a, b) -> float:
+    q = oracle.quadrature_weights(model, np.asarray(M))
+    return float(np.sum(q * np.abs(np.asarray(a, float) - np.asarray(b, float))))
+
+
+class Pair:
+    """One GPU filter and its oracle twin."""
+
+    def __init__(self, B, ctx, model, prior):
+        self.B = B
+        self.model = model
+        self.f = B.pmf_create(ctx, model, prior)
+        self.st = oracle.create(model, prior)
+
+    def close(self):
+        self.B.pmf_destroy(self.f)
+
+    def gpu_state(self):
+        _, c, M, t, P = self.B.pmf_get_state(self.f)
+        return c, M, t, P
+
+    def predict(self, T):
+        self.B.pmf_predict(self.f, T)
+        self.st, l = oracle.predict(self.model, self.st, T)
+        return l
+
+    def update(self, z):
+        ll = self.B.pmf_update(self.f, z, want_loglik=True)
+        self.st, ll_o, status, m, C = oracle.update(self.model, self.st, z)
+        return ll, ll_o, status
+
+    def inject_oracle_state(self):
+        """Lockstep: give the GPU the oracle's grid and density."""
+        self.B.pmf_set_state(self.f, self.st.c, self.st.M, self.st.t, self.st.P, self.model.grid,
+                             self.model.precision)
+
+    def compare(self, tol_l1, grid_rtol=1e-11, what=""):
+        c, M, t, P = self.gpu_state()
+        scale = np.max(np.abs(self.st.M))
+        np.testing.assert_allclose(M, self.st.M, rtol=0, atol=grid_rtol * scale, err_msg=f"grid M {what}")
+        np.testing.assert_allclose(c, self.st.c, rtol=0, atol=grid_rtol * (1 + np.abs(self.st.c).max()) + grid_rtol * scale * 10,
+                                   err_msg=f"grid c {what}")
+        err = l1(self.model, self.st.M, P, self.st.P)
+        assert err <= tol_l1, f"L1 {err:.3e} > {tol_l1:.1e} {what}"
+        return err
