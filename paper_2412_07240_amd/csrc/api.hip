@@ -241,6 +241,9 @@ static void build_kmodel(const pmf_model& m, KModel& k, double* Wnom) {
         k.lw[g] = std::log(m.noise_w[g] / wsum) - 0.5 * (m.nz * std::log(2.0 * M_PI) + std::log(det));
         for (int i = 0; i < m.nz; ++i) k.nmean[g][i] = m.noise_mean[3 * g + i];
     }
+    int maxn = 1;
+    for (int a = 0; a < m.nx; ++a) maxn = m.N[a] > maxn ? m.N[a] : maxn;
+    k.wstride = maxn * maxn;
     k.span = m.span_sigmas;
     double A[9], D[9];
     load_square(m.A, m.nx, A);
@@ -345,7 +348,7 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     f->part = static_cast<double*>(A((size_t)MAX_RED_BLOCKS * NPART * sizeof(double)));
     f->bfac = static_cast<double*>(A((size_t)MAX_RED_BLOCKS * sizeof(double)));
     f->coef = static_cast<double*>(A((size_t)(2 * LMAX + 1) * 6 * sizeof(double)));
-    f->W = static_cast<double*>(A((size_t)3 * 256 * 256 * sizeof(double)));
+    f->W = static_cast<double*>(A((size_t)model->nx * f->km.wstride * sizeof(double)));
     f->tab = static_cast<double*>(A((size_t)3 * TAB_STRIDE * sizeof(double)));
     f->desc = static_cast<DevDesc*>(A(sizeof(DevDesc)));
     if (model->grid == PMF_GRID_CHEBYSHEV) {
@@ -457,6 +460,10 @@ pmf_status pmf_predict(pmf_filter* f, double T, void* stream) {
     if (!f) return fail(PMF_E_INVALID, "filter is NULL");
     if (!std::isfinite(T) || T < 0.0) return fail(PMF_E_INVALID, "T must be finite and >= 0");
     if (T == 0.0) return PMF_OK;
+    if (f->in_batch) {
+        hipError_t eb = batch_leave(f);
+        if (eb != hipSuccess) return hip_fail(eb, "leave batch mode");
+    }
     hipError_t e = hipSetDevice(f->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -478,6 +485,10 @@ pmf_status pmf_update(pmf_filter* f, const double* z, double* loglik, void* stre
     if (!f || !z) return fail(PMF_E_INVALID, "filter/z is NULL");
     for (int i = 0; i < f->model.nz; ++i)
         if (!std::isfinite(z[i])) return fail(PMF_E_INVALID, "non-finite measurement");
+    if (f->in_batch) {
+        hipError_t eb = batch_leave(f);
+        if (eb != hipSuccess) return hip_fail(eb, "leave batch mode");
+    }
     hipError_t e = hipSetDevice(f->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -518,6 +529,10 @@ pmf_status pmf_sync_status(pmf_filter* f, void* stream) {
 
 pmf_status pmf_moments(pmf_filter* f, double* mean, double* cov, void* stream) {
     if (!f || !mean || !cov) return fail(PMF_E_INVALID, "NULL argument");
+    if (f->in_batch) {
+        hipError_t eb = batch_leave(f);
+        if (eb != hipSuccess) return hip_fail(eb, "leave batch mode");
+    }
     hipError_t e = hipSetDevice(f->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -551,6 +566,10 @@ pmf_status pmf_last_substeps(pmf_filter* f, int* l) {
 
 pmf_status pmf_get_state(pmf_filter* f, void* host_buf, size_t* bytes) {
     if (!f || !bytes) return fail(PMF_E_INVALID, "NULL argument");
+    if (f->in_batch) {
+        hipError_t eb = batch_leave(f);
+        if (eb != hipSuccess) return hip_fail(eb, "leave batch mode");
+    }
     const size_t need = sizeof(pmf_state_header) + (size_t)f->ntot * f->es;
     if (!host_buf) {
         *bytes = need;
@@ -584,6 +603,10 @@ pmf_status pmf_get_state(pmf_filter* f, void* host_buf, size_t* bytes) {
 
 pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes) {
     if (!f || !host_buf) return fail(PMF_E_INVALID, "NULL argument");
+    if (f->in_batch) {
+        hipError_t eb = batch_leave(f);
+        if (eb != hipSuccess) return hip_fail(eb, "leave batch mode");
+    }
     if (bytes < sizeof(pmf_state_header)) return fail(PMF_E_INVALID, "image too small");
     pmf_state_header h;
     std::memcpy(&h, host_buf, sizeof(h));
@@ -617,7 +640,11 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes) {
     return PMF_OK;
 }
 
-void* pmf_density_ptr(pmf_filter* f) { return f ? f->buf[f->cur] : nullptr; }
+void* pmf_density_ptr(pmf_filter* f) {
+    if (!f) return nullptr;
+    if (f->in_batch && batch_leave(f) != hipSuccess) return nullptr;
+    return f->buf[f->cur];
+}
 
 pmf_status pmf_stream_sync(void* stream) {
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));

@@ -36,6 +36,7 @@ struct pmf_filter {
     void* D2 = nullptr;
     void* rk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // Chebyshev RK4 scratch
     bool cheb_d32_ready = false;
+    bool in_batch = false;         // density lives in buffer desc->par (batched steps)
     int nb = 0, chunk = 0;         // reduction partition
     bool have_pa = false;
     pmf::PredictArgs pa{};
@@ -64,5 +65,6 @@ pmf_status cheb_predict_mfma(pmf_filter* f, int l, hipStream_t st);
 // fused batched step (batch.hip)
 void batch_cache_release(pmf_ctx* ctx);
 void batch_forget_filter(pmf_ctx* ctx, pmf_filter* f);
+hipError_t batch_leave(pmf_filter* f);
 
 }  // namespace pmf

@@ -561,7 +561,7 @@ __global__ void k_scale_blocks(T* P, int ntot, int chunk, const double* bfac) {
 
 // ------------------------------------------------------------------ re-interpolation
 
-// Separable spectral weights, one matrix per axis at W + a*256*256 (row j' = new node):
+// Separable spectral weights, one matrix per axis at W + a*wstride (row j' = new node):
 // Fourier: periodic interpolation kernel sin(pi d) / (N tan(pi d / N)) of the
 // trigonometric interpolant, zero when the new node is outside [0, N-1] in old
 // index units; Chebyshev: barycentric form of the polynomial through the N+2
@@ -608,7 +608,7 @@ __global__ void k_interp_weights(KModel m, const DevDesc* d, const double* tab, 
             }
         }
     }
-    W[(size_t)a * 256 * 256 + e] = w;
+    W[(size_t)a * m.wstride + e] = w;
 }
 
 // out = (matrix W_a applied along axis a of in).  With want_sums the block also
@@ -622,7 +622,7 @@ k_interp_axis(KModel m, const DevDesc* d, const double* tab, const double* Wall,
     const int n = m.N[a];
     int s = 1;
     for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
-    const double* W = Wall + (size_t)a * 256 * 256;
+    const double* W = Wall + (size_t)a * m.wstride;
     const int lo = blockIdx.x * chunk;
     const int hi = min(m.ntot, lo + chunk);
     double acc[11];

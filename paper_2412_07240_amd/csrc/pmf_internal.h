@@ -216,6 +216,8 @@ struct DevDesc {
     int status;      // sticky status bits since the last synchronising call
     int ok;          // 1 while the running update is accepted
     int sep;         // running update: separable spectral interpolation
+    int par;         // batched steps: which of buffers 0/1 holds the density
+    int pad_i;
     double s;        // likelihood shift
     double mass, loglik, bfrac;
     double mean[3], cov[9];
@@ -230,6 +232,8 @@ struct KModel {
     int nx, grid, meas, nz, ncomp, interp, integ, prec;
     int N[3];
     int ntot;
+    int wstride;                 // doubles per axis in the separable weight buffer
+    int pad_k;
     double H[9];
     double hp[4];
     double lw[MAXMIX];           // log w_g - 1/2 log det(2 pi R_g)

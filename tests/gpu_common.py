@@ -20,6 +20,20 @@ def l1(model, M, a, b) -> float:
     return float(np.sum(q * np.abs(np.asarray(a, float) - np.asarray(b, float))))
 
 
+def l1_vs_oracle(model, c, M, P, st) -> float:
+    """L1 of a GPU density (c, M, P) against the oracle state st.  When the two
+    grids differ by more than 1e-12 (FP32 moments move the designed grid by
+    ~1e-6), the GPU density is first mapped onto the oracle's grid with the
+    oracle's own interpolant, so the figure measures the density, not the grid
+    shift; the grid deviation is checked separately."""
+    c, M = np.asarray(c, float), np.asarray(M, float)
+    scale = np.abs(st.M).max()
+    if np.abs(M - st.M).max() <= 1e-12 * scale and np.abs(c - st.c).max() <= 1e-12 * (scale + np.abs(st.c).max()):
+        return l1(model, st.M, P, st.P)
+    mapped = oracle.interpolate(model, oracle.State(c, M, st.t, np.asarray(P, float)), st.c, st.M)
+    return l1(model, st.M, mapped, st.P)
+
+
 class Pair:
     """One GPU filter and its oracle twin."""
 
@@ -57,6 +71,6 @@ class Pair:
         np.testing.assert_allclose(M, self.st.M, rtol=0, atol=grid_rtol * scale, err_msg=f"grid M {what}")
         np.testing.assert_allclose(c, self.st.c, rtol=0, atol=grid_rtol * (1 + np.abs(self.st.c).max()) + grid_rtol * scale * 10,
                                    err_msg=f"grid c {what}")
-        err = l1(self.model, self.st.M, P, self.st.P)
+        err = l1_vs_oracle(self.model, c, M, P, self.st)
         assert err <= tol_l1, f"L1 {err:.3e} > {tol_l1:.1e} {what}"
         return err

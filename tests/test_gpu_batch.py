@@ -1,0 +1,178 @@
+"""The fused batched step (one persistent launch per step, recorded as a HIP graph)
+against the FP64 oracle and against the generic path.
+
+Bar (FP32 densities): L1 <= 1e-5 per filter per step vs the oracle started from
+the same state, grids equal to 1e-5 relative, log-likelihood to 1e-4."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_common import l1, l1_vs_oracle, note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2412_07240_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.pmf_ctx_create(0)
+    yield c
+    B.pmf_ctx_destroy(c)
+
+
+def make(B, ctx, scs):
+    return [B.pmf_create(ctx, sc.model, sc.prior) for sc in scs]
+
+
+def zmat(scs, k):
+    nz = max(sc.model.nz for sc in scs)
+    z = np.zeros((len(scs), nz))
+    for i, sc in enumerate(scs):
+        z[i, :sc.model.nz] = sc.z[k]
+    return z
+
+
+def check_against_oracle(B, fs, scs, before, lls, what):
+    """before[i] = (c, M, t, P) of filter i ahead of the step."""
+    worst = 0.0
+    for i, (f, sc) in enumerate(zip(fs, scs)):
+        c, M, t, P = before[i]
+        st = oracle.State(np.array(c), np.array(M), t, np.asarray(P, float))
+        st, _ = oracle.predict(sc.model, st, sc.T)
+        st, ll_o, status, _, _ = oracle.update(sc.model, st, sc.z[k_of(what)])
+        _, c2, M2, t2, P2 = B.pmf_get_state(f)
+        np.testing.assert_allclose(M2, st.M, rtol=1e-4, atol=0, err_msg=f"{what} filter {i}")
+        np.testing.assert_allclose(c2, st.c, atol=1e-4 * np.abs(st.M).max() * 100, err_msg=f"{what} filter {i}")
+        err = l1_vs_oracle(sc.model, c2, M2, P2, st)
+        worst = max(worst, err)
+        assert err <= 1e-5, f"{what} filter {i} N={sc.model.N}: L1 {err:.3e}"
+        if np.isnan(ll_o):
+            assert np.isnan(lls[i]), (what, i, lls[i])     # both reject; predicted state kept
+        else:
+            assert abs(lls[i] - ll_o) <= 1e-4 * max(1.0, abs(ll_o)), (what, i, lls[i], ll_o)
+    return worst
+
+
+_K = {}
+
+
+def k_of(what):
+    return _K[what]
+
+
+def test_batch_lockstep_mixed_sizes(B, ctx):
+    scs = W.batched_workload(40, K=3)
+    note(f"case: batch of 40 mixed-size 2-D filters, sizes {sorted(set(sc.model.N[0] for sc in scs))}")
+    fs = make(B, ctx, scs)
+    try:
+        for k in range(3):
+            before = [B.pmf_get_state(f)[1:] for f in fs]
+            lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, k), want_loglik=True)
+            what = f"lockstep step {k}"
+            _K[what] = k
+            worst = check_against_oracle(B, fs, scs, before, lls, what)
+            note(f"  step {k}: worst L1 {worst:.2e}")
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
+def test_batch_matches_generic_fp32_path(B, ctx):
+    scs = W.batched_workload(12, K=5)
+    note("case: batch vs separate predict+update calls, 12 filters, 5 steps")
+    fa = make(B, ctx, scs)
+    fb = make(B, ctx, scs)
+    try:
+        for k in range(5):
+            B.pmf_batch_step(ctx, fa, scs[0].T, zmat(scs, k))
+            for f, sc in zip(fb, scs):
+                B.pmf_predict(f, sc.T)
+                B.pmf_update(f, sc.z[k])
+        for f, g, sc in zip(fa, fb, scs):
+            _, c1, M1, _, P1 = B.pmf_get_state(f)
+            _, c2, M2, _, P2 = B.pmf_get_state(g)
+            np.testing.assert_allclose(M1, M2, rtol=1e-4)
+            ref = oracle.State(c2, M2, 0.0, np.asarray(P2, float))
+            assert l1_vs_oracle(sc.model, c1, M1, P1, ref) <= 1e-5
+    finally:
+        for f in fa + fb:
+            B.pmf_destroy(f)
+
+
+def test_batch_1d_filters_trig_regrid(B, ctx):
+    note("case: batch of 1-D filters N in 64..256 (trigonometric re-interpolation)")
+    scs = [W.serving_track(i, K=3) for i in range(60)]
+    scs = [sc for sc in scs if sc.model.nx == 1][:10]
+    assert len(scs) >= 5
+    fs = make(B, ctx, scs)
+    try:
+        for k in range(3):
+            before = [B.pmf_get_state(f)[1:] for f in fs]
+            lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, k), want_loglik=True)
+            what = f"1d step {k}"
+            _K[what] = k
+            check_against_oracle(B, fs, scs, before, lls, what)
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
+def test_batch_full_size_sampled(B, ctx):
+    """The benchmark's launch: 4096 filters, N uniform in {32..128}^2.  Sampled
+    filters are checked against the oracle from their pre-step state."""
+    n = 4096
+    note(f"case: full batch {n} filters, 2 steps, 12 sampled filters checked")
+    scs = W.batched_workload(n, K=2)
+    fs = make(B, ctx, scs)
+    rng = np.random.default_rng(5)
+    sample = sorted(rng.choice(n, size=12, replace=False).tolist())
+    # make sure the largest grid is in the sample
+    big = [i for i, sc in enumerate(scs) if sc.model.N[0] == 128][0]
+    if big not in sample:
+        sample[0] = big
+    try:
+        B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, 0))          # warm: graph built
+        before = [B.pmf_get_state(fs[i])[1:] for i in sample]
+        lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, 1), want_loglik=True)
+        assert np.all(np.isfinite(lls))
+        what = "full step 1"
+        _K[what] = 1
+        check_against_oracle(B, [fs[i] for i in sample], [scs[i] for i in sample], before,
+                             [lls[i] for i in sample], what)
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
+def test_batch_replays_are_deterministic(B, ctx):
+    note("case: two identical batches give bitwise equal densities")
+    scs = W.batched_workload(24, K=3)
+    outs = []
+    for _ in range(2):
+        fs = make(B, ctx, scs)
+        for k in range(3):
+            B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, k))
+        outs.append([B.pmf_get_state(f)[4] for f in fs])
+        for f in fs:
+            B.pmf_destroy(f)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_batch_rejects_unsupported_filters(B, ctx):
+    note("case: batch rejects FP64 / 3-D filters before running")
+    sc = W.config2(K=1, N=32)                       # FP64
+    f = B.pmf_create(ctx, sc.model, sc.prior)
+    try:
+        with pytest.raises(B.PmfError) as e:
+            B.pmf_batch_step(ctx, [f], sc.T, sc.z[:1])
+        assert e.value.status == B.PMF_E_INVALID
+    finally:
+        B.pmf_destroy(f)

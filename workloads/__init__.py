@@ -200,10 +200,12 @@ def batched_filter(index: int, K: int = 100, sizes: Sequence[int] = BATCH_SIZES,
     Q = np.diag(rng.uniform(0.05, 1.0, size=2))
     N = int(sizes[rng.integers(len(sizes))])
     T = 0.05
+    # prior and noise widths (0.3) keep the first posterior resolved on the prior's
+    # +-8 sigma grid even at N = 32
     model = ModelSpec(nx=2, A=A, Q=Q, N=(N, N), t_nominal=T, integrator=integrator,
                       substeps=1, precision=precision, meas_kind=H_LINEAR, nz=2,
-                      H=np.eye(2), **gaussian_noise(0.1 ** 2 * np.eye(2)))
-    prior = gaussian_prior([0.0, 0.0], np.eye(2))
+                      H=np.eye(2), **gaussian_noise(0.3 ** 2 * np.eye(2)))
+    prior = gaussian_prior([0.0, 0.0], 0.3 ** 2 * np.eye(2))
     return simulate(model, prior, T, K, rng)
 
 
@@ -228,8 +230,8 @@ def serving_track(index: int, K: int = 4) -> Scenario:
     T = 0.05
     model = ModelSpec(nx=nx, A=A, Q=Q, N=(N,) * nx, t_nominal=T, integrator=INT_EXACT,
                       substeps=1, precision=FP32, meas_kind=H_LINEAR, nz=nx,
-                      H=np.eye(nx), **gaussian_noise(0.1 ** 2 * np.eye(nx)))
-    prior = gaussian_prior(np.zeros(nx), np.eye(nx))
+                      H=np.eye(nx), **gaussian_noise(0.3 ** 2 * np.eye(nx)))
+    prior = gaussian_prior(np.zeros(nx), 0.3 ** 2 * np.eye(nx))
     return simulate(model, prior, T, K, rng)
 
 
