@@ -197,6 +197,15 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
 pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
                           const double* z, double* loglik, void* stream);
 
+/* Kernel timing of batched steps: with enable != 0, every later pmf_batch_step
+ * records HIP events on its stream around its graph launch (the fused kernel
+ * and the work-counter reset).  pmf_batch_kernel_time synchronises the context's
+ * last batch stream and returns the summed event time (ms) and the number of
+ * launches since the previous call, then clears them.  Diagnostic, for
+ * measuring the fused kernel's duration. */
+pmf_status pmf_batch_profile(pmf_ctx* ctx, int enable);
+pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int* launches);
+
 /* Device pointer of the density (for zero-copy inspection in tests); valid until
  * the next call on the filter.  Returns NULL on error. */
 void* pmf_density_ptr(pmf_filter* f);

@@ -76,6 +76,8 @@ def lib():
             "pmf_batch_step": (ip, [vp, C.POINTER(vp), ip, C.c_double, dp, dp, vp]),
             "pmf_density_ptr": (vp, [vp]),
             "pmf_stream_sync": (ip, [vp]),
+            "pmf_batch_profile": (ip, [vp, ip]),
+            "pmf_batch_kernel_time": (ip, [vp, dp, C.POINTER(C.c_int)]),
             "pmf_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -88,7 +90,8 @@ def lib():
 
 EXPORTED = ("pmf_ctx_create", "pmf_ctx_destroy", "pmf_create", "pmf_destroy", "pmf_predict",
             "pmf_update", "pmf_moments", "pmf_sync_status", "pmf_last_substeps", "pmf_get_state",
-            "pmf_set_state", "pmf_batch_step", "pmf_density_ptr", "pmf_stream_sync", "pmf_last_error")
+            "pmf_set_state", "pmf_batch_step", "pmf_density_ptr", "pmf_stream_sync", "pmf_batch_profile",
+            "pmf_batch_kernel_time", "pmf_last_error")
 
 
 def pmf_last_error() -> str:
@@ -283,3 +286,19 @@ def pmf_batch_step(ctx, filters, T: float, z, stream=None, want_loglik: bool = F
 
 def pmf_density_ptr(f) -> int:
     return lib().pmf_density_ptr(f)
+
+
+def pmf_stream_sync(stream=None) -> None:
+    _check(lib().pmf_stream_sync(_stream(stream)))
+
+
+def pmf_batch_profile(ctx, enable: bool) -> None:
+    _check(lib().pmf_batch_profile(ctx, 1 if enable else 0))
+
+
+def pmf_batch_kernel_time(ctx):
+    """(summed event time in ms, launches) of batched steps since the last call."""
+    ms = C.c_double(0.0)
+    n = C.c_int(0)
+    _check(lib().pmf_batch_kernel_time(ctx, C.byref(ms), C.byref(n)))
+    return ms.value, n.value

@@ -311,6 +311,7 @@ void pmf_ctx_destroy(pmf_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     batch_cache_release(ctx);
+    for (hipEvent_t ev : ctx->ev_pool) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -424,6 +425,7 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     }
     hd.gn = hd.g;
     hd.l = 0;
+    hd.pscale = 1.0;
     e = hipMemcpy(f->desc, &hd, sizeof(hd), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_prior(f->km, kp, f->desc, f->tab, f->buf[0], model->precision, st);
     if (e == hipSuccess) e = normalise_current(f, st);
@@ -632,6 +634,7 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes) {
     hd.gn = hd.g;
     hd.t = h.t;
     hd.status = 0;
+    hd.pscale = 1.0;
     e = hipMemcpy(f->desc, &hd, sizeof(hd), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(f->buf[f->cur], static_cast<const unsigned char*>(host_buf) + sizeof(h), (size_t)f->ntot * f->es,

@@ -14,6 +14,10 @@ struct pmf_ctx {
     bool has_alloc = false;
     pmf_allocator alloc{};
     BatchCache* batch = nullptr;
+    bool profile = false;                       // record events around batched launches
+    std::vector<hipEvent_t> ev_pool;             // start/stop pairs, reused
+    int ev_used = 0;
+    hipStream_t ev_stream = nullptr;
 };
 
 struct pmf_filter {

@@ -10,6 +10,7 @@
 //   store.
 // HBM traffic per filter: the density read once and written once.
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -18,36 +19,52 @@
 namespace pmf {
 
 constexpr int FUSED_THREADS = 1024;
-constexpr int FUSED_WAVES = FUSED_THREADS / 64;
 constexpr int FUSED_LMAX = 64;
+
+constexpr int GMAX = 16;            // filters of one size packed into a workgroup
 
 struct FConst {
     KModel m;
     PredictArgs pa;
 };
 
+// one filter of a batch
 struct BItem {
     float* P[2];
     DevDesc* d;
     const FConst* k;
+    double* coef;  // stage coefficient table (RK4 / Euler)
     int idx;       // row of z / loglik
     int n0, n1;    // rows (1 for nx = 1) and row length
     int nx;
 };
 
-struct FShared {
-    Grid g;        // grid after the move
-    Grid gn;       // proposed grid
-    double coef[(2 * FUSED_LMAX + 1) * 6];
-    double h, etr;
-    int l, ok, sep, item, bad;
-    int fast;                  // linear-Gaussian log-likelihood as a quadratic in u
-    double q0, qb[2], qQ[3];   // log l = q0 + qb.u - 1/2 u^T Q u  (Q packed 00, 11, 01)
-    double s, inv_mass, loglik, mass;
-    double amap[4], bmap[2];   // new index coords -> old index coords
-    double inv_mass2;
-    double red[FUSED_WAVES][8];
-    double bits;
+// a group of G filters with the same grid size, processed by one workgroup
+struct GItem {
+    int first, G, n0, n1, nx, seg, type, pad;
+};
+
+// per-filter plan for one step, written by k_batch_plan
+struct FPlan {
+    double c[2], M[4], Mi[4], vol;   // grid after the move (2x2 row-major)
+    double gc[3];                    // exact integrator: W_y packed 00, 11, 01
+    double h, etr, T;
+    double q0, qb[2], qQ[3];         // linear-Gaussian log l = q0 + qb.u - 1/2 u^T Q u
+    double Wnom[2], span;
+    double pscale;                   // pending scale of the stored density
+    int l, bad, fast, integ, interp, nx, par, pad;
+};
+
+// per-filter working state in LDS
+struct FState {
+    FPlan p;
+    const float* pin;
+    float* pout;
+    double s, inv_mass, loglik;
+    double amap[4], bmap[2];
+    double gnc[2], gnM[4], gnvol;
+    double pscale2;
+    int ok, bits;
 };
 
 // ---------------------------------------------------------------- small helpers
@@ -101,6 +118,24 @@ __device__ inline void fdft8(float2* a, int s) {
     a[7] = f2sub(e[3], o3);
 }
 
+
+// x / d for 0 <= x < 2^31 by multiply and shift (d fixed for a loop)
+struct FDiv {
+    uint32_t m, s;
+};
+__device__ inline FDiv fdiv_make(uint32_t d) {
+    uint32_t s = 0;
+    while ((1u << s) < d) ++s;
+    // m = floor(2^32 (2^s - d) / d) + 1; the quotient is never within 2^-20 of an
+    // integer for the divisors used here (d <= 2^16), so FP64 division is exact enough
+    const double q = 4294967296.0 * (double)((1u << s) - d) / (double)d;
+    FDiv f;
+    f.m = (uint32_t)floor(q) + 1u;
+    f.s = s;
+    return f;
+}
+__device__ inline int fdiv(int x, FDiv f) { return (int)((__umulhi((uint32_t)x, f.m) + (uint32_t)x) >> f.s); }
+
 // One Stockham pass over nlines lines; element i of line L at L*ls + i*es.
 // tw[m] = e^{-2 pi i m / n}.
 template <int R>
@@ -109,21 +144,23 @@ __device__ void fpass(const float2* __restrict__ in, float2* __restrict__ out, i
     const int nb = n / R;
     const int tot = nlines * nb;
     const int tws = n / (Ns * R);
+    const FDiv dnb = fdiv_make(nb), dnl = fdiv_make(nlines), dns = fdiv_make(Ns);
     for (int w = threadIdx.x; w < tot; w += blockDim.x) {
         int line, j;
         if (line_fast) {
-            line = w % nlines;
-            j = w / nlines;
+            j = fdiv(w, dnl);
+            line = w - j * nlines;
         } else {
-            j = w % nb;
-            line = w / nb;
+            line = fdiv(w, dnb);
+            j = w - line * nb;
         }
         const float2* src = in + line * ls;
         float2* dst = out + line * ls;
         float2 v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * es];
-        const int k = j % Ns;
+        const int q = fdiv(j, dns);
+        const int k = j - q * Ns;
         if (k) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -136,7 +173,7 @@ __device__ void fpass(const float2* __restrict__ in, float2* __restrict__ out, i
         if (R == 3) fdft3(v, sign);
         if (R == 4) fdft4(v, sign);
         if (R == 8) fdft8(v, sign);
-        const int base = (j / Ns) * Ns * R + k;
+        const int base = q * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[(base + r * Ns) * es] = v[r];
     }
@@ -165,127 +202,113 @@ __device__ float2* ffft(float2* a, float2* b, int n, int nlines, int ls, int es,
     return in;
 }
 
-__device__ inline double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ inline double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+// ---------------------------------------------------------------- segmented reductions
+// Threads map onto points as (tr, g, j): TPR = G * seg threads per "super-row",
+// seg = next power of two >= n1.  Every filter's threads form aligned segments of
+// sw = min(seg, 64) lanes, so a filter's partials are reduced in a fixed order:
+// xor-shuffles inside the segment, then slots in LDS summed by thread g.
+
+struct Seg {
+    int seg, sw, tpr, rps, tr, g, j;
+    bool active;
+};
+
+__device__ inline Seg seg_map(int G, int seg, int n1) {
+    Seg s;
+    s.seg = seg;
+    s.sw = seg < 64 ? seg : 64;
+    s.tpr = G * seg;
+    s.rps = blockDim.x / s.tpr;
+    s.tr = threadIdx.x / s.tpr;
+    const int tt = threadIdx.x - s.tr * s.tpr;
+    s.g = tt / seg;
+    s.j = tt - s.g * seg;
+    s.active = s.tr < s.rps && s.j < n1;
+    return s;
 }
 
-// fixed-order workgroup sums of NV doubles; the result is valid in thread 0
 template <int NV>
-__device__ void fblock_sum(double* v, FShared& S) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+__device__ void seg_sum(double* v, const Seg& s, double* slots, int G) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
-    if (lane == 0)
-        for (int q = 0; q < NV; ++q) S.red[wave][q] = v[q];
+    for (int q = 0; q < NV; ++q)
+        for (int o = s.sw >> 1; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+    if ((threadIdx.x & (s.sw - 1)) == 0 && s.tr < s.rps)
+        for (int q = 0; q < NV; ++q) slots[(threadIdx.x / s.sw) * 8 + q] = v[q];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = blockDim.x >> 6;
-        for (int q = 0; q < NV; ++q) {
-            double acc = 0.0;
-            for (int w = 0; w < nw; ++w) acc += S.red[w][q];
-            v[q] = acc;
-        }
+    if ((int)threadIdx.x < G) {
+        const int g = threadIdx.x;
+        const int per_row = s.tpr / s.sw, per_seg = s.seg / s.sw;
+        double acc[NV];
+        for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+        for (int tr = 0; tr < s.rps; ++tr)
+            for (int h = 0; h < per_seg; ++h) {
+                const int slot = tr * per_row + g * per_seg + h;
+                for (int q = 0; q < NV; ++q) acc[q] += slots[slot * 8 + q];
+            }
+        for (int q = 0; q < NV; ++q) v[q] = acc[q];
     }
     __syncthreads();
 }
 
-__device__ double fblock_max(double v, FShared& S) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    v = wave_max(v);
-    if (lane == 0) S.red[wave][0] = v;
+__device__ double seg_max(double v, const Seg& s, double* slots, int G) {
+    for (int o = s.sw >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & (s.sw - 1)) == 0 && s.tr < s.rps) slots[(threadIdx.x / s.sw) * 8] = v;
     __syncthreads();
-    double r = S.red[0][0];
-    const int nw = blockDim.x >> 6;
-    for (int w = 1; w < nw; ++w) r = fmax(r, S.red[w][0]);
+    if ((int)threadIdx.x < G) {
+        const int g = threadIdx.x;
+        const int per_row = s.tpr / s.sw, per_seg = s.seg / s.sw;
+        double r = -INFINITY;
+        for (int tr = 0; tr < s.rps; ++tr)
+            for (int h = 0; h < per_seg; ++h) r = fmax(r, slots[(tr * per_row + g * per_seg + h) * 8]);
+        v = r;
+    }
     __syncthreads();
-    return r;
+    return v;
 }
 
-// log p(z | x) at index coordinates u (general measurement models, FP64)
-__device__ double floglik(const KModel& m, const FShared& S, const double* u, const double* z) {
-    if (S.fast) {
-        const double q = S.qQ[0] * u[0] * u[0] + S.qQ[1] * u[1] * u[1] + 2.0 * S.qQ[2] * u[0] * u[1];
-        return S.q0 + S.qb[0] * u[0] + S.qb[1] * u[1] - 0.5 * q;
-    }
-    double x[3];
-    for (int i = 0; i < m.nx; ++i) {
-        double s = S.g.c[i];
-        for (int k = 0; k < m.nx; ++k) s += S.g.M[i * 3 + k] * u[k];
-        x[i] = s;
-    }
-    double hx[3] = {0, 0, 0};
-    if (m.meas == PMF_H_LINEAR) {
-        for (int i = 0; i < m.nz; ++i) {
-            double s = 0.0;
-            for (int k = 0; k < m.nx; ++k) s += m.H[i * 3 + k] * x[k];
-            hx[i] = s;
-        }
-    } else if (m.meas == PMF_H_CUBIC1) {
-        hx[0] = m.hp[0] * x[0] + m.hp[1] * x[0] * x[0] * x[0];
-    } else {
-        double s = 0.0;
-        for (int k = 0; k < m.nx; ++k) s += x[k] * x[k];
-        hx[0] = sqrt(s);
-    }
-    double best = -INFINITY, terms[MAXMIX];
-    for (int g = 0; g < m.ncomp; ++g) {
-        double r[3];
-        for (int i = 0; i < m.nz; ++i) r[i] = z[i] - hx[i] - m.nmean[g][i];
-        double q = 0.0;
-        for (int i = 0; i < m.nz; ++i)
-            for (int k = 0; k < m.nz; ++k) q += r[i] * m.nRi[g][i * 3 + k] * r[k];
-        terms[g] = m.lw[g] - 0.5 * q;
-        best = terms[g] > best ? terms[g] : best;
-    }
-    if (m.ncomp == 1) return terms[0];
-    double acc = 0.0;
-    for (int g = 0; g < m.ncomp; ++g) acc += exp(terms[g] - best);
-    return best + log(acc);
-}
+// ---------------------------------------------------------------- planning (one thread per filter)
 
-// Thread 0: substeps, stage coefficients, trace factor, grid move (into S.g).
-__device__ void fplan(const PredictArgs& a, const DevDesc* d, FShared& S) {
+__device__ void plan_one(const BItem& I, const double* z, FPlan& P) {
+    const PredictArgs& a = I.k->pa;
+    const KModel& m = I.k->m;
+    const DevDesc* d = I.d;
     const int n = a.nx;
-    S.g = d->g;
+    Grid g = d->g;
     double Mi[9];
-    mat_copy(Mi, S.g.Mi);
+    mat_copy(Mi, g.Mi);
     int l = a.lmin;
-    S.bad = 0;
+    P.bad = 0;
     if (a.integ == PMF_INT_RK4 && a.T > 0.0) {
         double lam = 0.0;
-        const double* Es[3] = {nullptr, a.emh, a.emT};
         for (int q = 0; q < 3; ++q) {
             double E[9], t1[9], Dy[9];
             if (q == 0) {
                 mat_copy(E, a.D);
             } else {
-                mat_mul(t1, Es[q], a.D, n);
-                mat_mul_bt(E, t1, Es[q], n);
+                const double* Eq = (q == 1) ? a.emh : a.emT;
+                mat_mul(t1, Eq, a.D, n);
+                mat_mul_bt(E, t1, Eq, n);
             }
             sandwich_inv(Dy, Mi, E, n);
             double lb = 0.0;
             for (int i = 0; i < n; ++i)
                 for (int j = 0; j < n; ++j) lb += fabs(Dy[i * 3 + j]) * a.rho[i] * a.rho[j];
-            lb *= 0.5;
-            lam = lb > lam ? lb : lam;
+            lam = fmax(lam, 0.5 * lb);
         }
         const double need = ceil(a.T * lam / RK4_STABLE_STEP);
         if (need > (double)l) l = need > (double)FUSED_LMAX ? FUSED_LMAX + 1 : (int)need;
     }
     if (l > FUSED_LMAX) {
         l = FUSED_LMAX;
-        S.bad = 1;
+        P.bad = 1;
     }
     const double h = a.T / l;
     if (a.integ == PMF_INT_EXACT) {
         double Wy[9];
         sandwich_inv(Wy, Mi, a.W, n);
-        pack_sym(S.coef, Wy);
+        P.gc[0] = Wy[0];
+        P.gc[1] = Wy[4];
+        P.gc[2] = Wy[1];
     } else {
         const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
         const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
@@ -296,477 +319,804 @@ __device__ void fplan(const PredictArgs& a, const DevDesc* d, FShared& S) {
             mat_mul(t1, Ek, a.D, n);
             mat_mul_bt(E, t1, Ek, n);
             sandwich_inv(Dy, Mi, E, n);
-            pack_sym(S.coef + 6 * k, Dy);
+            I.coef[3 * k + 0] = Dy[0];
+            I.coef[3 * k + 1] = Dy[4];
+            I.coef[3 * k + 2] = Dy[1];
             mat_mul(nxt, Ek, Estep, n);
             mat_copy(Ek, nxt);
         }
     }
-    S.l = l;
-    S.h = h;
-    S.etr = a.etr;
+    P.l = l;
+    P.h = h;
+    P.etr = a.etr;
+    P.T = a.T;
+    // grid follows x' = A x
     double c2[3], M2[9];
-    mat_vec(c2, a.Phi, S.g.c, n);
-    mat_mul(M2, a.Phi, S.g.M, n);
-    for (int i = 0; i < n; ++i) S.g.c[i] = c2[i];
-    mat_copy(S.g.M, M2);
-    grid_finish(S.g, n);
-}
-
-// linear-Gaussian fast path: log l(u) as a quadratic in index coordinates
-__device__ void flik_setup(const KModel& m, const double* z, FShared& S) {
-    S.fast = (m.meas == PMF_H_LINEAR && m.ncomp == 1 && m.nx <= 2) ? 1 : 0;
-    if (!S.fast) return;
-    const int nx = m.nx, nz = m.nz;
-    double r0[3], G[9];
-    for (int i = 0; i < nz; ++i) {
-        double hc = 0.0;
-        for (int k = 0; k < nx; ++k) hc += m.H[i * 3 + k] * S.g.c[k];
-        r0[i] = z[i] - m.nmean[0][i] - hc;
-        for (int b = 0; b < nx; ++b) {
+    mat_vec(c2, a.Phi, g.c, n);
+    mat_mul(M2, a.Phi, g.M, n);
+    for (int i = 0; i < n; ++i) g.c[i] = c2[i];
+    mat_copy(g.M, M2);
+    grid_finish(g, n);
+    P.c[0] = g.c[0];
+    P.c[1] = n > 1 ? g.c[1] : 0.0;
+    P.M[0] = g.M[0];
+    P.M[1] = g.M[1];
+    P.M[2] = g.M[3];
+    P.M[3] = g.M[4];
+    P.Mi[0] = g.Mi[0];
+    P.Mi[1] = g.Mi[1];
+    P.Mi[2] = g.Mi[3];
+    P.Mi[3] = g.Mi[4];
+    P.vol = g.vol;
+    P.Wnom[0] = m.Wnom[0];
+    P.Wnom[1] = m.Wnom[4];
+    P.span = m.span;
+    P.integ = a.integ;
+    P.interp = m.interp;
+    P.nx = n;
+    P.par = d->par;
+    P.pscale = d->pscale;
+    // linear-Gaussian measurement: log l as a quadratic in index coordinates
+    P.fast = (m.meas == PMF_H_LINEAR && m.ncomp == 1) ? 1 : 0;
+    P.q0 = 0.0;
+    P.qb[0] = P.qb[1] = 0.0;
+    P.qQ[0] = P.qQ[1] = P.qQ[2] = 0.0;
+    if (P.fast) {
+        const int nz = m.nz;
+        double r0[3], G[9], Rir0[3];
+        for (int i = 0; i < nz; ++i) {
+            double hc = 0.0;
+            for (int k = 0; k < n; ++k) hc += m.H[i * 3 + k] * g.c[k];
+            r0[i] = z[i] - m.nmean[0][i] - hc;
+            for (int b = 0; b < n; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += m.H[i * 3 + k] * g.M[k * 3 + b];
+                G[i * 3 + b] = s;
+            }
+        }
+        for (int i = 0; i < nz; ++i) {
             double s = 0.0;
-            for (int k = 0; k < nx; ++k) s += m.H[i * 3 + k] * S.g.M[k * 3 + b];
-            G[i * 3 + b] = s;
+            for (int k = 0; k < nz; ++k) s += m.nRi[0][i * 3 + k] * r0[k];
+            Rir0[i] = s;
         }
-    }
-    // log l = lw - 1/2 (r0 - G u)^T Ri (r0 - G u)
-    double Rir0[3];
-    for (int i = 0; i < nz; ++i) {
-        double s = 0.0;
-        for (int k = 0; k < nz; ++k) s += m.nRi[0][i * 3 + k] * r0[k];
-        Rir0[i] = s;
-    }
-    double rr = 0.0;
-    for (int i = 0; i < nz; ++i) rr += r0[i] * Rir0[i];
-    S.q0 = m.lw[0] - 0.5 * rr;
-    double Qf[4] = {0, 0, 0, 0};
-    S.qb[0] = S.qb[1] = 0.0;
-    for (int a = 0; a < nx; ++a) {
-        double s = 0.0;
-        for (int i = 0; i < nz; ++i) s += G[i * 3 + a] * Rir0[i];
-        S.qb[a] = s;
-        for (int b = 0; b < nx; ++b) {
-            double t = 0.0;
-            for (int i = 0; i < nz; ++i)
-                for (int k = 0; k < nz; ++k) t += G[i * 3 + a] * m.nRi[0][i * 3 + k] * G[k * 3 + b];
-            Qf[a * 2 + b] = t;
+        double rr = 0.0;
+        for (int i = 0; i < nz; ++i) rr += r0[i] * Rir0[i];
+        P.q0 = m.lw[0] - 0.5 * rr;
+        double Qf[4] = {0, 0, 0, 0};
+        for (int a2 = 0; a2 < n; ++a2) {
+            double s = 0.0;
+            for (int i = 0; i < nz; ++i) s += G[i * 3 + a2] * Rir0[i];
+            P.qb[a2] = s;
+            for (int b = 0; b < n; ++b) {
+                double t = 0.0;
+                for (int i = 0; i < nz; ++i)
+                    for (int k = 0; k < nz; ++k) t += G[i * 3 + a2] * m.nRi[0][i * 3 + k] * G[k * 3 + b];
+                Qf[a2 * 2 + b] = t;
+            }
         }
+        P.qQ[0] = Qf[0];
+        P.qQ[1] = Qf[3];
+        P.qQ[2] = Qf[1];
     }
-    S.qQ[0] = Qf[0];
-    S.qQ[1] = Qf[3];
-    S.qQ[2] = Qf[1];
 }
 
-__device__ inline void cubic_weights(double t, float* w) {
-    w[0] = (float)(-t * (t - 1.0) * (t - 2.0) / 6.0);
-    w[1] = (float)((t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0);
-    w[2] = (float)(-(t + 1.0) * t * (t - 2.0) / 2.0);
-    w[3] = (float)((t + 1.0) * t * (t - 1.0) / 6.0);
+__global__ void k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
+                             const double* __restrict__ zall, int nzmax) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const BItem I = items[i];
+    plan_one(I, zall + (size_t)I.idx * nzmax, plans[i]);
 }
-
-// ---------------------------------------------------------------- the kernel
 
 __global__ void k_batch_reset(int* ctr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = 0;
 }
 
-struct FBufs {
-    float2* A;
-    float2* B;
-    float2* twr;   // 128: row transform (n1/2 points)
-    float2* twc;   // 256: column transform (n0 points)
-    float2* twp;   // 130: r2c split twiddles e^{-2 pi i s / n1}
-    double* trig;  // 2 x 256: cos, sin of pi j / n1
-};
+// general measurement models: log p(z | x) at index coordinates u (FP64)
+__device__ __noinline__ double floglik_general(const KModel& m, const FPlan& P, double u0, double u1,
+                                               const double* z) {
+    double x[2];
+    x[0] = P.c[0] + P.M[0] * u0 + P.M[1] * u1;
+    x[1] = P.c[1] + P.M[2] * u0 + P.M[3] * u1;
+    double hx[3] = {0, 0, 0};
+    if (m.meas == PMF_H_LINEAR) {
+        for (int i = 0; i < m.nz; ++i) hx[i] = m.H[i * 3] * x[0] + (m.nx > 1 ? m.H[i * 3 + 1] * x[1] : 0.0);
+    } else if (m.meas == PMF_H_CUBIC1) {
+        hx[0] = m.hp[0] * x[0] + m.hp[1] * x[0] * x[0] * x[0];
+    } else {
+        hx[0] = sqrt(x[0] * x[0] + (m.nx > 1 ? x[1] * x[1] : 0.0));
+    }
+    double best = -INFINITY, terms[MAXMIX];
+    for (int g = 0; g < m.ncomp; ++g) {
+        double r[3];
+        for (int i = 0; i < m.nz; ++i) r[i] = z[i] - hx[i] - m.nmean[g][i];
+        double q = 0.0;
+        for (int i = 0; i < m.nz; ++i)
+            for (int k = 0; k < m.nz; ++k) q += r[i] * m.nRi[g][i * 3 + k] * r[k];
+        terms[g] = m.lw[g] - 0.5 * q;
+        best = fmax(best, terms[g]);
+    }
+    if (m.ncomp == 1) return terms[0];
+    double acc = 0.0;
+    for (int g = 0; g < m.ncomp; ++g) acc += exp(terms[g] - best);
+    return best + log(acc);
+}
 
-// Time update of one filter with the density resident in LDS.  Uses S.coef,
-// S.l, S.h, S.etr from fplan.  Returns the buffer holding the predicted real
-// density, element (r, j) at r * 2 * (n1/2 + 1) + j.
-__device__ float2* fused_predict(const BItem& I, const KModel& m, const float* Pin, FShared& S, const FBufs& F) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int n0 = I.n0, n1 = I.n1, nx = I.nx;
-    const int h1 = n1 / 2, pitch = h1 + 1;
-    float2* bufA = F.A;
-    float2* bufB = F.B;
-    // load rows as complex pairs (x_{2k}, x_{2k+1})
-    const float2* Pin2 = reinterpret_cast<const float2*>(Pin);
-    for (int e = tid; e < n0 * h1; e += nt) {
-        const int r = e / h1, k = e - r * h1;
-        bufA[r * pitch + k] = Pin2[e];
+__device__ inline double floglik(const FPlan& P, const KModel& m, double u0, double u1, const double* z) {
+    if (P.fast) return P.q0 + P.qb[0] * u0 + P.qb[1] * u1 -
+                       0.5 * (P.qQ[0] * u0 * u0 + P.qQ[1] * u1 * u1 + 2.0 * P.qQ[2] * u0 * u1);
+    return floglik_general(m, P, u0, u1, z);
+}
+
+// trigonometric interpolant of the n samples Po[0..n) at index position nu (1-D)
+__device__ __noinline__ float trig_interp_1d(const float* Po, int n, double nu) {
+    const double fl = floor(nu);
+    if (nu == fl) return Po[(int)fl];
+    double sa, ca, spn, cpn;
+    sincospi(nu / n, &sa, &ca);
+    sincospi(nu, &spn, &cpn);
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) {
+        double sb, cb;
+        sincospi((double)q / n, &sb, &cb);
+        const double num = ca * cb + sa * sb;
+        const double den = sa * cb - ca * sb;
+        acc += ((q & 1) ? -spn : spn) * num / (n * den) * (double)Po[q];
+    }
+    return (float)acc;
+}
+
+__device__ inline void cubic_weights(float t, float* w) {
+    w[0] = -t * (t - 1.f) * (t - 2.f) * (1.f / 6.f);
+    w[1] = (t + 1.f) * (t - 1.f) * (t - 2.f) * 0.5f;
+    w[2] = -(t + 1.f) * t * (t - 2.f) * 0.5f;
+    w[3] = (t + 1.f) * t * (t - 1.f) * (1.f / 6.f);
+}
+
+// ---------------------------------------------------------------- the fused kernel
+// Specialised at compile time per group type (N0 x N1 grid, G filters side by
+// side): every loop bound, divisor and radix plan is a constant.
+
+constexpr int radix_at(int n, int i) {
+    int k = 0;
+    while (n % 8 == 0 && n > 1) {
+        if (k == i) return 8;
+        n /= 8;
+        ++k;
+    }
+    while (n % 4 == 0) {
+        if (k == i) return 4;
+        n /= 4;
+        ++k;
+    }
+    while (n % 2 == 0) {
+        if (k == i) return 2;
+        n /= 2;
+        ++k;
+    }
+    while (n % 3 == 0) {
+        if (k == i) return 3;
+        n /= 3;
+        ++k;
+    }
+    return 0;
+}
+constexpr int num_passes(int n) {
+    int k = 0;
+    while (radix_at(n, k) != 0) ++k;
+    return k;
+}
+constexpr int pow2_ceil(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+template <int R> __device__ inline void fdft(float2* v, int sign) {
+    if constexpr (R == 2) fdft2(v);
+    if constexpr (R == 3) fdft3(v, sign);
+    if constexpr (R == 4) fdft4(v, sign);
+    if constexpr (R == 8) fdft8(v, sign);
+}
+
+// one Stockham pass; LF: consecutive threads take consecutive lines
+template <int R, int N, int NS, int NL, int LS, int ES, int SIGN, bool LF>
+__device__ inline void cpass(const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw) {
+    constexpr int NB = N / R;
+    constexpr int TOT = NL * NB;
+    constexpr int TWS = N / (NS * R);
+#pragma unroll 1
+    for (int w0 = 0; w0 < TOT; w0 += FUSED_THREADS) {
+        const int w = w0 + (int)threadIdx.x;
+        if (TOT % FUSED_THREADS == 0 || w < TOT) {
+            int line, j;
+            if constexpr (LF) {
+                j = w / NL;
+                line = w - j * NL;
+            } else {
+                line = w / NB;
+                j = w - line * NB;
+            }
+            const float2* src = in + line * LS;
+            float2* dst = out + line * LS;
+            float2 v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = src[(j + r * NB) * ES];
+            const int q = j / NS;
+            const int k = j - q * NS;
+            if (NS > 1 && k) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 t = tw[k * r * TWS];
+                    if (SIGN > 0) t.y = -t.y;
+                    v[r] = f2mul(v[r], t);
+                }
+            }
+            fdft<R>(v, SIGN);
+            const int base = q * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[(base + r * NS) * ES] = v[r];
+        }
+    }
+}
+
+template <int N, int NL, int LS, int ES, int SIGN, bool LF, int P = 0, int NS = 1>
+__device__ inline float2* cfft(float2* in, float2* out, const float2* tw) {
+    if constexpr (P == num_passes(N)) {
+        return in;
+    } else {
+        constexpr int R = radix_at(N, P);
+        cpass<R, N, NS, NL, LS, ES, SIGN, LF>(in, out, tw);
+        __syncthreads();
+        return cfft<N, NL, LS, ES, SIGN, LF, P + 1, NS * R>(out, in, tw);
+    }
+}
+
+// segmented reductions with compile-time mapping (see Seg above)
+template <int G, int SEGW, int NV>
+__device__ inline void cseg_sum(double* v, double* slots) {
+    constexpr int SW = SEGW < 64 ? SEGW : 64;
+    constexpr int TPR = G * SEGW;
+    constexpr int RPS = FUSED_THREADS / TPR;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int o = SW >> 1; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+    if ((threadIdx.x & (SW - 1)) == 0 && (int)threadIdx.x < RPS * TPR)
+        for (int q = 0; q < NV; ++q) slots[(threadIdx.x / SW) * 8 + q] = v[q];
+    __syncthreads();
+    if ((int)threadIdx.x < G) {
+        const int g = threadIdx.x;
+        constexpr int PER_ROW = TPR / SW, PER_SEG = SEGW / SW;
+        double acc[NV];
+        for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+        for (int tr = 0; tr < RPS; ++tr)
+            for (int h = 0; h < PER_SEG; ++h) {
+                const int slot = tr * PER_ROW + g * PER_SEG + h;
+                for (int q = 0; q < NV; ++q) acc[q] += slots[slot * 8 + q];
+            }
+        for (int q = 0; q < NV; ++q) v[q] = acc[q];
+    }
+    __syncthreads();
+}
+
+template <int G, int SEGW>
+__device__ inline double cseg_max(double v, double* slots) {
+    constexpr int SW = SEGW < 64 ? SEGW : 64;
+    constexpr int TPR = G * SEGW;
+    constexpr int RPS = FUSED_THREADS / TPR;
+#pragma unroll
+    for (int o = SW >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & (SW - 1)) == 0 && (int)threadIdx.x < RPS * TPR) slots[(threadIdx.x / SW) * 8] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < G) {
+        const int g = threadIdx.x;
+        constexpr int PER_ROW = TPR / SW, PER_SEG = SEGW / SW;
+        double r = -INFINITY;
+        for (int tr = 0; tr < RPS; ++tr)
+            for (int h = 0; h < PER_SEG; ++h) r = fmax(r, slots[(tr * PER_ROW + g * PER_SEG + h) * 8]);
+        v = r;
+    }
+    __syncthreads();
+    return v;
+}
+
+// thread 0..G-1: normaliser, moments and the new grid of filter tid (FP64, 2x2 scalars)
+__device__ void filter_design(FState& F, const double* acc, int NX, int n0, int n1) {
+    const FPlan& P = F.p;
+    const double S0 = acc[0];
+    const double mass = P.vol * S0;
+    const double half0 = (double)(n0 / 2), half1 = (double)(n1 / 2);
+    F.ok = !P.bad && isfinite(F.s) && isfinite(mass) && mass > 0.0;
+    F.bits = 0;
+    if (!F.ok) return;
+    F.inv_mass = 1.0 / mass;
+    F.loglik = F.s + log(mass);
+    const double ub0 = acc[1] / S0, ub1 = acc[2] / S0;
+    const double C00 = acc[3] / S0 - ub0 * ub0;
+    const double C11 = acc[4] / S0 - ub1 * ub1;
+    const double C01 = acc[5] / S0 - ub0 * ub1;
+    if (acc[6] / S0 > BOUNDARY_TOL) F.bits = PMF_W_BOUNDARY;
+    double mean0, mean1, cov00, cov11;
+    if (NX == 2) {
+        mean0 = P.c[0] + P.M[0] * ub0 + P.M[1] * ub1;
+        mean1 = P.c[1] + P.M[2] * ub0 + P.M[3] * ub1;
+        cov00 = P.M[0] * P.M[0] * C00 + 2.0 * P.M[0] * P.M[1] * C01 + P.M[1] * P.M[1] * C11;
+        cov11 = P.M[2] * P.M[2] * C00 + 2.0 * P.M[2] * P.M[3] * C01 + P.M[3] * P.M[3] * C11;
+    } else {
+        mean0 = P.c[0] + P.M[0] * ub0;
+        mean1 = 0.0;
+        cov00 = P.M[0] * P.M[0] * C00;
+        cov11 = 1.0;
+    }
+    const double v0 = cov00 + P.Wnom[0];
+    const double v1 = (NX == 2) ? cov11 + P.Wnom[1] : 1.0;
+    if (!(v0 > 0.0) || !(v1 > 0.0) || !isfinite(v0) || !isfinite(v1)) {
+        F.ok = 0;
+        return;
+    }
+    const double d0 = 2.0 * P.span * sqrt(v0) / (NX == 2 ? (double)n0 : (double)n1);
+    const double d1 = (NX == 2) ? 2.0 * P.span * sqrt(v1) / (double)n1 : 1.0;
+    F.gnc[0] = mean0;
+    F.gnc[1] = mean1;
+    F.gnM[0] = d0;
+    F.gnM[1] = 0.0;
+    F.gnM[2] = 0.0;
+    F.gnM[3] = d1;
+    F.gnvol = (NX == 2) ? d0 * d1 : d0;
+    const bool aligned = (NX == 1) || (P.M[1] == 0.0 && P.M[2] == 0.0);
+    // separable 2-D and Lagrange 1-D regrids are not fused: reject, flagged
+    if ((NX == 2 && P.interp == PMF_INTERP_AUTO && aligned) || (NX == 1 && P.interp != PMF_INTERP_AUTO)) {
+        F.ok = 0;
+        F.bits = PMF_E_INVALID;
+        return;
+    }
+    // new index coordinates -> old index coordinates: Mi (M' u' + c' - c) + N/2
+    const double dc0 = mean0 - P.c[0], dc1 = mean1 - P.c[1];
+    if (NX == 2) {
+        F.amap[0] = P.Mi[0] * d0;
+        F.amap[1] = P.Mi[1] * d1;
+        F.amap[2] = P.Mi[2] * d0;
+        F.amap[3] = P.Mi[3] * d1;
+        F.bmap[0] = P.Mi[0] * dc0 + P.Mi[1] * dc1 + half0;
+        F.bmap[1] = P.Mi[2] * dc0 + P.Mi[3] * dc1 + half1;
+    } else {
+        F.amap[0] = P.Mi[0] * d0;
+        F.bmap[0] = P.Mi[0] * dc0 + half1;
+    }
+}
+
+// thread 0..G-1: write back descriptor and log-likelihood of filter tid
+__device__ void filter_commit(const FState& F, const BItem& I, double* ll_out) {
+    const FPlan& P = F.p;
+    DevDesc* d = I.d;
+    Grid gg;
+    mat_zero(gg.M);
+    for (int q = 0; q < 3; ++q) gg.c[q] = 0.0;
+    if (F.ok) {
+        gg.c[0] = F.gnc[0];
+        gg.c[1] = P.nx == 2 ? F.gnc[1] : 0.0;
+        gg.M[0] = F.gnM[0];
+        if (P.nx == 2) gg.M[4] = F.gnM[3];
+    } else {
+        gg.c[0] = P.c[0];
+        gg.c[1] = P.c[1];
+        gg.M[0] = P.M[0];
+        if (P.nx == 2) {
+            gg.M[1] = P.M[1];
+            gg.M[3] = P.M[2];
+            gg.M[4] = P.M[3];
+        }
+    }
+    grid_finish(gg, P.nx);
+    d->g = gg;
+    d->gn = gg;
+    d->t += P.T;
+    d->l = P.l;
+    d->h = P.h;
+    d->etr = P.etr;
+    d->par = 1 - P.par;
+    if (F.ok) {
+        d->loglik = F.loglik;
+        d->status |= F.bits;
+        d->pscale = F.pscale2;
+        ll_out[I.idx] = F.loglik;
+    } else {
+        d->loglik = NAN;
+        d->status |= PMF_E_DEGENERATE | F.bits | (P.bad ? PMF_E_INVALID : 0);
+        d->pscale = 1.0;
+        ll_out[I.idx] = NAN;
+    }
+}
+
+template <int N0, int N1, int NX, int G>
+__device__ __noinline__ void process_group(const GItem& GI, const BItem* __restrict__ items, const FPlan* __restrict__ plans,
+                              const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out, float2* bufA,
+                              float2* bufB, float2* twr, float2* twc, float2* twp, FState* FS, double* slots) {
+    constexpr int H1 = N1 / 2, PITCH = H1 + 1, SPITCH = G * PITCH, RP = 2 * PITCH, RS = G * RP;
+    constexpr int SEGW = pow2_ceil(N1) < 32 ? 32 : pow2_ceil(N1);
+    constexpr int TPR = G * SEGW, RPS = FUSED_THREADS / TPR;
+    constexpr int NT = FUSED_THREADS;
+    const int tid = threadIdx.x;
+    const int Gact = GI.G;   // filters present (<= G)
+
+    if (tid < G) {
+        const int gg = tid < Gact ? tid : 0;
+        FS[tid].p = plans[GI.first + gg];
+        const BItem& I = items[GI.first + gg];
+        FS[tid].pin = I.P[FS[tid].p.par];
+        FS[tid].pout = I.P[1 - FS[tid].p.par];
+    }
+    for (int i = tid; i < H1; i += NT) {
+        float sn, cs;
+        sincospif(-2.0f * i / H1, &sn, &cs);
+        twr[i] = make_float2(cs, sn);
+    }
+    if (NX == 2)
+        for (int i = tid; i < N0; i += NT) {
+            float sn, cs;
+            sincospif(-2.0f * i / N0, &sn, &cs);
+            twc[i] = make_float2(cs, sn);
+        }
+    for (int i = tid; i <= H1; i += NT) {
+        float sn, cs;
+        sincospif(-2.0f * i / N1, &sn, &cs);
+        twp[i] = make_float2(cs, sn);
+    }
+    __syncthreads();
+
+    // ---- load: super-row L = r*G + g holds row r of filter g as complex pairs
+#pragma unroll 1
+    for (int e = tid; e < G * N0 * H1; e += NT) {
+        const int L = e / H1, k = e - L * H1;
+        const int r = L / G, g = L - r * G;
+        float2 v = make_float2(0.f, 0.f);
+        if (g < Gact) v = f2scale(reinterpret_cast<const float2*>(FS[g].pin)[r * H1 + k], (float)FS[g].p.pscale);
+        bufA[L * PITCH + k] = v;
     }
     __syncthreads();
     // ---- forward: rows (r2c), columns
-    float2* cur = ffft(bufA, bufB, h1, n0, pitch, 1, -1, F.twr, false);
+    float2* cur = cfft<H1, N0 * G, PITCH, 1, -1, true>(bufA, bufB, twr);
     float2* oth = (cur == bufA) ? bufB : bufA;
-    for (int e = tid; e < n0 * (h1 + 1); e += nt) {
-        const int r = e / (h1 + 1), s = e - r * (h1 + 1);
-        const float2 Zs = cur[r * pitch + (s == h1 ? 0 : s)];
-        const float2 Zc = f2conj(cur[r * pitch + (s == 0 ? 0 : h1 - s)]);
+#pragma unroll 1
+    for (int e = tid; e < N0 * G * PITCH; e += NT) {
+        const int L = e / PITCH, s = e - L * PITCH;
+        const float2 Zs = cur[L * PITCH + (s == H1 ? 0 : s)];
+        const float2 Zc = f2conj(cur[L * PITCH + (s == 0 ? 0 : H1 - s)]);
         const float2 E = f2scale(f2add(Zs, Zc), 0.5f);
-        const float2 Dd = f2sub(Zs, Zc);
-        // X_s = E - i/2 W^s (Z_s - conj Z_{h1-s})
-        const float2 t = f2mul(F.twp[s], Dd);
-        oth[r * pitch + s] = f2add(E, make_float2(0.5f * t.y, -0.5f * t.x));
+        const float2 t = f2mul(twp[s], f2sub(Zs, Zc));
+        // X_s = E - i/2 W^s (Z_s - conj Z_{H1-s})
+        oth[L * PITCH + s] = f2add(E, make_float2(0.5f * t.y, -0.5f * t.x));
     }
     __syncthreads();
     cur = oth;
     oth = (cur == bufA) ? bufB : bufA;
-    if (nx == 2) {
-        cur = ffft(cur, oth, n0, h1 + 1, 1, pitch, -1, F.twc, true);
+    if constexpr (NX == 2) {
+        cur = cfft<N0, SPITCH, 1, SPITCH, -1, true>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
-    // ---- per-mode gain, with 1/(n0 n1) of the unnormalised transforms
+    // ---- per-mode gain with 1/(N0 N1) of the unnormalised transforms
     {
-        const float scale = (float)(S.etr / ((double)n0 * n1));
-        const int l = S.l, integ = m.integ;
-        const float hh = (float)S.h;
-        for (int e = tid; e < n0 * (h1 + 1); e += nt) {
-            const int s0 = e / (h1 + 1), s1 = e - s0 * (h1 + 1);
-            float a1[2], a2[2];
+        constexpr float inv = 1.0f / ((float)N0 * (float)N1);
+#pragma unroll 1
+        for (int e = tid; e < N0 * SPITCH; e += NT) {
+            const int s0 = e / SPITCH, c = e - s0 * SPITCH;
+            const int g = c / PITCH, s1 = c - g * PITCH;
+            const FPlan& P = FS[g].p;
+            float a1, a2, b1 = 0.f, b2 = 0.f;   // axis 0 (a), axis 1 (b)
             {
-                const int kk = (s1 < h1) ? s1 : s1 - n1;
-                const float kap = 6.283185307179586f * kk / n1;
-                const int ax = (nx == 2) ? 1 : 0;
-                a2[ax] = kap * kap;
-                a1[ax] = (s1 == h1) ? 0.f : kap;
+                const int kk = (s1 < H1) ? s1 : s1 - N1;
+                const float kap = (6.283185307179586f / N1) * kk;
+                b2 = kap * kap;
+                b1 = (s1 == H1) ? 0.f : kap;
             }
-            if (nx == 2) {
-                const int kk = (s0 < n0 / 2) ? s0 : s0 - n0;
-                const float kap = 6.283185307179586f * kk / n0;
-                a2[0] = kap * kap;
-                a1[0] = (2 * s0 == n0) ? 0.f : kap;
+            if constexpr (NX == 2) {
+                const int kk = (s0 < N0 / 2) ? s0 : s0 - N0;
+                const float kap = (6.283185307179586f / N0) * kk;
+                a2 = kap * kap;
+                a1 = (2 * s0 == N0) ? 0.f : kap;
             } else {
-                a1[1] = 0.f;
-                a2[1] = 0.f;
+                a1 = b1;
+                a2 = b2;
+                b1 = b2 = 0.f;
             }
-            auto sigma = [&](const double* p) {
-                return (float)p[0] * a2[0] + (float)p[1] * a2[1] + 2.f * (float)p[3] * a1[0] * a1[1];
-            };
-            float g;
-            if (integ == PMF_INT_EXACT) {
-                g = expf(-0.5f * sigma(S.coef));
-            } else if (integ == PMF_INT_EULER) {
-                g = 1.f;
-                for (int q = 0; q < l; ++q) g = g / (1.f + 0.5f * hh * sigma(S.coef + 6 * q));
+            float g2;
+            if (P.integ == PMF_INT_EXACT) {
+                const float sig = (float)P.gc[0] * a2 + (float)P.gc[1] * b2 + 2.f * (float)P.gc[2] * a1 * b1;
+                g2 = __expf(-0.5f * sig);
             } else {
-                g = 1.f;
-                for (int q = 0; q < l; ++q) {
-                    const float la = -0.5f * sigma(S.coef + 12 * q);
-                    const float lb = -0.5f * sigma(S.coef + 12 * q + 6);
-                    const float lc = -0.5f * sigma(S.coef + 12 * q + 12);
-                    const float y2 = 1.f + 0.5f * hh * la;
-                    const float y3 = 1.f + 0.5f * hh * lb * y2;
-                    const float y4 = 1.f + hh * lb * y3;
-                    g *= 1.f + hh / 6.f * (la + 2.f * lb * y2 + 2.f * lb * y3 + lc * y4);
+                const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
+                const float hh = (float)P.h;
+                g2 = 1.f;
+                if (P.integ == PMF_INT_EULER) {
+                    for (int q = 0; q < P.l; ++q) {
+                        const float sig = (float)cf[3 * q] * a2 + (float)cf[3 * q + 1] * b2 +
+                                          2.f * (float)cf[3 * q + 2] * a1 * b1;
+                        g2 = g2 / (1.f + 0.5f * hh * sig);
+                    }
+                } else {
+                    for (int q = 0; q < P.l; ++q) {
+                        const double* c3 = cf + 6 * q;
+                        const float la = -0.5f * ((float)c3[0] * a2 + (float)c3[1] * b2 + 2.f * (float)c3[2] * a1 * b1);
+                        const float lb = -0.5f * ((float)c3[3] * a2 + (float)c3[4] * b2 + 2.f * (float)c3[5] * a1 * b1);
+                        const float lc = -0.5f * ((float)c3[6] * a2 + (float)c3[7] * b2 + 2.f * (float)c3[8] * a1 * b1);
+                        const float y2 = 1.f + 0.5f * hh * la;
+                        const float y3 = 1.f + 0.5f * hh * lb * y2;
+                        const float y4 = 1.f + hh * lb * y3;
+                        g2 *= 1.f + hh / 6.f * (la + 2.f * lb * y2 + 2.f * lb * y3 + lc * y4);
+                    }
                 }
             }
-            const float2 v = cur[s0 * pitch + s1];
-            cur[s0 * pitch + s1] = f2scale(v, g * scale);
+            cur[s0 * SPITCH + c] = f2scale(cur[s0 * SPITCH + c], g2 * (float)P.etr * inv);
         }
     }
     __syncthreads();
     // ---- inverse: columns, rows (c2r)
-    if (nx == 2) {
-        cur = ffft(cur, oth, n0, h1 + 1, 1, pitch, +1, F.twc, true);
+    if constexpr (NX == 2) {
+        cur = cfft<N0, SPITCH, 1, SPITCH, +1, true>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
-    for (int e = tid; e < n0 * h1; e += nt) {
-        const int r = e / h1, s = e - r * h1;
-        const float2 Xs = cur[r * pitch + s];
-        const float2 Xc = f2conj(cur[r * pitch + h1 - s]);
+#pragma unroll 1
+    for (int e = tid; e < N0 * G * H1; e += NT) {
+        const int L = e / H1, s = e - L * H1;
+        const float2 Xs = cur[L * PITCH + s];
+        const float2 Xc = f2conj(cur[L * PITCH + H1 - s]);
         const float2 Aa = f2add(Xs, Xc);
-        const float2 Bb = f2mul(f2conj(F.twp[s]), f2sub(Xs, Xc));
-        // Z_s = (X_s + conj X_{h1-s}) + i W^{-s} (X_s - conj X_{h1-s})
-        oth[r * pitch + s] = make_float2(Aa.x - Bb.y, Aa.y + Bb.x);
+        const float2 Bb = f2mul(f2conj(twp[s]), f2sub(Xs, Xc));
+        // Z_s = (X_s + conj X_{H1-s}) + i W^{-s} (X_s - conj X_{H1-s})
+        oth[L * PITCH + s] = make_float2(Aa.x - Bb.y, Aa.y + Bb.x);
     }
     __syncthreads();
-    return ffft(oth, cur, h1, n0, pitch, 1, +1, F.twr, false);
+    cur = cfft<H1, N0 * G, PITCH, 1, +1, true>(oth, cur, twr);
+    oth = (cur == bufA) ? bufB : bufA;
+    const float* Pr = reinterpret_cast<const float*>(cur);   // predicted: (r, g, j) at r*RS + g*RP + j
+    float* Po = reinterpret_cast<float*>(oth);               // posterior, same layout
+
+    // ---- likelihood (FP64 Horner in u0 per thread), shift, multiply, FP64 sums
+    const int tr = tid / TPR;
+    const int tt = tid - tr * TPR;
+    const int g = tt / SEGW;
+    const int j = tt - g * SEGW;
+    const bool act = tr < RPS && j < N1 && g < Gact;
+    constexpr double half0 = (double)(N0 / 2), half1 = (double)(N1 / 2);
+    const int gi = act ? g : 0;
+    const double* zg = zall + (size_t)items[GI.first + gi].idx * nzmax;
+    const KModel& mg = items[GI.first + gi].k->m;
+    const FPlan& Pg = FS[gi].p;
+    // log l = alpha + beta u0 + gamma u0^2 along this thread's rows (fast path)
+    const double uj = (double)j - half1;
+    double al, be, ga;
+    if (NX == 2) {
+        al = Pg.q0 + Pg.qb[1] * uj - 0.5 * Pg.qQ[1] * uj * uj;
+        be = Pg.qb[0] - Pg.qQ[2] * uj;
+        ga = -0.5 * Pg.qQ[0];
+    } else {
+        al = Pg.q0;
+        be = Pg.qb[0];
+        ga = -0.5 * Pg.qQ[0];
+    }
+    double mx = -INFINITY;
+    if (act) {
+        for (int r = tr; r < N0; r += RPS) {
+            const double u0 = (NX == 2) ? (double)r - half0 : uj;
+            const double L = Pg.fast ? al + u0 * (be + ga * u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
+            mx = fmax(mx, L);
+        }
+    }
+    mx = cseg_max<G, SEGW>(mx, slots);
+    if (tid < G) FS[tid].s = mx;
+    __syncthreads();
+    double acc[4] = {0, 0, 0, 0};   // sum w, sum w u0, sum w u0^2, boundary
+    if (act) {
+        const double sh = FS[g].s;
+        for (int r = tr; r < N0; r += RPS) {
+            const double u0 = (NX == 2) ? (double)r - half0 : uj;
+            const double L = Pg.fast ? al + u0 * (be + ga * u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
+            const int idx = r * RS + g * RP + j;
+            const float v = Pr[idx] * __expf((float)(L - sh));
+            Po[idx] = v;
+            const double w = (double)v;
+            acc[0] += w;
+            acc[1] += w * u0;
+            acc[2] += w * u0 * u0;
+            const bool edge = (NX == 2) ? (r == 0 || r == N0 - 1 || j == 0 || j == N1 - 1) : (j == 0 || j == N1 - 1);
+            if (edge) acc[3] += w;
+        }
+    }
+    // per-thread sums -> the seven moment sums (u1 is constant per thread in 2-D)
+    double red[7];
+    if (NX == 2) {
+        red[0] = acc[0];
+        red[1] = acc[1];
+        red[2] = uj * acc[0];
+        red[3] = acc[2];
+        red[4] = uj * uj * acc[0];
+        red[5] = uj * acc[1];
+        red[6] = acc[3];
+    } else {
+        red[0] = acc[0];
+        red[1] = acc[1];
+        red[2] = 0.0;
+        red[3] = acc[2];
+        red[4] = 0.0;
+        red[5] = 0.0;
+        red[6] = acc[3];
+    }
+    if (!act)
+        for (int q = 0; q < 7; ++q) red[q] = 0.0;
+    cseg_sum<G, SEGW, 7>(red, slots);
+    if (tid < Gact) filter_design(FS[tid], red, NX, N0, N1);
+    __syncthreads();
+
+    // ---- interpolation onto the new grid, straight to HBM (normalised lazily)
+    double macc[1] = {0.0};
+    if (act && FS[g].ok) {
+        const FState& F = FS[g];
+        float* Pout = F.pout;
+        const float* Pog = Po + g * RP;
+        const float inv_mass = (float)F.inv_mass;
+        for (int r = tr; r < N0; r += RPS) {
+            float val = 0.f;
+            if constexpr (NX == 2) {
+                const double u0 = (double)r - half0;
+                const double nu0 = F.amap[0] * u0 + F.amap[1] * uj + F.bmap[0];
+                const double nu1 = F.amap[2] * u0 + F.amap[3] * uj + F.bmap[1];
+                if (nu0 >= 0.0 && nu0 <= (double)(N0 - 1) && nu1 >= 0.0 && nu1 <= (double)(N1 - 1)) {
+                    const int i0 = (int)nu0, i1 = (int)nu1;   // floor: nu >= 0
+                    float w0[4], w1[4];
+                    cubic_weights((float)(nu0 - i0), w0);
+                    cubic_weights((float)(nu1 - i1), w1);
+                    int ra[4], cb[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int rr = i0 - 1 + a, cc = i1 - 1 + a;
+                        const bool okr = rr >= 0 && rr < N0, okc = cc >= 0 && cc < N1;
+                        ra[a] = okr ? rr : i0;
+                        cb[a] = okc ? cc : i1;
+                        if (!okr) w0[a] = 0.f;
+                        if (!okc) w1[a] = 0.f;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const float* row = Pog + ra[a] * RS;
+                        const float rsum = w1[0] * row[cb[0]] + w1[1] * row[cb[1]] + w1[2] * row[cb[2]] +
+                                           w1[3] * row[cb[3]];
+                        val += w0[a] * rsum;
+                    }
+                }
+            } else {
+                const double nu = F.amap[0] * uj + F.bmap[0];
+                if (nu >= 0.0 && nu <= (double)(N1 - 1)) val = trig_interp_1d(Pog, N1, nu);
+            }
+            val *= inv_mass;
+            Pout[r * N1 + j] = val;
+            macc[0] += (double)val;
+        }
+    }
+    cseg_sum<G, SEGW, 1>(macc, slots);
+    if (tid < Gact) {
+        FState& F = FS[tid];
+        if (F.ok) {
+            const double mass2 = F.gnvol * macc[0];
+            if (!(mass2 > 0.0) || !isfinite(mass2)) F.ok = 0;
+            else F.pscale2 = 1.0 / mass2;
+        }
+    }
+    __syncthreads();
+    // ---- rejected updates keep the predicted density and the moved grid
+    if (act && !FS[g].ok) {
+        float* Pout = FS[g].pout;
+        for (int r = tr; r < N0; r += RPS) Pout[r * N1 + j] = Pr[r * RS + g * RP + j];
+    }
+    if (tid < Gact) filter_commit(FS[tid], items[GI.first + tid], ll_out);
+    __syncthreads();
 }
 
-// store the predicted density (pitched in LDS) with the moved grid, update rejected
-__device__ void fused_store_predicted(const BItem& I, const float* Pr, float* Pout, DevDesc* d, FShared& S,
-                                      double* ll_out, int par, int extra_bits) {
-    const int n0 = I.n0, n1 = I.n1, rp = 2 * (n1 / 2 + 1);
-    for (int e = threadIdx.x; e < n0 * n1; e += blockDim.x) {
-        const int r = e / n1, j = e - r * n1;
-        Pout[e] = Pr[r * rp + j];
-    }
-    if (threadIdx.x == 0) {
-        d->g = S.g;
-        d->gn = S.g;
-        d->t += I.k->pa.T;
-        d->l = S.l;
-        d->h = S.h;
-        d->etr = S.etr;
-        d->loglik = NAN;
-        d->status |= PMF_E_DEGENERATE | extra_bits;
-        d->par = 1 - par;
-        ll_out[I.idx] = NAN;
-    }
-    __syncthreads();
+// group types served by the fused kernel
+enum {
+    GT_2D_128, GT_2D_96, GT_2D_64, GT_2D_48, GT_2D_32,
+    GT_1D_256, GT_1D_192, GT_1D_128, GT_1D_96, GT_1D_64, GT_1D_48, GT_1D_32, GT_COUNT
+};
+
+template <int N0, int N1>
+constexpr int group_g() {
+    constexpr int pitch = N1 / 2 + 1;
+    constexpr int seg = pow2_ceil(N1) < 32 ? 32 : pow2_ceil(N1);
+    int G = 1;
+    while (G < GMAX && N0 * (2 * G) * pitch <= 8704 && (2 * G) * seg <= FUSED_THREADS) G *= 2;
+    return G;
 }
 
 __global__ void __launch_bounds__(FUSED_THREADS)
-k_fused(const BItem* __restrict__ items, int nitems, int* ctr, const double* __restrict__ zall, int nzmax,
+k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__ items,
+        const FPlan* __restrict__ plans, int* ctr, const double* __restrict__ zall, int nzmax,
         double* __restrict__ ll_out, int bufcplx) {
     extern __shared__ __align__(16) unsigned char fsm[];
-    __shared__ FShared S;
-    FBufs F;
-    F.A = reinterpret_cast<float2*>(fsm);
-    F.B = F.A + bufcplx;
-    F.twr = F.B + bufcplx;
-    F.twc = F.twr + 128;
-    F.twp = F.twc + 256;
-    F.trig = reinterpret_cast<double*>(F.twp + 130);
-    const int tid = threadIdx.x, nt = blockDim.x;
-
+    __shared__ FState FS[GMAX];
+    __shared__ double slots[32 * 8];
+    __shared__ int item_sh;
+    float2* bufA = reinterpret_cast<float2*>(fsm);
+    float2* bufB = bufA + bufcplx;
+    float2* twr = bufB + bufcplx;   // 128
+    float2* twc = twr + 128;        // 128
+    float2* twp = twc + 128;        // 130
     for (;;) {
-        if (tid == 0) S.item = atomicAdd(ctr, 1);
+        if (threadIdx.x == 0) item_sh = atomicAdd(ctr, 1);
         __syncthreads();
-        const int it = S.item;
+        const int it = item_sh;
         __syncthreads();
-        if (it >= nitems) break;
-        const BItem I = items[it];
-        const KModel& m = I.k->m;
-        DevDesc* d = I.d;
-        const int n0 = I.n0, n1 = I.n1, nx = I.nx;
-        const int h1 = n1 / 2, pitch = h1 + 1;
-        const int par = d->par;
-        const float* Pin = I.P[par];
-        float* Pout = I.P[1 - par];
-        const double* z = zall + (size_t)I.idx * nzmax;
-
-        if (tid == 0) {
-            fplan(I.k->pa, d, S);
-            flik_setup(m, z, S);
+        if (it >= ngroups) break;
+        const GItem GI = groups[it];
+#define PMF_GROUP(T, N0, N1, NX) \
+    case T: process_group<N0, N1, NX, group_g<N0, N1>()>(GI, items, plans, zall, nzmax, ll_out, bufA, bufB, twr, twc, twp, FS, slots); break;
+        switch (GI.type) {
+            PMF_GROUP(GT_2D_128, 128, 128, 2)
+            PMF_GROUP(GT_2D_96, 96, 96, 2)
+            PMF_GROUP(GT_2D_64, 64, 64, 2)
+            PMF_GROUP(GT_2D_48, 48, 48, 2)
+            PMF_GROUP(GT_2D_32, 32, 32, 2)
+            PMF_GROUP(GT_1D_256, 1, 256, 1)
+            PMF_GROUP(GT_1D_192, 1, 192, 1)
+            PMF_GROUP(GT_1D_128, 1, 128, 1)
+            PMF_GROUP(GT_1D_96, 1, 96, 1)
+            PMF_GROUP(GT_1D_64, 1, 64, 1)
+            PMF_GROUP(GT_1D_48, 1, 48, 1)
+            PMF_GROUP(GT_1D_32, 1, 32, 1)
+            default: break;
         }
-        for (int i = tid; i < h1; i += nt) {
-            float s, c;
-            sincospif(-2.0f * i / h1, &s, &c);
-            F.twr[i] = make_float2(c, s);
-        }
-        for (int i = tid; i < n0; i += nt) {
-            float s, c;
-            sincospif(-2.0f * i / n0, &s, &c);
-            F.twc[i] = make_float2(c, s);
-        }
-        for (int i = tid; i <= h1; i += nt) {
-            float s, c;
-            sincospif(-2.0f * i / n1, &s, &c);
-            F.twp[i] = make_float2(c, s);
-        }
-        __syncthreads();
-        float2* cur = fused_predict(I, m, Pin, S, F);
-        float2* oth = (cur == F.A) ? F.B : F.A;
-        const float* Pr = reinterpret_cast<const float*>(cur);   // predicted, (r, j) at r*rp + j
-        float* Po = reinterpret_cast<float*>(oth);               // posterior, same layout
-        const int rp = 2 * pitch;
-
-        // ---- likelihood: max pass, multiply pass with FP64 sums
-        const int npt = n0 * n1;
-        const double half0 = (double)(n0 / 2), half1 = (double)(n1 / 2);
-        double mx = -INFINITY;
-        for (int e = tid; e < npt; e += nt) {
-            const int r = e / n1, j = e - r * n1;
-            double u[2];
-            if (nx == 2) {
-                u[0] = r - half0;
-                u[1] = j - half1;
-            } else {
-                u[0] = j - half1;
-                u[1] = 0.0;
-            }
-            mx = fmax(mx, floglik(m, S, u, z));
-        }
-        const double sh = fblock_max(mx, S);
-        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-        for (int e = tid; e < npt; e += nt) {
-            const int r = e / n1, j = e - r * n1;
-            double u[2];
-            bool edge;
-            if (nx == 2) {
-                u[0] = r - half0;
-                u[1] = j - half1;
-                edge = (r == 0 || r == n0 - 1 || j == 0 || j == n1 - 1);
-            } else {
-                u[0] = j - half1;
-                u[1] = 0.0;
-                edge = (j == 0 || j == n1 - 1);
-            }
-            const double L = floglik(m, S, u, z);
-            const float v = Pr[r * rp + j] * expf((float)(L - sh));
-            Po[r * rp + j] = v;
-            const double w = (double)v;
-            acc[0] += w;
-            acc[1] += w * u[0];
-            acc[2] += w * u[1];
-            acc[3] += w * u[0] * u[0];
-            acc[4] += w * u[1] * u[1];
-            acc[5] += w * u[0] * u[1];
-            if (edge) acc[6] += w;
-        }
-        fblock_sum<7>(acc, S);
-        if (tid == 0) {
-            const double mass = S.g.vol * acc[0];
-            S.ok = !S.bad && isfinite(sh) && isfinite(mass) && mass > 0.0;
-            S.bits = 0.0;
-            if (S.ok) {
-                S.s = sh;
-                S.mass = mass;
-                S.inv_mass = 1.0 / mass;
-                S.loglik = sh + log(mass);
-                // moments in index coordinates -> physical
-                const double ub[2] = {acc[1] / acc[0], acc[2] / acc[0]};
-                double Cu[9];
-                mat_zero(Cu);
-                Cu[0] = acc[3] / acc[0] - ub[0] * ub[0];
-                Cu[4] = acc[4] / acc[0] - ub[1] * ub[1];
-                Cu[1] = Cu[3] = acc[5] / acc[0] - ub[0] * ub[1];
-                double mu[3], mean[3], t1[9], C[9], cov[9];
-                mat_vec(mu, S.g.M, ub, nx);
-                for (int a = 0; a < nx; ++a) mean[a] = S.g.c[a] + mu[a];
-                mat_mul(t1, S.g.M, Cu, nx);
-                mat_mul_bt(C, t1, S.g.M, nx);
-                mat_zero(cov);
-                for (int a = 0; a < nx; ++a)
-                    for (int b = 0; b < nx; ++b) cov[a * 3 + b] = 0.5 * (C[a * 3 + b] + C[b * 3 + a]);
-                if (acc[6] / acc[0] > BOUNDARY_TOL) S.bits = (double)PMF_W_BOUNDARY;
-                // grid design
-                mat_zero(S.gn.M);
-                for (int a = 0; a < nx; ++a) {
-                    const double v = cov[a * 3 + a] + m.Wnom[a * 3 + a];
-                    if (!(v > 0.0) || !isfinite(v)) S.ok = 0;
-                    const double hw = m.span * sqrt(v);
-                    S.gn.M[a * 3 + a] = 2.0 * hw / (nx == 2 ? (a == 0 ? n0 : n1) : n1);
-                    S.gn.c[a] = mean[a];
-                }
-                for (int a = nx; a < 3; ++a) S.gn.c[a] = 0.0;
-                grid_finish(S.gn, nx);
-                bool aligned = true;
-                for (int a = 0; a < nx; ++a)
-                    for (int b = 0; b < nx; ++b)
-                        if (a != b && S.g.M[a * 3 + b] != 0.0) aligned = false;
-                S.sep = (m.interp == PMF_INTERP_AUTO && aligned) ? 1 : 0;
-                if (nx == 2 && S.sep) S.ok = 0;   // separable 2-D regrid is not fused
-                // new index coordinates u' -> old index coordinates
-                double t2[9], dc[3], bb[3];
-                mat_mul(t2, S.g.Mi, S.gn.M, nx);
-                for (int a = 0; a < nx; ++a) dc[a] = S.gn.c[a] - S.g.c[a];
-                mat_vec(bb, S.g.Mi, dc, nx);
-                if (nx == 2) {
-                    S.amap[0] = t2[0];
-                    S.amap[1] = t2[1];
-                    S.amap[2] = t2[3];
-                    S.amap[3] = t2[4];
-                    S.bmap[0] = bb[0] + half0;
-                    S.bmap[1] = bb[1] + half1;
-                } else {
-                    S.amap[0] = t2[0];
-                    S.bmap[0] = bb[0] + half1;
-                }
-            }
-        }
-        __syncthreads();
-        if (!S.ok) {
-            fused_store_predicted(I, Pr, Pout, d, S, ll_out, par, S.bad ? PMF_E_INVALID : 0);
-            continue;
-        }
-        // ---- interpolation of the posterior onto the new grid (dense, into cur)
-        float* Qv = reinterpret_cast<float*>(cur);
-        const float inv_mass = (float)S.inv_mass;
-        if (nx == 1) {
-            for (int j = tid; j < n1; j += nt) {
-                double sv, cv;
-                sincospi((double)j / n1, &sv, &cv);
-                F.trig[j] = cv;
-                F.trig[256 + j] = sv;
-            }
-        }
-        __syncthreads();   // every thread is done reading the predicted density
-        double macc[1] = {0.0};
-        for (int e = tid; e < npt; e += nt) {
-            const int r = e / n1, j = e - r * n1;
-            float val = 0.f;
-            if (nx == 2) {
-                const double u0 = r - half0, u1 = j - half1;
-                const double nu0 = S.amap[0] * u0 + S.amap[1] * u1 + S.bmap[0];
-                const double nu1 = S.amap[2] * u0 + S.amap[3] * u1 + S.bmap[1];
-                if (nu0 >= 0.0 && nu0 <= (double)(n0 - 1) && nu1 >= 0.0 && nu1 <= (double)(n1 - 1)) {
-                    const int i0 = (int)floor(nu0), i1 = (int)floor(nu1);
-                    float w0[4], w1[4];
-                    cubic_weights(nu0 - i0, w0);
-                    cubic_weights(nu1 - i1, w1);
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const int ra = i0 - 1 + a;
-                        if (ra < 0 || ra >= n0) continue;
-                        float rs = 0.f;
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const int cb = i1 - 1 + b;
-                            if (cb < 0 || cb >= n1) continue;
-                            rs += w1[b] * Po[ra * rp + cb];
-                        }
-                        val += w0[a] * rs;
-                    }
-                }
-            } else {
-                const double nu = S.amap[0] * (j - half1) + S.bmap[0];
-                if (nu >= 0.0 && nu <= (double)(n1 - 1)) {
-                    const double fl = floor(nu);
-                    if (nu == fl) {
-                        val = Po[(int)fl];
-                    } else {
-                        double sa, ca, spn, cpn;
-                        sincospi(nu / n1, &sa, &ca);
-                        sincospi(nu, &spn, &cpn);
-                        double acc1 = 0.0;
-                        for (int q = 0; q < n1; ++q) {
-                            const double cb = F.trig[q], sb = F.trig[256 + q];
-                            const double num = ca * cb + sa * sb;
-                            const double den = sa * cb - ca * sb;
-                            const double wgt = ((q & 1) ? -spn : spn) * num / (n1 * den);
-                            acc1 += wgt * (double)Po[q];
-                        }
-                        val = (float)acc1;
-                    }
-                }
-            }
-            val *= inv_mass;
-            Qv[e] = val;
-            macc[0] += (double)val;
-        }
-        fblock_sum<1>(macc, S);
-        if (tid == 0) {
-            const double mass2 = S.gn.vol * macc[0];
-            if (!(mass2 > 0.0) || !isfinite(mass2)) {
-                S.ok = 0;
-            } else {
-                S.inv_mass2 = 1.0 / mass2;
-            }
-        }
-        __syncthreads();
-        if (!S.ok) {
-            // the new grid lost the mass: redo the time update and keep it
-            float2* again = fused_predict(I, m, Pin, S, F);
-            fused_store_predicted(I, reinterpret_cast<const float*>(again), Pout, d, S, ll_out, par, 0);
-            continue;
-        }
-        const float inv2 = (float)S.inv_mass2;
-        for (int e = tid; e < npt; e += nt) Pout[e] = Qv[e] * inv2;
-        if (tid == 0) {
-            d->g = S.gn;
-            d->gn = S.gn;
-            d->t += I.k->pa.T;
-            d->l = S.l;
-            d->h = S.h;
-            d->etr = S.etr;
-            d->loglik = S.loglik;
-            d->status |= (int)S.bits;
-            d->par = 1 - par;
-            ll_out[I.idx] = S.loglik;
-        }
-        __syncthreads();
+#undef PMF_GROUP
     }
+}
+
+// host copy of the group sizes / types
+static int group_type(int nx, int n0, int n1) {
+    if (nx == 2 && n0 == n1) {
+        switch (n1) {
+            case 128: return GT_2D_128;
+            case 96: return GT_2D_96;
+            case 64: return GT_2D_64;
+            case 48: return GT_2D_48;
+            case 32: return GT_2D_32;
+        }
+    }
+    if (nx == 1) {
+        switch (n1) {
+            case 256: return GT_1D_256;
+            case 192: return GT_1D_192;
+            case 128: return GT_1D_128;
+            case 96: return GT_1D_96;
+            case 64: return GT_1D_64;
+            case 48: return GT_1D_48;
+            case 32: return GT_1D_32;
+        }
+    }
+    return -1;
+}
+
+static int group_capacity(int type) {
+    switch (type) {
+        case GT_2D_128: return group_g<128, 128>();
+        case GT_2D_96: return group_g<96, 96>();
+        case GT_2D_64: return group_g<64, 64>();
+        case GT_2D_48: return group_g<48, 48>();
+        case GT_2D_32: return group_g<32, 32>();
+        case GT_1D_256: return group_g<1, 256>();
+        case GT_1D_192: return group_g<1, 192>();
+        case GT_1D_128: return group_g<1, 128>();
+        case GT_1D_96: return group_g<1, 96>();
+        case GT_1D_64: return group_g<1, 64>();
+        case GT_1D_48: return group_g<1, 48>();
+        case GT_1D_32: return group_g<1, 32>();
+    }
+    return 0;
+}
+
+// density *= pending scale (one block), then the scale is cleared
+__global__ void k_apply_pscale(float* P, int n, DevDesc* d) {
+    const float s = (float)d->pscale;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) P[i] *= s;
+    __syncthreads();
+    if (threadIdx.x == 0) d->pscale = 1.0;
 }
 
 }  // namespace pmf
@@ -777,8 +1127,10 @@ struct BatchCache {
     std::vector<pmf_filter*> filters;
     double T = 0.0;
     hipStream_t stream = nullptr;
-    int n = 0, nzmax = 1;
+    int n = 0, nzmax = 1, ngroups = 0;
     pmf::BItem* d_items = nullptr;
+    pmf::GItem* d_groups = nullptr;
+    pmf::FPlan* d_plans = nullptr;
     pmf::FConst* d_consts = nullptr;
     double* d_z = nullptr;
     double* d_ll = nullptr;
@@ -794,12 +1146,16 @@ struct BatchCache {
 
 namespace pmf {
 
+constexpr int CPLX_BUDGET = 8704;   // complex LDS entries per buffer (2 buffers)
+
 static void cache_free(pmf_ctx* ctx, BatchCache* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     ctx_free(ctx, c->d_items, nullptr);
+    ctx_free(ctx, c->d_groups, nullptr);
+    ctx_free(ctx, c->d_plans, nullptr);
     ctx_free(ctx, c->d_consts, nullptr);
     ctx_free(ctx, c->d_z, nullptr);
     ctx_free(ctx, c->d_ll, nullptr);
@@ -825,13 +1181,18 @@ void batch_forget_filter(pmf_ctx* ctx, pmf_filter* f) {
         }
 }
 
-// Filters whose density lives in the batch buffer pair must be brought back
-// before the generic kernels touch them (and the other way round).
+// A filter's density lives in buffer desc->par, scaled lazily by desc->pscale,
+// while it takes batched steps; bring it back before the generic kernels run.
 hipError_t batch_leave(pmf_filter* f) {
     if (!f->in_batch) return hipSuccess;
     hipError_t e = hipDeviceSynchronize();
     int par = 0;
     if (e == hipSuccess) e = hipMemcpy(&par, &f->desc->par, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_apply_pscale, dim3(1), dim3(1024), 0, nullptr, static_cast<float*>(f->buf[par]), f->ntot,
+                       f->desc);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
     f->cur = par;
     f->in_batch = false;
@@ -861,8 +1222,18 @@ bool batch_fusable(const pmf_filter* f, std::string* why) {
     if (m.nx == 2 && m.interp == PMF_INTERP_AUTO && m.A[1] == 0.0 && m.A[2] == 0.0)
         return *why = "diagonal A: separable 2-D regrid", false;
     if (m.nx == 1 && m.interp == PMF_INTERP_LAGRANGE) return *why = "1-D Lagrange regrid", false;
-    if (m.nx == 2 && (m.N[1] / 2) > 128) return *why = "row too long", false;
+    if (m.integrator != PMF_INT_EXACT && m.substeps > FUSED_LMAX) return *why = "more than 64 substeps", false;
+    const int n0 = m.nx == 2 ? m.N[0] : 1, n1 = m.nx == 2 ? m.N[1] : m.N[0];
+    if (group_type(m.nx, n0, n1) < 0)
+        return *why = "grid size without a fused form (2-D: N x N, N in {32,48,64,96,128}; "
+                      "1-D: N in {32,48,64,96,128,192,256})", false;
     return true;
+}
+
+static int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
 }
 
 static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, hipStream_t st) {
@@ -878,7 +1249,6 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     c->nzmax = nzmax;
     std::vector<FConst> consts(n);
     std::vector<BItem> items(n);
-    int maxcplx = 0;
     for (int i = 0; i < n; ++i) {
         pmf_filter* f = filters[i];
         consts[i].m = f->km;
@@ -887,18 +1257,49 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
         b.P[0] = static_cast<float*>(f->buf[0]);
         b.P[1] = static_cast<float*>(f->buf[1]);
         b.d = f->desc;
+        b.coef = f->coef;
         b.idx = i;
         b.nx = f->model.nx;
         b.n0 = f->model.nx == 2 ? f->model.N[0] : 1;
         b.n1 = f->model.nx == 2 ? f->model.N[1] : f->model.N[0];
-        maxcplx = std::max(maxcplx, b.n0 * (b.n1 / 2 + 1));
     }
-    // largest grid first
+    // same-size filters in groups, largest groups' grids first
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return items[a].n0 * items[a].n1 > items[b].n0 * items[b].n1;
+        const long pa = (long)items[a].n0 * items[a].n1, pb = (long)items[b].n0 * items[b].n1;
+        if (pa != pb) return pa > pb;
+        if (items[a].n1 != items[b].n1) return items[a].n1 > items[b].n1;
+        return items[a].nx > items[b].nx;
     });
+    std::vector<BItem> sorted(n);
+    std::vector<GItem> groups;
+    int maxcplx = 0;
+    for (int q = 0; q < n;) {
+        const BItem& b = items[order[q]];
+        const int pitch = b.n1 / 2 + 1;
+        const int type = group_type(b.nx, b.n0, b.n1);
+        const int G = group_capacity(type);
+        GItem gi;
+        gi.first = q;
+        gi.n0 = b.n0;
+        gi.n1 = b.n1;
+        gi.nx = b.nx;
+        gi.seg = std::max(32, pow2_at_least(b.n1));
+        gi.type = type;
+        gi.pad = 0;
+        int cnt = 0;
+        while (q < n && cnt < G && items[order[q]].n0 == b.n0 && items[order[q]].n1 == b.n1 &&
+               items[order[q]].nx == b.nx) {
+            sorted[q] = items[order[q]];
+            ++q;
+            ++cnt;
+        }
+        gi.G = cnt;
+        groups.push_back(gi);
+        maxcplx = std::max(maxcplx, gi.n0 * G * pitch);
+    }
+    c->ngroups = (int)groups.size();
     bool ok = true;
     auto A = [&](size_t bytes) {
         void* p = ctx_alloc(ctx, bytes, st);
@@ -907,24 +1308,24 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     };
     c->d_consts = static_cast<FConst*>(A(sizeof(FConst) * n));
     c->d_items = static_cast<BItem*>(A(sizeof(BItem) * n));
+    c->d_groups = static_cast<GItem*>(A(sizeof(GItem) * groups.size()));
+    c->d_plans = static_cast<FPlan*>(A(sizeof(FPlan) * n));
     c->d_z = static_cast<double*>(A(sizeof(double) * n * nzmax));
     c->d_ll = static_cast<double*>(A(sizeof(double) * n));
     c->d_ctr = static_cast<int*>(A(sizeof(int)));
     if (!ok) return fail(PMF_E_NOMEM, "batch allocation failed");
-    std::vector<BItem> sorted(n);
-    for (int i = 0; i < n; ++i) {
-        sorted[i] = items[order[i]];
-        sorted[i].k = c->d_consts + order[i];
-    }
+    for (int q = 0; q < n; ++q) sorted[q].k = c->d_consts + sorted[q].idx;
     hipError_t e = hipMemcpy(c->d_consts, consts.data(), sizeof(FConst) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_items, sorted.data(), sizeof(BItem) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_groups, groups.data(), sizeof(GItem) * groups.size(), hipMemcpyHostToDevice);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipHostMalloc(reinterpret_cast<void**>(&c->h_z[i]), sizeof(double) * n * nzmax, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
     }
     if (e != hipSuccess) return hip_fail(e, "batch setup");
     c->bufcplx = maxcplx;
-    c->lds = 2 * (size_t)maxcplx * sizeof(float2) + (128 + 256 + 130) * sizeof(float2) + 512 * sizeof(double);
+    c->lds = 2 * (size_t)maxcplx * sizeof(float2) + (128 + 128 + 130) * sizeof(float2);
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_fused), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)c->lds);
     if (e != hipSuccess) return hip_fail(e, "fused kernel LDS attribute");
@@ -935,15 +1336,17 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, ctx->device);
     if (e != hipSuccess) return hip_fail(e, "device properties");
-    c->grid = std::min(n, per_cu * prop.multiProcessorCount);
-    // record the step: reset the work counter, run the fused kernel
+    c->grid = std::min(c->ngroups, per_cu * prop.multiProcessorCount);
+    // the step as a graph: reset the work counter, plan every filter, fused kernel
     hipStream_t cap;
     e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, cap, c->d_ctr);
-        hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, cap, c->d_items, n, c->d_ctr,
-                           c->d_z, nzmax, c->d_ll, c->bufcplx);
+        hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, cap, c->d_items, c->d_plans, n, c->d_z,
+                           nzmax);
+        hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, cap, c->d_groups, c->ngroups,
+                           c->d_items, c->d_plans, c->d_ctr, c->d_z, nzmax, c->d_ll, c->bufcplx);
         e = hipStreamEndCapture(cap, &c->graph);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
@@ -1001,8 +1404,52 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
     std::memcpy(c->h_z[slot], z, sizeof(double) * n * nzmax);
     e = hipMemcpyAsync(c->d_z, c->h_z[slot], sizeof(double) * n * nzmax, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(c->ev[slot], st);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess && ctx->profile) {
+        if ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {
+            for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+                hipEvent_t ev;
+                e = hipEventCreate(&ev);
+                if (e == hipSuccess) ctx->ev_pool.push_back(ev);
+            }
+        }
+        if (e == hipSuccess) {
+            t0 = ctx->ev_pool[2 * ctx->ev_used];
+            t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
+            ctx->ev_used++;
+            ctx->ev_stream = st;
+            e = hipEventRecord(t0, st);
+        }
+    }
     if (e == hipSuccess) e = hipGraphLaunch(c->exec, st);
+    if (e == hipSuccess && t1) e = hipEventRecord(t1, st);
     if (e == hipSuccess && loglik) e = hipMemcpyAsync(loglik, c->d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return PMF_OK;
+}
+
+extern "C" pmf_status pmf_batch_profile(pmf_ctx* ctx, int enable) {
+    using namespace pmf;
+    if (!ctx) return fail(PMF_E_INVALID, "ctx is NULL");
+    ctx->profile = enable != 0;
+    ctx->ev_used = 0;
+    return PMF_OK;
+}
+
+extern "C" pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int* launches) {
+    using namespace pmf;
+    if (!ctx || !total_ms || !launches) return fail(PMF_E_INVALID, "NULL argument");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->ev_stream);
+    double tot = 0.0;
+    for (int i = 0; i < ctx->ev_used && e == hipSuccess; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ctx->ev_pool[2 * i], ctx->ev_pool[2 * i + 1]);
+        tot += ms;
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch kernel time");
+    *total_ms = tot;
+    *launches = ctx->ev_used;
+    ctx->ev_used = 0;
     return PMF_OK;
 }

@@ -224,7 +224,8 @@ struct DevDesc {
     double mass2;
     double h;        // substep length of the last predict
     double etr;      // e^{-tr(A) T} of the last predict
-    double pad[2];
+    double pscale;   // batched steps: the stored density times pscale is the density
+    double pad1;
 };
 
 // Model constants passed to kernels by value.
