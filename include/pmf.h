@@ -198,11 +198,11 @@ pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, doubl
                           const double* z, double* loglik, void* stream);
 
 /* Kernel timing of batched steps: with enable != 0, every later pmf_batch_step
- * records HIP events on its stream around its graph launch (the fused kernel
- * and the work-counter reset).  pmf_batch_kernel_time synchronises the context's
- * last batch stream and returns the summed event time (ms) and the number of
- * launches since the previous call, then clears them.  Diagnostic, for
- * measuring the fused kernel's duration. */
+ * launches the step's kernels directly (instead of replaying its graph) and
+ * records HIP events on its stream right before and after the fused kernel.
+ * pmf_batch_kernel_time synchronises the context's last batch stream and
+ * returns the summed event time (ms) of the fused kernel and the number of
+ * launches since the previous call, then clears them.  Diagnostic. */
 pmf_status pmf_batch_profile(pmf_ctx* ctx, int enable);
 pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int* launches);
 

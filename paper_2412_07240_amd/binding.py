@@ -271,12 +271,21 @@ def pmf_set_state(f, c, M, t, P, grid: int, precision: int) -> None:
     _check(lib().pmf_set_state(f, buf, len(blob)))
 
 
+class FilterArray:
+    """A list of filter handles marshalled once for repeated pmf_batch_step calls."""
+
+    def __init__(self, filters):
+        self.n = len(filters)
+        self.arr = (C.c_void_p * self.n)(*[f.value for f in filters])
+
+
 def pmf_batch_step(ctx, filters, T: float, z, stream=None, want_loglik: bool = False):
-    n = len(filters)
-    arr = (C.c_void_p * n)(*[f.value for f in filters])
+    """filters: a list of handles or a FilterArray (cheaper when called every step)."""
+    fa = filters if isinstance(filters, FilterArray) else FilterArray(filters)
+    n = fa.n
     zz = np.ascontiguousarray(np.asarray(z, float).reshape(n, -1))
     ll = np.full(n, np.nan) if want_loglik else None
-    _check(lib().pmf_batch_step(ctx, arr, n, float(T), zz.ctypes.data_as(C.POINTER(C.c_double)),
+    _check(lib().pmf_batch_step(ctx, fa.arr, n, float(T), zz.ctypes.data_as(C.POINTER(C.c_double)),
                                 ll.ctypes.data_as(C.POINTER(C.c_double)) if want_loglik else None,
                                 _stream(stream)))
     if want_loglik:

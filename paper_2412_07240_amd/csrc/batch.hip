@@ -466,11 +466,14 @@ __device__ __noinline__ float trig_interp_1d(const float* Po, int n, double nu) 
     return (float)acc;
 }
 
+// cubic Lagrange weights through nodes -1, 0, 1, 2 at t in [0, 1)
 __device__ inline void cubic_weights(float t, float* w) {
-    w[0] = -t * (t - 1.f) * (t - 2.f) * (1.f / 6.f);
-    w[1] = (t + 1.f) * (t - 1.f) * (t - 2.f) * 0.5f;
-    w[2] = -(t + 1.f) * t * (t - 2.f) * 0.5f;
-    w[3] = (t + 1.f) * t * (t - 1.f) * (1.f / 6.f);
+    const float tp = t + 1.f, tm = t - 1.f, tm2 = t - 2.f;
+    const float a = t * tm, d = tp * t;
+    w[0] = a * tm2 * (-1.f / 6.f);
+    w[1] = tp * tm * tm2 * 0.5f;
+    w[2] = d * tm2 * -0.5f;
+    w[3] = d * tm * (1.f / 6.f);
 }
 
 // ---------------------------------------------------------------- the fused kernel
@@ -578,6 +581,8 @@ __device__ inline void cseg_sum(double* v, double* slots) {
     constexpr int SW = SEGW < 64 ? SEGW : 64;
     constexpr int TPR = G * SEGW;
     constexpr int RPS = FUSED_THREADS / TPR;
+    constexpr int PER_ROW = TPR / SW, PER_SEG = SEGW / SW;
+    constexpr int NSLOT = FUSED_THREADS / SW;
 #pragma unroll
     for (int q = 0; q < NV; ++q)
 #pragma unroll
@@ -585,19 +590,20 @@ __device__ inline void cseg_sum(double* v, double* slots) {
     if ((threadIdx.x & (SW - 1)) == 0 && (int)threadIdx.x < RPS * TPR)
         for (int q = 0; q < NV; ++q) slots[(threadIdx.x / SW) * 8 + q] = v[q];
     __syncthreads();
-    if ((int)threadIdx.x < G) {
-        const int g = threadIdx.x;
-        constexpr int PER_ROW = TPR / SW, PER_SEG = SEGW / SW;
-        double acc[NV];
-        for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    // one thread per (filter, value) sums that filter's slots in a fixed order
+    double* res = slots + NSLOT * 8;
+    if ((int)threadIdx.x < G * NV) {
+        const int g = threadIdx.x / NV, q = threadIdx.x - g * NV;
+        double acc = 0.0;
+#pragma unroll
         for (int tr = 0; tr < RPS; ++tr)
-            for (int h = 0; h < PER_SEG; ++h) {
-                const int slot = tr * PER_ROW + g * PER_SEG + h;
-                for (int q = 0; q < NV; ++q) acc[q] += slots[slot * 8 + q];
-            }
-        for (int q = 0; q < NV; ++q) v[q] = acc[q];
+#pragma unroll
+            for (int h = 0; h < PER_SEG; ++h) acc += slots[(tr * PER_ROW + g * PER_SEG + h) * 8 + q];
+        res[g * 8 + q] = acc;
     }
     __syncthreads();
+    if ((int)threadIdx.x < G)
+        for (int q = 0; q < NV; ++q) v[q] = res[threadIdx.x * 8 + q];
 }
 
 template <int G, int SEGW>
@@ -729,10 +735,26 @@ __device__ void filter_commit(const FState& F, const BItem& I, double* ll_out) {
     }
 }
 
+// LDS of the fused kernel, at file scope so that the specialised group functions
+// address it as LDS (ds_* instructions) rather than through generic pointers
+extern __shared__ __align__(16) unsigned char pmf_fsm[];
+__shared__ FState pmf_FS[GMAX];
+__shared__ double pmf_slots[32 * 8 + GMAX * 8];
+__shared__ int pmf_item;
+
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) const float cgfloat;
+
 template <int N0, int N1, int NX, int G>
 __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restrict__ items, const FPlan* __restrict__ plans,
-                              const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out, float2* bufA,
-                              float2* bufB, float2* twr, float2* twc, float2* twp, FState* FS, double* slots) {
+                              const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out, int bufcplx) {
+    float2* bufA = reinterpret_cast<float2*>(pmf_fsm);
+    float2* bufB = bufA + bufcplx;
+    float2* twr = bufB + bufcplx;   // 128
+    float2* twc = twr + 128;        // 128
+    float2* twp = twc + 128;        // 130
+    FState* FS = pmf_FS;
+    double* slots = pmf_slots;
     constexpr int H1 = N1 / 2, PITCH = H1 + 1, SPITCH = G * PITCH, RP = 2 * PITCH, RS = G * RP;
     constexpr int SEGW = pow2_ceil(N1) < 32 ? 32 : pow2_ceil(N1);
     constexpr int TPR = G * SEGW, RPS = FUSED_THREADS / TPR;
@@ -771,7 +793,11 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
         const int L = e / H1, k = e - L * H1;
         const int r = L / G, g = L - r * G;
         float2 v = make_float2(0.f, 0.f);
-        if (g < Gact) v = f2scale(reinterpret_cast<const float2*>(FS[g].pin)[r * H1 + k], (float)FS[g].p.pscale);
+        if (g < Gact) {
+            cgfloat* src = (cgfloat*)FS[g].pin + 2 * (r * H1 + k);
+            const float sc = (float)FS[g].p.pscale;
+            v = make_float2(src[0] * sc, src[1] * sc);
+        }
         bufA[L * PITCH + k] = v;
     }
     __syncthreads();
@@ -795,59 +821,61 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
         cur = cfft<N0, SPITCH, 1, SPITCH, -1, true>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
-    // ---- per-mode gain with 1/(N0 N1) of the unnormalised transforms
+    // ---- per-mode gain with 1/(N0 N1) of the unnormalised transforms; a thread
+    // owns spectral column c (filter g, frequency s1) and walks its rows
     {
         constexpr float inv = 1.0f / ((float)N0 * (float)N1);
-#pragma unroll 1
-        for (int e = tid; e < N0 * SPITCH; e += NT) {
-            const int s0 = e / SPITCH, c = e - s0 * SPITCH;
-            const int g = c / PITCH, s1 = c - g * PITCH;
+        constexpr int CPS = NT / SPITCH;   // rows walked in parallel per column
+        const int cth = tid % SPITCH, r0 = tid / SPITCH;
+        if (r0 < CPS) {
+            const int g = cth / PITCH, s1 = cth - g * PITCH;
             const FPlan& P = FS[g].p;
-            float a1, a2, b1 = 0.f, b2 = 0.f;   // axis 0 (a), axis 1 (b)
-            {
-                const int kk = (s1 < H1) ? s1 : s1 - N1;
-                const float kap = (6.283185307179586f / N1) * kk;
-                b2 = kap * kap;
-                b1 = (s1 == H1) ? 0.f : kap;
-            }
-            if constexpr (NX == 2) {
-                const int kk = (s0 < N0 / 2) ? s0 : s0 - N0;
-                const float kap = (6.283185307179586f / N0) * kk;
-                a2 = kap * kap;
-                a1 = (2 * s0 == N0) ? 0.f : kap;
-            } else {
-                a1 = b1;
-                a2 = b2;
-                b1 = b2 = 0.f;
-            }
-            float g2;
-            if (P.integ == PMF_INT_EXACT) {
-                const float sig = (float)P.gc[0] * a2 + (float)P.gc[1] * b2 + 2.f * (float)P.gc[2] * a1 * b1;
-                g2 = __expf(-0.5f * sig);
-            } else {
-                const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
-                const float hh = (float)P.h;
-                g2 = 1.f;
-                if (P.integ == PMF_INT_EULER) {
-                    for (int q = 0; q < P.l; ++q) {
-                        const float sig = (float)cf[3 * q] * a2 + (float)cf[3 * q + 1] * b2 +
-                                          2.f * (float)cf[3 * q + 2] * a1 * b1;
-                        g2 = g2 / (1.f + 0.5f * hh * sig);
-                    }
+            const int kk1 = (s1 < H1) ? s1 : s1 - N1;
+            const float kap1 = (6.283185307179586f / N1) * kk1;
+            const float b2 = (NX == 2) ? kap1 * kap1 : 0.f;
+            const float b1 = (NX == 2) ? ((s1 == H1) ? 0.f : kap1) : 0.f;
+            const float scale = (float)P.etr * inv;
+            const float p0 = (float)P.gc[0], p1 = (float)P.gc[1], p2 = (float)P.gc[2];
+            const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
+            for (int s0 = r0; s0 < N0; s0 += CPS) {
+                float a1, a2;
+                if constexpr (NX == 2) {
+                    const int kk = (s0 < N0 / 2) ? s0 : s0 - N0;
+                    const float kap = (6.283185307179586f / N0) * kk;
+                    a2 = kap * kap;
+                    a1 = (2 * s0 == N0) ? 0.f : kap;
                 } else {
-                    for (int q = 0; q < P.l; ++q) {
-                        const double* c3 = cf + 6 * q;
-                        const float la = -0.5f * ((float)c3[0] * a2 + (float)c3[1] * b2 + 2.f * (float)c3[2] * a1 * b1);
-                        const float lb = -0.5f * ((float)c3[3] * a2 + (float)c3[4] * b2 + 2.f * (float)c3[5] * a1 * b1);
-                        const float lc = -0.5f * ((float)c3[6] * a2 + (float)c3[7] * b2 + 2.f * (float)c3[8] * a1 * b1);
-                        const float y2 = 1.f + 0.5f * hh * la;
-                        const float y3 = 1.f + 0.5f * hh * lb * y2;
-                        const float y4 = 1.f + hh * lb * y3;
-                        g2 *= 1.f + hh / 6.f * (la + 2.f * lb * y2 + 2.f * lb * y3 + lc * y4);
+                    a2 = kap1 * kap1;
+                    a1 = (s1 == H1) ? 0.f : kap1;
+                }
+                float g2;
+                if (P.integ == PMF_INT_EXACT) {
+                    g2 = __expf(-0.5f * (p0 * a2 + p1 * b2) - p2 * a1 * b1);
+                } else {
+                    const float hh = (float)P.h;
+                    g2 = 1.f;
+                    if (P.integ == PMF_INT_EULER) {
+                        for (int q = 0; q < P.l; ++q) {
+                            const float sig = (float)cf[3 * q] * a2 + (float)cf[3 * q + 1] * b2 +
+                                              2.f * (float)cf[3 * q + 2] * a1 * b1;
+                            g2 = g2 / (1.f + 0.5f * hh * sig);
+                        }
+                    } else {
+                        for (int q = 0; q < P.l; ++q) {
+                            const double* c3 = cf + 6 * q;
+                            const float la = -0.5f * ((float)c3[0] * a2 + (float)c3[1] * b2 + 2.f * (float)c3[2] * a1 * b1);
+                            const float lb = -0.5f * ((float)c3[3] * a2 + (float)c3[4] * b2 + 2.f * (float)c3[5] * a1 * b1);
+                            const float lc = -0.5f * ((float)c3[6] * a2 + (float)c3[7] * b2 + 2.f * (float)c3[8] * a1 * b1);
+                            const float y2 = 1.f + 0.5f * hh * la;
+                            const float y3 = 1.f + 0.5f * hh * lb * y2;
+                            const float y4 = 1.f + hh * lb * y3;
+                            g2 *= 1.f + hh / 6.f * (la + 2.f * lb * y2 + 2.f * lb * y3 + lc * y4);
+                        }
                     }
                 }
+                float2* x = cur + s0 * SPITCH + cth;
+                *x = f2scale(*x, g2 * scale);
             }
-            cur[s0 * SPITCH + c] = f2scale(cur[s0 * SPITCH + c], g2 * (float)P.etr * inv);
         }
     }
     __syncthreads();
@@ -896,9 +924,11 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
         ga = -0.5 * Pg.qQ[0];
     }
     double mx = -INFINITY;
+    const double u0first = (NX == 2) ? (double)tr - half0 : uj;
+    constexpr double du0 = (NX == 2) ? (double)RPS : 0.0;
     if (act) {
-        for (int r = tr; r < N0; r += RPS) {
-            const double u0 = (NX == 2) ? (double)r - half0 : uj;
+        double u0 = u0first;
+        for (int r = tr; r < N0; r += RPS, u0 += du0) {
             const double L = Pg.fast ? al + u0 * (be + ga * u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
             mx = fmax(mx, L);
         }
@@ -909,18 +939,25 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     double acc[4] = {0, 0, 0, 0};   // sum w, sum w u0, sum w u0^2, boundary
     if (act) {
         const double sh = FS[g].s;
-        for (int r = tr; r < N0; r += RPS) {
-            const double u0 = (NX == 2) ? (double)r - half0 : uj;
+        const bool jedge = (j == 0 || j == N1 - 1);
+        double u0 = u0first;
+        const float* pr = Pr + tr * RS + g * RP + j;
+        float* po = Po + tr * RS + g * RP + j;
+#pragma unroll 2
+        for (int r = tr; r < N0; r += RPS, u0 += du0, pr += RPS * RS, po += RPS * RS) {
             const double L = Pg.fast ? al + u0 * (be + ga * u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
-            const int idx = r * RS + g * RP + j;
-            const float v = Pr[idx] * __expf((float)(L - sh));
-            Po[idx] = v;
+            const float v = *pr * __expf((float)(L - sh));
+            *po = v;
             const double w = (double)v;
             acc[0] += w;
             acc[1] += w * u0;
             acc[2] += w * u0 * u0;
-            const bool edge = (NX == 2) ? (r == 0 || r == N0 - 1 || j == 0 || j == N1 - 1) : (j == 0 || j == N1 - 1);
-            if (edge) acc[3] += w;
+            if (jedge) acc[3] += w;
+        }
+        if (NX == 2 && !jedge) {
+            // rows 0 and N0-1 are on the boundary too
+            if (tr == 0) acc[3] += (double)Po[g * RP + j];
+            if ((N0 - 1) % RPS == tr) acc[3] += (double)Po[(N0 - 1) * RS + g * RP + j];
         }
     }
     // per-thread sums -> the seven moment sums (u1 is constant per thread in 2-D)
@@ -952,44 +989,59 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     double macc[1] = {0.0};
     if (act && FS[g].ok) {
         const FState& F = FS[g];
-        float* Pout = F.pout;
+        gfloat* Pout = (gfloat*)F.pout;
         const float* Pog = Po + g * RP;
         const float inv_mass = (float)F.inv_mass;
-        for (int r = tr; r < N0; r += RPS) {
-            float val = 0.f;
-            if constexpr (NX == 2) {
-                const double u0 = (double)r - half0;
-                const double nu0 = F.amap[0] * u0 + F.amap[1] * uj + F.bmap[0];
-                const double nu1 = F.amap[2] * u0 + F.amap[3] * uj + F.bmap[1];
+        if constexpr (NX == 2) {
+            // old index coordinates of new node (r, j), advanced by RPS rows per step
+            double nu0 = F.amap[0] * ((double)tr - half0) + F.amap[1] * uj + F.bmap[0];
+            double nu1 = F.amap[2] * ((double)tr - half0) + F.amap[3] * uj + F.bmap[1];
+            const double dn0 = F.amap[0] * RPS, dn1 = F.amap[2] * RPS;
+#pragma unroll 2
+            for (int r = tr; r < N0; r += RPS, nu0 += dn0, nu1 += dn1) {
+                float val = 0.f;
                 if (nu0 >= 0.0 && nu0 <= (double)(N0 - 1) && nu1 >= 0.0 && nu1 <= (double)(N1 - 1)) {
                     const int i0 = (int)nu0, i1 = (int)nu1;   // floor: nu >= 0
                     float w0[4], w1[4];
                     cubic_weights((float)(nu0 - i0), w0);
                     cubic_weights((float)(nu1 - i1), w1);
-                    int ra[4], cb[4];
+                    if (i0 >= 1 && i0 <= N0 - 3 && i1 >= 1 && i1 <= N1 - 3) {
+                        // interior: the 4 x 4 stencil at constant offsets from one base
+                        const float* p = Pog + (i0 - 1) * RS + (i1 - 1);
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const int rr = i0 - 1 + a, cc = i1 - 1 + a;
-                        const bool okr = rr >= 0 && rr < N0, okc = cc >= 0 && cc < N1;
-                        ra[a] = okr ? rr : i0;
-                        cb[a] = okc ? cc : i1;
-                        if (!okr) w0[a] = 0.f;
-                        if (!okc) w1[a] = 0.f;
-                    }
+                        for (int a = 0; a < 4; ++a) {
+                            const float* row = p + a * RS;
+                            val += w0[a] * (w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3]);
+                        }
+                    } else {
+                        int ra[4], cb[4];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const float* row = Pog + ra[a] * RS;
-                        const float rsum = w1[0] * row[cb[0]] + w1[1] * row[cb[1]] + w1[2] * row[cb[2]] +
-                                           w1[3] * row[cb[3]];
-                        val += w0[a] * rsum;
+                        for (int a = 0; a < 4; ++a) {
+                            const int rr = i0 - 1 + a, cc = i1 - 1 + a;
+                            const bool okr = rr >= 0 && rr < N0, okc = cc >= 0 && cc < N1;
+                            ra[a] = okr ? rr : i0;
+                            cb[a] = okc ? cc : i1;
+                            if (!okr) w0[a] = 0.f;
+                            if (!okc) w1[a] = 0.f;
+                        }
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            const float* row = Pog + ra[a] * RS;
+                            val += w0[a] * (w1[0] * row[cb[0]] + w1[1] * row[cb[1]] + w1[2] * row[cb[2]] +
+                                            w1[3] * row[cb[3]]);
+                        }
                     }
                 }
-            } else {
-                const double nu = F.amap[0] * uj + F.bmap[0];
-                if (nu >= 0.0 && nu <= (double)(N1 - 1)) val = trig_interp_1d(Pog, N1, nu);
+                val *= inv_mass;
+                Pout[r * N1 + j] = val;
+                macc[0] += (double)val;
             }
+        } else {
+            const double nu = F.amap[0] * uj + F.bmap[0];
+            float val = 0.f;
+            if (nu >= 0.0 && nu <= (double)(N1 - 1)) val = trig_interp_1d(Pog, N1, nu);
             val *= inv_mass;
-            Pout[r * N1 + j] = val;
+            Pout[j] = val;
             macc[0] += (double)val;
         }
     }
@@ -1005,7 +1057,7 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     __syncthreads();
     // ---- rejected updates keep the predicted density and the moved grid
     if (act && !FS[g].ok) {
-        float* Pout = FS[g].pout;
+        gfloat* Pout = (gfloat*)FS[g].pout;
         for (int r = tr; r < N0; r += RPS) Pout[r * N1 + j] = Pr[r * RS + g * RP + j];
     }
     if (tid < Gact) filter_commit(FS[tid], items[GI.first + tid], ll_out);
@@ -1031,24 +1083,15 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__ items,
         const FPlan* __restrict__ plans, int* ctr, const double* __restrict__ zall, int nzmax,
         double* __restrict__ ll_out, int bufcplx) {
-    extern __shared__ __align__(16) unsigned char fsm[];
-    __shared__ FState FS[GMAX];
-    __shared__ double slots[32 * 8];
-    __shared__ int item_sh;
-    float2* bufA = reinterpret_cast<float2*>(fsm);
-    float2* bufB = bufA + bufcplx;
-    float2* twr = bufB + bufcplx;   // 128
-    float2* twc = twr + 128;        // 128
-    float2* twp = twc + 128;        // 130
     for (;;) {
-        if (threadIdx.x == 0) item_sh = atomicAdd(ctr, 1);
+        if (threadIdx.x == 0) pmf_item = atomicAdd(ctr, 1);
         __syncthreads();
-        const int it = item_sh;
+        const int it = pmf_item;
         __syncthreads();
         if (it >= ngroups) break;
         const GItem GI = groups[it];
 #define PMF_GROUP(T, N0, N1, NX) \
-    case T: process_group<N0, N1, NX, group_g<N0, N1>()>(GI, items, plans, zall, nzmax, ll_out, bufA, bufB, twr, twc, twp, FS, slots); break;
+    case T: process_group<N0, N1, NX, group_g<N0, N1>()>(GI, items, plans, zall, nzmax, ll_out, bufcplx); break;
         switch (GI.type) {
             PMF_GROUP(GT_2D_128, 128, 128, 2)
             PMF_GROUP(GT_2D_96, 96, 96, 2)
@@ -1404,8 +1447,8 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
     std::memcpy(c->h_z[slot], z, sizeof(double) * n * nzmax);
     e = hipMemcpyAsync(c->d_z, c->h_z[slot], sizeof(double) * n * nzmax, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(c->ev[slot], st);
-    hipEvent_t t0 = nullptr, t1 = nullptr;
     if (e == hipSuccess && ctx->profile) {
+        // same kernels as the graph, launched directly with events around the fused one
         if ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {
             for (int q = 0; q < 2 && e == hipSuccess; ++q) {
                 hipEvent_t ev;
@@ -1414,15 +1457,25 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             }
         }
         if (e == hipSuccess) {
-            t0 = ctx->ev_pool[2 * ctx->ev_used];
-            t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
+            hipEvent_t t0 = ctx->ev_pool[2 * ctx->ev_used];
+            hipEvent_t t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
             ctx->ev_used++;
             ctx->ev_stream = st;
+            hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, c->d_ctr);
+            hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, c->d_items, c->d_plans, n,
+                               c->d_z, c->nzmax);
             e = hipEventRecord(t0, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups,
+                                   c->ngroups, c->d_items, c->d_plans, c->d_ctr, c->d_z, c->nzmax, c->d_ll,
+                                   c->bufcplx);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipEventRecord(t1, st);
         }
+    } else if (e == hipSuccess) {
+        e = hipGraphLaunch(c->exec, st);
     }
-    if (e == hipSuccess) e = hipGraphLaunch(c->exec, st);
-    if (e == hipSuccess && t1) e = hipEventRecord(t1, st);
     if (e == hipSuccess && loglik) e = hipMemcpyAsync(loglik, c->d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return PMF_OK;
