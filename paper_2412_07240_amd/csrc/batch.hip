@@ -268,8 +268,11 @@ __device__ double seg_max(double v, const Seg& s, double* slots, int G) {
 
 // ---------------------------------------------------------------- planning (one thread per filter)
 
-__device__ void plan_one(const BItem& I, const double* z, FPlan& P) {
-    const PredictArgs& a = I.k->pa;
+__device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Pout) {
+    // built in registers and stored once: loads of the constants can all be
+    // issued up front (no interleaved stores that could alias them)
+    FPlan P;
+    const PredictArgs a = I.k->pa;
     const KModel& m = I.k->m;
     const DevDesc* d = I.d;
     const int n = a.nx;
@@ -398,6 +401,7 @@ __device__ void plan_one(const BItem& I, const double* z, FPlan& P) {
         P.qQ[1] = Qf[3];
         P.qQ[2] = Qf[1];
     }
+    Pout = P;
 }
 
 __global__ void k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
