@@ -38,11 +38,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# sources the fused batched kernel is compiled from: a traffic figure measured on
+# another version of them is stale and not reported
+FUSED_SOURCES = ("paper_2412_07240_amd/csrc/batch.hip", "paper_2412_07240_amd/csrc/api_internal.h",
+                 "paper_2412_07240_amd/csrc/pmf_internal.h", "include/pmf.h")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2412_07240_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
+    for f in FUSED_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -82,8 +87,14 @@ def cpu_baseline(seconds: float, nfilters: int):
     wall = time.perf_counter() - t0
     pts = sum(r[0] for r in res)
     busy = max(r[1] for r in res)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": pts / busy if busy > 0 else None, "unit": "grid-point updates/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": model, "nproc": os.cpu_count(),
             "sample": f"FP64 oracle predict+update cycles of the batched workload's filters "
                       f"(same N mix), {cores} processes x 1 BLAS thread, ~{seconds:.0f} s each; "
                       f"{pts} points in {busy:.1f} s busy ({wall:.1f} s wall incl. start-up)"}

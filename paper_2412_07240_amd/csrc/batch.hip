@@ -268,39 +268,64 @@ __device__ double seg_max(double v, const Seg& s, double* slots, int G) {
 
 // ---------------------------------------------------------------- planning (one thread per filter)
 
+// RK4 substep clamp on the moved grid (rarely used in batched steps: out of line)
+__device__ __noinline__ int plan_substeps(const PredictArgs& a, const double* Mi, int n, int l) {
+    double lam = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        double E[9], t1[9], Dy[9];
+        if (q == 0) {
+            mat_copy(E, a.D);
+        } else {
+            const double* Eq = (q == 1) ? a.emh : a.emT;
+            mat_mul(t1, Eq, a.D, n);
+            mat_mul_bt(E, t1, Eq, n);
+        }
+        sandwich_inv(Dy, Mi, E, n);
+        double lb = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) lb += fabs(Dy[i * 3 + j]) * a.rho[i] * a.rho[j];
+        lam = fmax(lam, 0.5 * lb);
+    }
+    const double need = ceil(a.T * lam / RK4_STABLE_STEP);
+    if (need > (double)l) l = need > (double)FUSED_LMAX ? FUSED_LMAX + 1 : (int)need;
+    return l;
+}
+
+// D_y at the RK4 stage times / Euler substep starts, packed 00, 11, 01
+__device__ __noinline__ void plan_stage_coefs(const PredictArgs& a, const double* Mi, int n, int l, double h,
+                                              double* coef) {
+    const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
+    const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
+    double Estep[9], Ek[9], t1[9], E[9], Dy[9], nxt[9];
+    expm3(Estep, a.A, -dt, n);
+    mat_eye(Ek, n);
+    for (int k = 0; k < cnt; ++k) {
+        mat_mul(t1, Ek, a.D, n);
+        mat_mul_bt(E, t1, Ek, n);
+        sandwich_inv(Dy, Mi, E, n);
+        coef[3 * k + 0] = Dy[0];
+        coef[3 * k + 1] = Dy[4];
+        coef[3 * k + 2] = Dy[1];
+        mat_mul(nxt, Ek, Estep, n);
+        mat_copy(Ek, nxt);
+    }
+}
+
+template <int NX>
 __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Pout) {
     // built in registers and stored once: loads of the constants can all be
     // issued up front (no interleaved stores that could alias them)
     FPlan P;
-    const PredictArgs a = I.k->pa;
+    const PredictArgs& a = I.k->pa;
     const KModel& m = I.k->m;
     const DevDesc* d = I.d;
-    const int n = a.nx;
+    constexpr int n = NX;   // compile-time: the small matrix loops unroll into registers
     Grid g = d->g;
     double Mi[9];
     mat_copy(Mi, g.Mi);
     int l = a.lmin;
     P.bad = 0;
-    if (a.integ == PMF_INT_RK4 && a.T > 0.0) {
-        double lam = 0.0;
-        for (int q = 0; q < 3; ++q) {
-            double E[9], t1[9], Dy[9];
-            if (q == 0) {
-                mat_copy(E, a.D);
-            } else {
-                const double* Eq = (q == 1) ? a.emh : a.emT;
-                mat_mul(t1, Eq, a.D, n);
-                mat_mul_bt(E, t1, Eq, n);
-            }
-            sandwich_inv(Dy, Mi, E, n);
-            double lb = 0.0;
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j) lb += fabs(Dy[i * 3 + j]) * a.rho[i] * a.rho[j];
-            lam = fmax(lam, 0.5 * lb);
-        }
-        const double need = ceil(a.T * lam / RK4_STABLE_STEP);
-        if (need > (double)l) l = need > (double)FUSED_LMAX ? FUSED_LMAX + 1 : (int)need;
-    }
+    if (a.integ == PMF_INT_RK4 && a.T > 0.0) l = plan_substeps(a, Mi, n, l);
     if (l > FUSED_LMAX) {
         l = FUSED_LMAX;
         P.bad = 1;
@@ -313,21 +338,7 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
         P.gc[1] = Wy[4];
         P.gc[2] = Wy[1];
     } else {
-        const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
-        const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
-        double Estep[9], Ek[9], t1[9], E[9], Dy[9], nxt[9];
-        expm3(Estep, a.A, -dt, n);
-        mat_eye(Ek, n);
-        for (int k = 0; k < cnt; ++k) {
-            mat_mul(t1, Ek, a.D, n);
-            mat_mul_bt(E, t1, Ek, n);
-            sandwich_inv(Dy, Mi, E, n);
-            I.coef[3 * k + 0] = Dy[0];
-            I.coef[3 * k + 1] = Dy[4];
-            I.coef[3 * k + 2] = Dy[1];
-            mat_mul(nxt, Ek, Estep, n);
-            mat_copy(Ek, nxt);
-        }
+        plan_stage_coefs(a, Mi, n, l, h, I.coef);
     }
     P.l = l;
     P.h = h;
@@ -404,17 +415,20 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     Pout = P;
 }
 
+// one thread per filter; thread 0 also clears the work counter of the fused launch
 __global__ void k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
-                             const double* __restrict__ zall, int nzmax) {
+                             const double* __restrict__ zall, int nzmax, int* __restrict__ ctr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *ctr = 0;
     if (i >= n) return;
-    const BItem I = items[i];
-    plan_one(I, zall + (size_t)I.idx * nzmax, plans[i]);
+    const BItem& I = items[i];
+    const double* z = zall + (size_t)I.idx * nzmax;
+    if (I.nx == 2)
+        plan_one<2>(I, z, plans[i]);
+    else
+        plan_one<1>(I, z, plans[i]);
 }
 
-__global__ void k_batch_reset(int* ctr) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = 0;
-}
 
 // general measurement models: log p(z | x) at index coordinates u (FP64)
 __device__ __noinline__ double floglik_general(const KModel& m, const FPlan& P, double u0, double u1,
@@ -1384,14 +1398,13 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     e = hipGetDeviceProperties(&prop, ctx->device);
     if (e != hipSuccess) return hip_fail(e, "device properties");
     c->grid = std::min(c->ngroups, per_cu * prop.multiProcessorCount);
-    // the step as a graph: reset the work counter, plan every filter, fused kernel
+    // the step as a graph: plan every filter (and clear the work counter), fused kernel
     hipStream_t cap;
     e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, cap, c->d_ctr);
         hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, cap, c->d_items, c->d_plans, n, c->d_z,
-                           nzmax);
+                           nzmax, c->d_ctr);
         hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, cap, c->d_groups, c->ngroups,
                            c->d_items, c->d_plans, c->d_ctr, c->d_z, nzmax, c->d_ll, c->bufcplx);
         e = hipStreamEndCapture(cap, &c->graph);
@@ -1465,9 +1478,8 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             hipEvent_t t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
             ctx->ev_used++;
             ctx->ev_stream = st;
-            hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, c->d_ctr);
             hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, c->d_items, c->d_plans, n,
-                               c->d_z, c->nzmax);
+                               c->d_z, c->nzmax, c->d_ctr);
             e = hipEventRecord(t0, st);
             if (e == hipSuccess) {
                 hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups,

@@ -186,7 +186,10 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
 }
 
 // ------------------------------------------------------------------ predict planning
-// One thread: substep count, per-stage diffusion in index coordinates, grid move.
+// Substep count, per-stage diffusion in index coordinates, grid move.  Thread 0
+// takes the substep decision and the powers E^(2^j) of the stage propagator
+// E = e^{-A dt}; the stage sets k = 0..cnt-1 are then built in parallel from
+// E^k = prod over the set bits of k (powers of one matrix commute).
 
 __device__ double lambda_bound_dev(const double* Dy, const double* rho, int n) {
     double s = 0.0;
@@ -195,65 +198,89 @@ __device__ double lambda_bound_dev(const double* Dy, const double* rho, int n) {
     return 0.5 * s;
 }
 
-__global__ void k_plan(PredictArgs a, DevDesc* d, double* coef) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int n = a.nx;
+constexpr int PLAN_THREADS = 256;
+constexpr int PLAN_POW = 14;   // 2 LMAX + 1 < 2^14
+
+template <int NX>
+__global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d, double* coef) {
+    constexpr int n = NX;
+    __shared__ double pw[PLAN_POW][9];
+    __shared__ int s_l;
     double Mi[9];
     mat_copy(Mi, d->g.Mi);
-    int l = a.lmin;
-    if (a.integ == PMF_INT_RK4 && a.T > 0.0) {
-        double lam = 0.0;
-        const double* Es[3] = {nullptr, a.emh, a.emT};
-        for (int q = 0; q < 3; ++q) {
-            double E[9], t1[9], Dy[9];
-            if (q == 0) {
-                mat_copy(E, a.D);
-            } else {
-                mat_mul(t1, Es[q], a.D, n);
-                mat_mul_bt(E, t1, Es[q], n);
+    if (threadIdx.x == 0) {
+        int l = a.lmin;
+        if (a.integ == PMF_INT_RK4 && a.T > 0.0) {
+            double lam = 0.0;
+            const double* Es[3] = {nullptr, a.emh, a.emT};
+            for (int q = 0; q < 3; ++q) {
+                double E[9], t1[9], Dy[9];
+                if (q == 0) {
+                    mat_copy(E, a.D);
+                } else {
+                    mat_mul(t1, Es[q], a.D, n);
+                    mat_mul_bt(E, t1, Es[q], n);
+                }
+                sandwich_inv(Dy, Mi, E, n);
+                const double lb = lambda_bound_dev(Dy, a.rho, n);
+                lam = lb > lam ? lb : lam;
             }
-            sandwich_inv(Dy, Mi, E, n);
-            const double lb = lambda_bound_dev(Dy, a.rho, n);
-            lam = lb > lam ? lb : lam;
+            const double need = ceil(a.T * lam / RK4_STABLE_STEP);
+            if (need > (double)l) l = need > (double)a.lmax ? a.lmax + 1 : (int)need;
         }
-        const double need = ceil(a.T * lam / RK4_STABLE_STEP);
-        if (need > (double)l) l = need > (double)a.lmax ? a.lmax + 1 : (int)need;
+        if (l > a.lmax) {
+            l = a.lmax;
+            d->status |= PMF_E_INVALID;   // substep limit reached: result is not trustworthy
+        }
+        s_l = l;
+        const double h = a.T / l;
+        if (a.integ == PMF_INT_EXACT) {
+            double Wy[9];
+            sandwich_inv(Wy, Mi, a.W, n);
+            pack_sym(coef, Wy);
+        } else {
+            const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
+            double E[9];
+            expm3(E, a.A, -dt, n);
+            for (int i = 0; i < 9; ++i) pw[0][i] = E[i];
+            for (int j = 1; j < PLAN_POW; ++j) {
+                double sq[9];
+                mat_mul(sq, pw[j - 1], pw[j - 1], n);
+                for (int i = 0; i < 9; ++i) pw[j][i] = sq[i];
+            }
+        }
+        d->l = l;
+        d->h = h;
+        d->etr = a.etr;
     }
-    if (l > a.lmax) {
-        l = a.lmax;
-        d->status |= PMF_E_INVALID;   // substep limit reached: result is not trustworthy
-    }
-    const double h = a.T / l;
-    if (a.integ == PMF_INT_EXACT) {
-        double Wy[9];
-        sandwich_inv(Wy, Mi, a.W, n);
-        pack_sym(coef, Wy);
-    } else {
+    __syncthreads();
+    if (a.integ != PMF_INT_EXACT) {
+        const int l = s_l;
         const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
-        const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
-        double Estep[9], Ek[9], t1[9], E[9], Dy[9], nxt[9];
-        expm3(Estep, a.A, -dt, n);
-        mat_eye(Ek, n);
-        for (int k = 0; k < cnt; ++k) {
+        for (int k = threadIdx.x; k < cnt; k += PLAN_THREADS) {
+            double Ek[9], nxt[9], t1[9], E[9], Dy[9];
+            mat_eye(Ek, n);
+            for (int j = 0; j < PLAN_POW; ++j)
+                if ((k >> j) & 1) {
+                    mat_mul(nxt, Ek, pw[j], n);
+                    mat_copy(Ek, nxt);
+                }
             mat_mul(t1, Ek, a.D, n);
             mat_mul_bt(E, t1, Ek, n);
             sandwich_inv(Dy, Mi, E, n);
             pack_sym(coef + 6 * k, Dy);
-            mat_mul(nxt, Ek, Estep, n);
-            mat_copy(Ek, nxt);
         }
     }
-    d->l = l;
-    d->h = h;
-    d->etr = a.etr;
-    // grid follows x' = A x over T
-    double c2[3], M2[9];
-    mat_vec(c2, a.Phi, d->g.c, n);
-    mat_mul(M2, a.Phi, d->g.M, n);
-    for (int i = 0; i < n; ++i) d->g.c[i] = c2[i];
-    mat_copy(d->g.M, M2);
-    grid_finish(d->g, n);
-    d->t += a.T;
+    if (threadIdx.x == 0) {
+        // grid follows x' = A x over T
+        double c2[3], M2[9];
+        mat_vec(c2, a.Phi, d->g.c, n);
+        mat_mul(M2, a.Phi, d->g.M, n);
+        for (int i = 0; i < n; ++i) d->g.c[i] = c2[i];
+        mat_copy(d->g.M, M2);
+        grid_finish(d->g, n);
+        d->t += a.T;
+    }
 }
 
 // ------------------------------------------------------------------ spectral gain
@@ -939,7 +966,12 @@ hipError_t launch_predict_fourier(const KModel& m, DevDesc* d, const double* coe
 }
 
 hipError_t launch_plan(const PredictArgs& a, DevDesc* d, double* coef, hipStream_t st) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, a, d, coef);
+    if (a.nx == 1)
+        hipLaunchKernelGGL(k_plan<1>, dim3(1), dim3(PLAN_THREADS), 0, st, a, d, coef);
+    else if (a.nx == 2)
+        hipLaunchKernelGGL(k_plan<2>, dim3(1), dim3(PLAN_THREADS), 0, st, a, d, coef);
+    else
+        hipLaunchKernelGGL(k_plan<3>, dim3(1), dim3(PLAN_THREADS), 0, st, a, d, coef);
     return hipGetLastError();
 }
 
