@@ -113,13 +113,21 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip latency / L1 / plain-path legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain device copy of known size (counter scaling)")
+    ap.add_argument("--workload", choices=("batched", "cheb3d"), default="batched",
+                    help="batched: the headline batched workload (default); cheb3d: one 3-D "
+                         "Chebyshev filter on a 64^3 grid (RK4 on MFMA, range measurement)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(independent filters would be partitioned across processes); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "cheb3d":
+        return run_cheb3d(args)
+    return run_batched(args)
 
+
+def run_batched(args):
     import numpy as np
     import torch
     import workloads as W
@@ -261,6 +269,127 @@ def main():
     if not args.no_cpu:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, nf)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ 3-D Chebyshev
+
+MFMA_FP32_PEAK_TFLOPS = 157.3
+CHEB_PRODUCTS_PER_STAGE = 7   # line products per RK4 stage in 3-D
+
+
+def _cheb_cpu_worker(args):
+    N, frac = args
+    from threadpoolctl import threadpool_limits
+    import oracle
+    import workloads as W
+    sc = W.config3(K=1, N=N, precision=W.FP64)
+    m = sc.model
+    st = oracle.create(m, sc.prior)
+    l_full = oracle.substeps(m, st, sc.T)
+    Ts = sc.T * frac
+    t0 = time.perf_counter()
+    st2, l = oracle.predict(m, st, Ts)
+    tp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.update(m, st2, sc.z[0])
+    tu = time.perf_counter() - t0
+    return l_full, l, tp, tu
+
+
+def cheb_cpu_baseline(N: int, frac: float):
+    """The oracle on a bounded sample of one cycle: a predict over a fraction of
+    the interval (its substeps cost the same each) and one full update; the cycle
+    time is the sample's predict time scaled to the full substep count plus the
+    update time.  Multi-threaded BLAS on all host cores, as the oracle runs."""
+    l_full, l, tp, tu = _cheb_cpu_worker((N, frac))
+    cycle = tp * l_full / max(l, 1) + tu
+    cores = os.cpu_count() or 1
+    return {"value": N ** 3 / cycle, "unit": "grid-point updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, one {N}^3 predict over {frac:.2f} T ({l} of {l_full} substeps, "
+                      f"{tp:.1f} s) scaled to the full interval, plus one update ({tu:.1f} s); "
+                      f"NumPy BLAS on {cores} host threads"}
+
+
+def run_cheb3d(args):
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2412_07240_amd import binding as B
+
+    N = 64
+    K = args.warmup + args.steps + 2
+    sc = W.config3(K=K, N=N, precision=W.FP32)
+    pts = N ** 3
+    ctx = B.pmf_ctx_create(0)
+    f = B.pmf_create(ctx, sc.model, sc.prior)
+    log(f"bench cheb3d: warmup {args.warmup} cycles")
+    k = 0
+    for _ in range(args.warmup):
+        B.pmf_predict(f, sc.T)
+        B.pmf_update(f, sc.z[k])
+        k += 1
+    B.pmf_stream_sync()
+    torch.cuda.synchronize()
+    # predict duration from HIP events on the stream the passes run on (the null
+    # stream, which is also torch's default stream here)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    subs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        B.pmf_predict(f, sc.T)
+        ev[i][1].record()
+        subs.append(B.pmf_last_substeps(f))
+        B.pmf_update(f, sc.z[k])
+        k += 1
+    B.pmf_stream_sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pred_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = pts * args.steps / elapsed
+    lsum = sum(subs)
+    flops = 4.0 * lsum * CHEB_PRODUCTS_PER_STAGE * 2.0 * N * pts
+    achieved = flops / (sum(pred_ms) * 1e-3) / 1e12
+    log(f"bench cheb3d: {ms_per_step:.2f} ms/cycle, substeps {subs}, {achieved:.2f} TFLOP/s")
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid-point updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one 3-D filter, 64^3 Chebyshev grid, RK4 method of lines on MFMA, "
+                               "range measurement; one step = predict(T = 0.05) + update",
+                   "points": pts, "T": sc.T, "substeps": subs, "reductions": "f64"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "pmf::k_cheb_pass (all passes of a predict)",
+                     "predict_ms": float(np.mean(pred_ms)),
+                     "us_per_substep": 1e3 * sum(pred_ms) / lsum,
+                     "algorithmic_flops_per_predict": flops / args.steps},
+    }
+    if not args.no_extras:
+        # one predict against the FP64 GPU path (parity-tested against the oracle)
+        f64 = B.pmf_create(ctx, sc.model.with_(precision=W.FP64), sc.prior)
+        _, c0, M0, t0_, P0 = B.pmf_get_state(f)
+        B.pmf_set_state(f64, c0, M0, t0_, P0, W.CHEBYSHEV, W.FP64)
+        B.pmf_predict(f, sc.T)
+        B.pmf_predict(f64, sc.T)
+        _, _, M1, _, P1 = B.pmf_get_state(f)
+        _, _, M2, _, P2 = B.pmf_get_state(f64)
+        import oracle
+        q = oracle.quadrature_weights(sc.model, np.asarray(M2))
+        out["l1_vs_fp64"] = {"value": float(np.sum(q * np.abs(np.asarray(P1, float) - np.asarray(P2, float)))),
+                             "what": "one predict, FP32 MFMA path vs the FP64 GPU path from the same state",
+                             "tolerance": 1e-5}
+        B.pmf_destroy(f64)
+    B.pmf_destroy(f)
+    B.pmf_ctx_destroy(ctx)
+    if not args.no_cpu:
+        log("bench cheb3d: CPU oracle baseline")
+        out["cpu_baseline"] = cheb_cpu_baseline(N, 0.2)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
