@@ -113,9 +113,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip latency / L1 / plain-path legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain device copy of known size (counter scaling)")
-    ap.add_argument("--workload", choices=("batched", "cheb3d"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "cheb3d", "serve"), default="batched",
                     help="batched: the headline batched workload (default); cheb3d: one 3-D "
-                         "Chebyshev filter on a 64^3 grid (RK4 on MFMA, range measurement)")
+                         "Chebyshev filter on a 64^3 grid (RK4 on MFMA, range measurement); serve: "
+                         "many live tracks fed by Poisson arrivals through the serving runtime")
+    ap.add_argument("--tracks", type=int, default=10000, help="serve: live tracks")
+    ap.add_argument("--rates", type=str, default="1000,2000,5000,10000,20000,50000",
+                    help="serve: offered request rates (requests/s; one request = predict + update)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="serve: arrival window per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -124,6 +129,8 @@ def main():
         sys.exit(2)
     if args.workload == "cheb3d":
         return run_cheb3d(args)
+    if args.workload == "serve":
+        return run_serve(args)
     return run_batched(args)
 
 
@@ -392,6 +399,111 @@ def run_cheb3d(args):
         out["cpu_baseline"] = cheb_cpu_baseline(N, 0.2)
     else:
         out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ serving
+
+def run_serve(args):
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2412_07240_amd import binding as B
+
+    rates = [float(r) for r in args.rates.split(",") if r]
+    ntr = args.tracks
+    n_req = [int(r * args.serve_seconds) for r in rates]
+    K = 8 + int(2 * sum(n_req) / ntr)            # measurements per track, with margin
+    log(f"bench serve: generating {ntr} tracks")
+    scs = [W.serving_track(i, K=K) for i in range(ntr)]
+    pts = np.array([int(np.prod(sc.model.N[:sc.model.nx])) for sc in scs])
+    cls = np.array([sc.model.nx for sc in scs])
+    ctx = B.pmf_ctx_create(0)
+    srv = B.pmf_server_create(ctx, 64 << 30, ntr)
+    log("bench serve: creating tracks")
+    ids = [B.pmf_server_add_track(srv, sc.model, sc.prior) for sc in scs]
+    st0 = B.pmf_server_stats_get(srv)
+    nextk = np.zeros(ntr, dtype=int)
+    rng = np.random.default_rng(np.random.SeedSequence([241207240, 7]))
+    # warm every track once (first fused use uploads its constants)
+    tag = 0
+    for i in range(ntr):
+        B.pmf_server_submit_cycle(srv, ids[i], scs[i].T, scs[i].z[nextk[i]], tag=tag)
+        nextk[i] += 1
+        tag += 2
+    B.pmf_server_drain(srv)
+    B.pmf_server_poll(srv, cap=2 * tag + 16)
+    torch.cuda.synchronize()
+    results = []
+    for rate, n in zip(rates, n_req):
+        arr = W.poisson_arrivals(rate, n, seed_index=int(rate))
+        who = rng.integers(ntr, size=n)
+        tag0 = tag
+        log(f"bench serve: {rate:.0f} req/s, {n} requests")
+        t0 = time.perf_counter()
+        for j in range(n):
+            target = t0 + arr[j]
+            while time.perf_counter() < target:
+                pass
+            i = int(who[j])
+            B.pmf_server_submit_cycle(srv, ids[i], scs[i].T, scs[i].z[nextk[i] % K], tag=tag)
+            nextk[i] += 1
+            tag += 2
+        t_sub = time.perf_counter() - t0
+        B.pmf_server_drain(srv)
+        t_all = time.perf_counter() - t0
+        done = B.pmf_server_poll(srv, cap=2 * (tag - tag0) + 16)
+        upd = [c for c in done if c["op"] == B.PMF_OP_UPDATE]
+        lat = np.array([c["latency_us"] for c in upd]) / 1e3
+        tr = np.array([c["track"] for c in upd])
+        fused = np.mean([c["fused"] for c in upd]) if upd else 0.0
+        rec = {"offered_req_s": rate, "requests": n, "achieved_req_s": len(upd) / t_all,
+               "points_per_s": float(pts[tr].sum() / t_all), "submit_window_s": t_sub,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "fused_fraction": float(fused)}
+        for nx in (1, 2, 3):
+            sel = cls[tr] == nx
+            if sel.any():
+                rec[f"p50_ms_{nx}d"] = float(np.percentile(lat[sel], 50))
+                rec[f"p99_ms_{nx}d"] = float(np.percentile(lat[sel], 99))
+        results.append(rec)
+        log(f"bench serve: {json.dumps(rec)}")
+    stats = B.pmf_server_stats_get(srv)
+    B.pmf_server_destroy(srv)
+    # plain path: FP64 copies of a sample of the tracks, one op at a time
+    sub = scs[:200]
+    ff = [B.pmf_create(ctx, sc.model.with_(precision=W.FP64), sc.prior) for sc in sub]
+    for f, sc in zip(ff, sub):
+        B.pmf_predict(f, sc.T)
+        B.pmf_update(f, sc.z[0])
+    B.pmf_stream_sync()
+    t1 = time.perf_counter()
+    for f, sc in zip(ff, sub):
+        B.pmf_predict(f, sc.T)
+        B.pmf_update(f, sc.z[1])
+    B.pmf_stream_sync()
+    dtp = time.perf_counter() - t1
+    plain = float(pts[:200].sum() / dtp)
+    for f in ff:
+        B.pmf_destroy(f)
+    B.pmf_ctx_destroy(ctx)
+    best = max(results, key=lambda r: r["points_per_s"])
+    out = {
+        "metric": METRIC, "value": best["points_per_s"], "unit": "grid-point updates/s", "n_gpus": 1,
+        "steps": len(rates), "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving: {ntr} live tracks (50% 1-D N 64-256, 40% 2-D N 32-128, "
+                               "10% 3-D N 32-64), Poisson arrivals, one request = predict(T = 0.05) + "
+                               "update, per-track FIFO",
+                   "tracks": ntr, "device_bytes": st0["used_bytes"], "rates": rates,
+                   "seconds_per_rate": args.serve_seconds},
+        "serving": results,
+        "server_stats": stats,
+        "plain_fp64_gpu": {"value": plain, "unit": "grid-point updates/s",
+                           "what": "200 of the same tracks in FP64, one op at a time through "
+                                   "pmf_predict + pmf_update"},
+        "roofline": None, "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

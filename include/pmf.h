@@ -206,6 +206,72 @@ pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, doubl
 pmf_status pmf_batch_profile(pmf_ctx* ctx, int enable);
 pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int* launches);
 
+/* ------------------------------------------------------------------ serving
+ * Many independent tracks (one filter each) fed by an asynchronous stream of
+ * requests.  A native worker thread takes rounds: in each round every idle track
+ * contributes the head of its FIFO; a track whose head is predict(T) followed by
+ * update(z) and that pmf_batch_step accepts (Fourier, FP32, nx <= 2, the sizes
+ * listed there) runs that pair as one fused cycle, batched with the other tracks
+ * of the round that have the same T; every other op runs alone through
+ * pmf_predict / pmf_update on one of a few HIP streams.  Ops of one track run in
+ * submission order; results equal the direct calls on the same filter.  The
+ * server owns its tracks' filters.  A server's functions may be called from any
+ * thread; the filters of its tracks must not be used directly while ops of theirs
+ * are queued or running. */
+typedef struct pmf_server pmf_server;
+
+typedef enum { PMF_OP_PREDICT = 0, PMF_OP_UPDATE = 1 } pmf_op;
+
+typedef struct {
+    long long tag;        /* the caller's tag of the request */
+    int track;
+    int op;               /* pmf_op */
+    int status;           /* PMF_OK, or PMF_E_DEGENERATE for a rejected update */
+    int fused;            /* 1 if the op ran in a fused batched cycle */
+    double loglik;        /* update: log p(z_k | z^{k-1}) (NaN if rejected); predict: 0 */
+    double latency_us;    /* submission to completion, host clock */
+} pmf_completion;
+
+typedef struct {
+    size_t budget_bytes, used_bytes;   /* device bytes of the tracks' filters */
+    int tracks;
+    long long submitted, completed, rounds, fused_ops, single_ops;
+} pmf_server_stats;
+
+/* Server on ctx with a device-memory budget for its tracks (admission control)
+ * and at most max_tracks live tracks. */
+pmf_status pmf_server_create(pmf_ctx* ctx, size_t budget_bytes, int max_tracks, pmf_server** out);
+
+/* Blocks until every submitted op has completed, then frees the tracks. */
+void pmf_server_destroy(pmf_server* s);
+
+/* New track: creates its filter (as pmf_create).  PMF_E_NOMEM, with nothing
+ * kept, when its device bytes would exceed the budget or max_tracks are live. */
+pmf_status pmf_server_add_track(pmf_server* s, const pmf_model* model, const pmf_prior* prior, int* track);
+
+/* Removes an idle track (PMF_E_BUSY while it has queued or running ops). */
+pmf_status pmf_server_remove_track(pmf_server* s, int track);
+
+/* Queue one op: PMF_OP_PREDICT over T (z unused) or PMF_OP_UPDATE with z[0..nz)
+ * (T unused).  Copies z; returns at once. */
+pmf_status pmf_server_submit(pmf_server* s, int track, int op, double T, const double* z, long long tag);
+
+/* Queue predict(T) then update(z) as one unit (no op of another submission can
+ * come between them), tagged tag and tag + 1.  Returns at once. */
+pmf_status pmf_server_submit_cycle(pmf_server* s, int track, double T, const double* z, long long tag);
+
+/* Move up to cap completions (oldest first) into out; *n = how many. */
+pmf_status pmf_server_poll(pmf_server* s, pmf_completion* out, int cap, int* n);
+
+/* Block until every op submitted so far has completed. */
+pmf_status pmf_server_drain(pmf_server* s);
+
+pmf_status pmf_server_stats_get(pmf_server* s, pmf_server_stats* out);
+
+/* The filter of an idle track, for pmf_get_state / pmf_moments (NULL if the
+ * track does not exist). */
+pmf_filter* pmf_server_filter(pmf_server* s, int track);
+
 /* Device pointer of the density (for zero-copy inspection in tests); valid until
  * the next call on the filter.  Returns NULL on error. */
 void* pmf_density_ptr(pmf_filter* f);

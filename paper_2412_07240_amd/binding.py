@@ -43,6 +43,20 @@ class pmf_state_header(C.Structure):
                 ("c", C.c_double * 3), ("M", C.c_double * 9), ("t", C.c_double)]
 
 
+PMF_OP_PREDICT, PMF_OP_UPDATE = 0, 1
+
+
+class pmf_completion(C.Structure):
+    _fields_ = [("tag", C.c_longlong), ("track", C.c_int), ("op", C.c_int), ("status", C.c_int),
+                ("fused", C.c_int), ("loglik", C.c_double), ("latency_us", C.c_double)]
+
+
+class pmf_server_stats(C.Structure):
+    _fields_ = [("budget_bytes", C.c_size_t), ("used_bytes", C.c_size_t), ("tracks", C.c_int),
+                ("submitted", C.c_longlong), ("completed", C.c_longlong), ("rounds", C.c_longlong),
+                ("fused_ops", C.c_longlong), ("single_ops", C.c_longlong)]
+
+
 class PmfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"pmf status {status}: {msg}")
@@ -79,6 +93,16 @@ def lib():
             "pmf_batch_profile": (ip, [vp, ip]),
             "pmf_batch_kernel_time": (ip, [vp, dp, C.POINTER(C.c_int)]),
             "pmf_last_error": (C.c_char_p, []),
+            "pmf_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
+            "pmf_server_destroy": (None, [vp]),
+            "pmf_server_add_track": (ip, [vp, C.POINTER(pmf_model), C.POINTER(pmf_prior), C.POINTER(C.c_int)]),
+            "pmf_server_remove_track": (ip, [vp, ip]),
+            "pmf_server_submit": (ip, [vp, ip, ip, C.c_double, dp, C.c_longlong]),
+            "pmf_server_submit_cycle": (ip, [vp, ip, C.c_double, dp, C.c_longlong]),
+            "pmf_server_poll": (ip, [vp, C.POINTER(pmf_completion), ip, C.POINTER(C.c_int)]),
+            "pmf_server_drain": (ip, [vp]),
+            "pmf_server_stats_get": (ip, [vp, C.POINTER(pmf_server_stats)]),
+            "pmf_server_filter": (vp, [vp, ip]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -91,7 +115,9 @@ def lib():
 EXPORTED = ("pmf_ctx_create", "pmf_ctx_destroy", "pmf_create", "pmf_destroy", "pmf_predict",
             "pmf_update", "pmf_moments", "pmf_sync_status", "pmf_last_substeps", "pmf_get_state",
             "pmf_set_state", "pmf_batch_step", "pmf_density_ptr", "pmf_stream_sync", "pmf_batch_profile",
-            "pmf_batch_kernel_time", "pmf_last_error")
+            "pmf_batch_kernel_time", "pmf_last_error", "pmf_server_create", "pmf_server_destroy",
+            "pmf_server_add_track", "pmf_server_remove_track", "pmf_server_submit", "pmf_server_submit_cycle", "pmf_server_poll",
+            "pmf_server_drain", "pmf_server_stats_get", "pmf_server_filter")
 
 
 def pmf_last_error() -> str:
@@ -311,3 +337,65 @@ def pmf_batch_kernel_time(ctx):
     n = C.c_int(0)
     _check(lib().pmf_batch_kernel_time(ctx, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+# ------------------------------------------------------------------ serving
+
+def pmf_server_create(ctx, budget_bytes: int, max_tracks: int):
+    out = C.c_void_p()
+    _check(lib().pmf_server_create(ctx, int(budget_bytes), int(max_tracks), C.byref(out)))
+    return out
+
+
+def pmf_server_destroy(s) -> None:
+    lib().pmf_server_destroy(s)
+
+
+def pmf_server_add_track(s, model, prior) -> int:
+    m = make_model(model)
+    p = make_prior(prior, model.nx)
+    t = C.c_int(-1)
+    _check(lib().pmf_server_add_track(s, C.byref(m), C.byref(p), C.byref(t)))
+    return t.value
+
+
+def pmf_server_remove_track(s, track: int) -> None:
+    _check(lib().pmf_server_remove_track(s, int(track)))
+
+
+def pmf_server_submit(s, track: int, op: int, T: float = 0.0, z=None, tag: int = 0) -> None:
+    zp = None
+    if z is not None:
+        zz = np.ascontiguousarray(np.asarray(z, float).ravel())
+        zp = zz.ctypes.data_as(C.POINTER(C.c_double))
+    _check(lib().pmf_server_submit(s, int(track), int(op), float(T), zp, int(tag)))
+
+
+def pmf_server_submit_cycle(s, track: int, T: float, z, tag: int = 0) -> None:
+    zz = np.ascontiguousarray(np.asarray(z, float).ravel())
+    _check(lib().pmf_server_submit_cycle(s, int(track), float(T), zz.ctypes.data_as(C.POINTER(C.c_double)),
+                                         int(tag)))
+
+
+def pmf_server_poll(s, cap: int = 4096):
+    """Completions as a list of dicts (oldest first)."""
+    buf = (pmf_completion * cap)()
+    n = C.c_int(0)
+    _check(lib().pmf_server_poll(s, buf, cap, C.byref(n)))
+    return [{"tag": c.tag, "track": c.track, "op": c.op, "status": c.status, "fused": c.fused,
+             "loglik": c.loglik, "latency_us": c.latency_us} for c in buf[:n.value]]
+
+
+def pmf_server_drain(s) -> None:
+    _check(lib().pmf_server_drain(s))
+
+
+def pmf_server_stats_get(s) -> dict:
+    st = pmf_server_stats()
+    _check(lib().pmf_server_stats_get(s, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in pmf_server_stats._fields_}
+
+
+def pmf_server_filter(s, track: int):
+    p = lib().pmf_server_filter(s, int(track))
+    return C.c_void_p(p) if p else None

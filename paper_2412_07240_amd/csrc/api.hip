@@ -342,6 +342,7 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     auto A = [&](size_t bytes) {
         void* p = ctx_alloc(ctx, bytes, st);
         if (!p) okalloc = false;
+        f->bytes += bytes;
         return p;
     };
     for (int i = 0; i < 4; ++i) f->buf[i] = A(f->ntot * f->es);
@@ -454,6 +455,7 @@ void pmf_destroy(pmf_filter* f) {
     ctx_free(ctx, f->D1, nullptr);
     ctx_free(ctx, f->D2, nullptr);
     for (int i = 0; i < 5; ++i) ctx_free(ctx, f->rk[i], nullptr);
+    ctx_free(ctx, f->dconst, nullptr);
     batch_forget_filter(ctx, f);
     delete f;
 }

@@ -8,6 +8,7 @@
 #include "pmf_internal.h"
 
 struct BatchCache;
+struct DynBatch;
 
 struct pmf_ctx {
     int device = 0;
@@ -44,6 +45,9 @@ struct pmf_filter {
     int nb = 0, chunk = 0;         // reduction partition
     bool have_pa = false;
     pmf::PredictArgs pa{};
+    size_t bytes = 0;              // device bytes this filter holds
+    void* dconst = nullptr;        // device copy of the fused-step constants (served batches)
+    double dconst_T = -1.0;        // interval those constants were built for
 };
 
 namespace pmf {
@@ -70,5 +74,17 @@ pmf_status cheb_predict_mfma(pmf_filter* f, int l, hipStream_t st);
 void batch_cache_release(pmf_ctx* ctx);
 void batch_forget_filter(pmf_ctx* ctx, pmf_filter* f);
 hipError_t batch_leave(pmf_filter* f);
+bool batch_fusable(const pmf_filter* f, std::string* why);
+
+// fused steps over a changing set of filters (served batches, batch.hip): the
+// items are rebuilt on every call, no graph.  Asynchronous on st; the host
+// staging is reused by the next call, so the caller waits for st in between.
+DynBatch* dyn_create(pmf_ctx* ctx);
+void dyn_destroy(pmf_ctx* ctx, DynBatch* db);
+// z: n x 3 doubles (row i for filters[i]); after st completes, dyn_loglik(db)[i]
+// is filter i's log-likelihood (NaN when its update was rejected)
+pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n, double T, const double* z,
+                   hipStream_t st);
+const double* dyn_loglik(const DynBatch* db);
 
 }  // namespace pmf

@@ -10,6 +10,7 @@
 //   store.
 // HBM traffic per filter: the density read once and written once.
 #include <algorithm>
+#include <map>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -1297,6 +1298,60 @@ static int pow2_at_least(int v) {
     return p;
 }
 
+// Same-size filters in groups of at most the group type's capacity, largest
+// grids first (the persistent workgroups take the longest work first).
+// Returns the largest complex LDS need of a group.
+static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sorted, std::vector<GItem>& groups) {
+    const int n = (int)items.size();
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const long pa = (long)items[a].n0 * items[a].n1, pb = (long)items[b].n0 * items[b].n1;
+        if (pa != pb) return pa > pb;
+        if (items[a].n1 != items[b].n1) return items[a].n1 > items[b].n1;
+        return items[a].nx > items[b].nx;
+    });
+    sorted.assign(n, BItem{});
+    groups.clear();
+    int maxcplx = 0;
+    for (int q = 0; q < n;) {
+        const BItem& b = items[order[q]];
+        const int pitch = b.n1 / 2 + 1;
+        const int type = group_type(b.nx, b.n0, b.n1);
+        const int G = group_capacity(type);
+        GItem gi;
+        gi.first = q;
+        gi.n0 = b.n0;
+        gi.n1 = b.n1;
+        gi.nx = b.nx;
+        gi.seg = std::max(32, pow2_at_least(b.n1));
+        gi.type = type;
+        gi.pad = 0;
+        int cnt = 0;
+        while (q < n && cnt < G && items[order[q]].n0 == b.n0 && items[order[q]].n1 == b.n1 &&
+               items[order[q]].nx == b.nx) {
+            sorted[q] = items[order[q]];
+            ++q;
+            ++cnt;
+        }
+        gi.G = cnt;
+        groups.push_back(gi);
+        maxcplx = std::max(maxcplx, gi.n0 * G * pitch);
+    }
+    return maxcplx;
+}
+
+// dynamic LDS of the fused kernel for a given complex buffer size, and the
+// largest it can be (two buffers of CPLX_BUDGET entries)
+static size_t fused_lds(int maxcplx) {
+    return 2 * (size_t)maxcplx * sizeof(float2) + (128 + 128 + 130) * sizeof(float2);
+}
+
+static hipError_t fused_lds_attribute() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_fused), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)fused_lds(CPLX_BUDGET));
+}
+
 static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, hipStream_t st) {
     batch_cache_release(ctx);
     BatchCache* c = new BatchCache();
@@ -1324,42 +1379,9 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
         b.n0 = f->model.nx == 2 ? f->model.N[0] : 1;
         b.n1 = f->model.nx == 2 ? f->model.N[1] : f->model.N[0];
     }
-    // same-size filters in groups, largest groups' grids first
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const long pa = (long)items[a].n0 * items[a].n1, pb = (long)items[b].n0 * items[b].n1;
-        if (pa != pb) return pa > pb;
-        if (items[a].n1 != items[b].n1) return items[a].n1 > items[b].n1;
-        return items[a].nx > items[b].nx;
-    });
-    std::vector<BItem> sorted(n);
+    std::vector<BItem> sorted;
     std::vector<GItem> groups;
-    int maxcplx = 0;
-    for (int q = 0; q < n;) {
-        const BItem& b = items[order[q]];
-        const int pitch = b.n1 / 2 + 1;
-        const int type = group_type(b.nx, b.n0, b.n1);
-        const int G = group_capacity(type);
-        GItem gi;
-        gi.first = q;
-        gi.n0 = b.n0;
-        gi.n1 = b.n1;
-        gi.nx = b.nx;
-        gi.seg = std::max(32, pow2_at_least(b.n1));
-        gi.type = type;
-        gi.pad = 0;
-        int cnt = 0;
-        while (q < n && cnt < G && items[order[q]].n0 == b.n0 && items[order[q]].n1 == b.n1 &&
-               items[order[q]].nx == b.nx) {
-            sorted[q] = items[order[q]];
-            ++q;
-            ++cnt;
-        }
-        gi.G = cnt;
-        groups.push_back(gi);
-        maxcplx = std::max(maxcplx, gi.n0 * G * pitch);
-    }
+    const int maxcplx = group_items(items, sorted, groups);
     c->ngroups = (int)groups.size();
     bool ok = true;
     auto A = [&](size_t bytes) {
@@ -1386,9 +1408,8 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     }
     if (e != hipSuccess) return hip_fail(e, "batch setup");
     c->bufcplx = maxcplx;
-    c->lds = 2 * (size_t)maxcplx * sizeof(float2) + (128 + 128 + 130) * sizeof(float2);
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_fused), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)c->lds);
+    c->lds = fused_lds(maxcplx);
+    e = fused_lds_attribute();
     if (e != hipSuccess) return hip_fail(e, "fused kernel LDS attribute");
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, FUSED_THREADS, c->lds);
@@ -1412,6 +1433,175 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return hip_fail(e, "graph capture");
+    return PMF_OK;
+}
+
+// ---------------------------------------------------------------- served batches
+
+}  // namespace pmf
+
+struct DynBatch {
+    int cap = 0;                     // filters the buffers hold
+    pmf::BItem* d_items = nullptr;
+    pmf::GItem* d_groups = nullptr;
+    pmf::FPlan* d_plans = nullptr;
+    double* d_z = nullptr;
+    double* d_ll = nullptr;
+    int* d_ctr = nullptr;
+    pmf::BItem* h_items = nullptr;   // pinned staging
+    pmf::GItem* h_groups = nullptr;
+    double* h_z = nullptr;
+    double* h_ll = nullptr;
+    bool attr = false;
+    int ncu = 0;
+    std::map<size_t, int> per_cu;    // resident fused workgroups per CU, by LDS size
+};
+
+namespace pmf {
+
+static void dyn_free_buffers(pmf_ctx* ctx, DynBatch* db) {
+    ctx_free(ctx, db->d_items, nullptr);
+    ctx_free(ctx, db->d_groups, nullptr);
+    ctx_free(ctx, db->d_plans, nullptr);
+    ctx_free(ctx, db->d_z, nullptr);
+    ctx_free(ctx, db->d_ll, nullptr);
+    ctx_free(ctx, db->d_ctr, nullptr);
+    if (db->h_items) (void)hipHostFree(db->h_items);
+    if (db->h_groups) (void)hipHostFree(db->h_groups);
+    if (db->h_z) (void)hipHostFree(db->h_z);
+    if (db->h_ll) (void)hipHostFree(db->h_ll);
+    db->d_items = nullptr;
+    db->d_groups = nullptr;
+    db->d_plans = nullptr;
+    db->d_z = db->d_ll = nullptr;
+    db->d_ctr = nullptr;
+    db->h_items = nullptr;
+    db->h_groups = nullptr;
+    db->h_z = db->h_ll = nullptr;
+    db->cap = 0;
+}
+
+DynBatch* dyn_create(pmf_ctx*) { return new DynBatch(); }
+
+void dyn_destroy(pmf_ctx* ctx, DynBatch* db) {
+    if (!db) return;
+    (void)hipDeviceSynchronize();
+    dyn_free_buffers(ctx, db);
+    delete db;
+}
+
+const double* dyn_loglik(const DynBatch* db) { return db->h_ll; }
+
+static pmf_status dyn_reserve(pmf_ctx* ctx, DynBatch* db, int n) {
+    if (n <= db->cap) return PMF_OK;
+    int cap = std::max(64, db->cap);
+    while (cap < n) cap *= 2;
+    (void)hipDeviceSynchronize();   // the old buffers may still be read by a launch
+    dyn_free_buffers(ctx, db);
+    bool ok = true;
+    auto A = [&](size_t bytes) {
+        void* p = ctx_alloc(ctx, bytes, nullptr);
+        if (!p) ok = false;
+        return p;
+    };
+    db->d_items = static_cast<BItem*>(A(sizeof(BItem) * cap));
+    db->d_groups = static_cast<GItem*>(A(sizeof(GItem) * cap));
+    db->d_plans = static_cast<FPlan*>(A(sizeof(FPlan) * cap));
+    db->d_z = static_cast<double*>(A(sizeof(double) * 3 * cap));
+    db->d_ll = static_cast<double*>(A(sizeof(double) * cap));
+    db->d_ctr = static_cast<int*>(A(sizeof(int)));
+    hipError_t e = hipSuccess;
+    if (ok) e = hipHostMalloc(reinterpret_cast<void**>(&db->h_items), sizeof(BItem) * cap, hipHostMallocDefault);
+    if (ok && e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&db->h_groups), sizeof(GItem) * cap, hipHostMallocDefault);
+    if (ok && e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&db->h_z), sizeof(double) * 3 * cap, hipHostMallocDefault);
+    if (ok && e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&db->h_ll), sizeof(double) * cap, hipHostMallocDefault);
+    if (!ok || e != hipSuccess) {
+        dyn_free_buffers(ctx, db);
+        return fail(PMF_E_NOMEM, "served batch allocation failed");
+    }
+    db->cap = cap;
+    return PMF_OK;
+}
+
+pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n, double T, const double* z,
+                   hipStream_t st) {
+    if (n < 1) return PMF_OK;
+    if (!std::isfinite(T) || !(T > 0.0)) return fail(PMF_E_INVALID, "T must be finite and > 0");
+    pmf_status s = dyn_reserve(ctx, db, n);
+    if (s != PMF_OK) return s;
+    hipError_t e = hipSuccess;
+    if (!db->attr) {
+        e = fused_lds_attribute();
+        hipDeviceProp_t prop;
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, ctx->device);
+        if (e != hipSuccess) return hip_fail(e, "fused kernel set-up");
+        db->ncu = prop.multiProcessorCount;
+        db->attr = true;
+    }
+    std::vector<BItem> items(n);
+    for (int i = 0; i < n; ++i) {
+        pmf_filter* f = filters[i];
+        std::string why;
+        if (!batch_fusable(f, &why)) return fail(PMF_E_INVALID, "filter not fusable: " + why);
+        e = batch_enter(f);
+        if (e != hipSuccess) return hip_fail(e, "batch enter");
+        if (!f->dconst) {
+            f->dconst = ctx_alloc(ctx, sizeof(FConst), nullptr);
+            if (!f->dconst) return fail(PMF_E_NOMEM, "fused constants");
+            f->bytes += sizeof(FConst);
+            f->dconst_T = -1.0;
+        }
+        if (f->dconst_T != T) {
+            FConst k;
+            k.m = f->km;
+            k.pa = predict_args(f, T);
+            e = hipMemcpy(f->dconst, &k, sizeof(FConst), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "fused constants upload");
+            f->dconst_T = T;
+        }
+        BItem& b = items[i];
+        b.P[0] = static_cast<float*>(f->buf[0]);
+        b.P[1] = static_cast<float*>(f->buf[1]);
+        b.d = f->desc;
+        b.k = static_cast<const FConst*>(f->dconst);
+        b.coef = f->coef;
+        b.idx = i;
+        b.nx = f->model.nx;
+        b.n0 = f->model.nx == 2 ? f->model.N[0] : 1;
+        b.n1 = f->model.nx == 2 ? f->model.N[1] : f->model.N[0];
+    }
+    std::vector<BItem> sorted;
+    std::vector<GItem> groups;
+    const int maxcplx = group_items(items, sorted, groups);
+    const int ng = (int)groups.size();
+    const size_t lds = fused_lds(maxcplx);
+    auto it = db->per_cu.find(lds);
+    if (it == db->per_cu.end()) {
+        int pc = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, k_fused, FUSED_THREADS, lds);
+        if (e != hipSuccess) return hip_fail(e, "occupancy");
+        if (pc < 1) return fail(PMF_E_INVALID, "fused kernel does not fit on a compute unit");
+        it = db->per_cu.emplace(lds, pc).first;
+    }
+    const int grid = std::min(ng, it->second * db->ncu);
+    std::memcpy(db->h_items, sorted.data(), sizeof(BItem) * n);
+    std::memcpy(db->h_groups, groups.data(), sizeof(GItem) * ng);
+    std::memcpy(db->h_z, z, sizeof(double) * 3 * n);
+    e = hipMemcpyAsync(db->d_items, db->h_items, sizeof(BItem) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(db->d_groups, db->h_groups, sizeof(GItem) * ng, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(db->d_z, db->h_z, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "served batch upload");
+    hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, db->d_items, db->d_plans, n, db->d_z, 3,
+                       db->d_ctr);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, db->d_groups, ng, db->d_items,
+                       db->d_plans, db->d_ctr, db->d_z, 3, db->d_ll, maxcplx);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(db->h_ll, db->d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "served batch launch");
     return PMF_OK;
 }
 
