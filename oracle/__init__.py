@@ -12,7 +12,8 @@ Every routine follows a definition of the paper written out directly:
   and second derivatives (eq. secDer), as dense matrices;
 * the moving-grid Fokker-Planck equation of Sec. II.B (eqs. movFPEadv, easyFPE),
   integrated in physical grid space by classic RK4 (method of lines), or by the
-  implicit Euler step of Sec. V.A, or exactly (a per-mode exponential);
+  implicit Euler step of Sec. V.A, or exactly (a per-mode exponential), or by
+  the explicit finite-difference baseline of eq. FDM (step matrices of eq. fdiff);
 * Chebyshev differentiation (Sec. IV.B) on Chebyshev-Gauss-Lobatto nodes;
 * the Bayes rule of Sec. I.A (eq. filt) applied point by point, with the
   normalisation of Sec. III.A (eq. PDF_pm).

@@ -24,7 +24,7 @@ from . import fourier as fou
 from . import linear as lin
 
 FOURIER, CHEBYSHEV = 0, 1
-INT_EXACT, INT_RK4, INT_EULER = 0, 1, 2
+INT_EXACT, INT_RK4, INT_EULER, INT_FDM = 0, 1, 2, 3
 INTERP_AUTO, INTERP_LAGRANGE = 0, 1
 H_LINEAR, H_CUBIC1, H_NORM = 0, 1, 2
 
@@ -33,6 +33,7 @@ STATUS_DEGENERATE = 4
 STATUS_BOUNDARY = 64
 BOUNDARY_TOL = 1e-4
 RK4_STABLE_STEP = 2.5   # h * lambda_max kept at or below this (RK4 is stable to 2.78)
+FDM_STABLE_STEP = 1.0   # h * sum_a Dy_aa kept at or below this (explicit scheme of eq. FDM)
 
 
 @dataclass
@@ -208,13 +209,30 @@ def lambda_bound(model, Dy: np.ndarray) -> float:
 
 def substeps(model, state: State, T: float) -> int:
     """l = max(l_min, ceil(T * lambda_max / 2.5)) for RK4, with lambda_max the bound
-    at t = 0, T/2, T; the other integrators use l_min."""
+    at t = 0, T/2, T; for the finite-difference scheme l = max(l_min,
+    ceil(T * max_t sum_a Dy_aa(t))) over the same times (its step matrix keeps
+    its eigenvalues in (-1, 1] for h sum_a Dy_aa <= 1); exact and Euler use l_min."""
     l_min = max(1, int(model.substeps))
-    if model.integrator != INT_RK4 or T <= 0.0:
+    if T <= 0.0:
+        return l_min
+    if model.integrator == INT_FDM:
+        lam = max(float(np.trace(lin.Dy(model.A, model.D, state.M, t))) for t in (0.0, 0.5 * T, T))
+        return max(l_min, int(math.ceil(T * lam / FDM_STABLE_STEP)))
+    if model.integrator != INT_RK4:
         return l_min
     lam = max(lambda_bound(model, lin.Dy(model.A, model.D, state.M, t))
               for t in (0.0, 0.5 * T, T))
     return max(l_min, int(math.ceil(T * lam / RK4_STABLE_STEP)))
+
+
+def second_difference(n: int) -> np.ndarray:
+    """tridiag(1, -2, 1) on n interior nodes with zero values beyond both ends."""
+    return -2.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+
+
+def fdm_step_matrix(n: int, a_t: float, b_t: float) -> np.ndarray:
+    """The 1-D step matrix of eq. fdiff: b_t on the diagonal, a_t beside it."""
+    return b_t * np.eye(n) + a_t * (np.eye(n, k=1) + np.eye(n, k=-1))
 
 
 def _operators(model):
@@ -271,6 +289,21 @@ def predict(model, state: State, T: float):
             Wy = np.linalg.inv(M0) @ lin.W_integral(A, D, T) @ np.linalg.inv(M0).T
             S = fou.dft_nd(P) * np.exp(-0.5 * fou.symbol(P.shape, Wy))
             P = fou.idft_nd(S).real
+        elif model.integrator == INT_FDM:
+            # explicit finite differences of eq. FDM on the moving grid, in index
+            # coordinates: P <- P + h (-tr(A) P + 1/2 sum_a Dy_aa(t_n) (P_{j+1} - 2 P_j + P_{j-1})_a),
+            # n = 0..l-1, zero beyond the grid (the step matrix of eq. fdiff per axis)
+            if np.any(A != np.diag(np.diag(A))) or np.any(D != np.diag(np.diag(D))):
+                raise ValueError("the finite-difference scheme needs diagonal A and D")
+            h = T / l
+            trA = float(np.trace(A))
+            L2 = [second_difference(model.N[a]) for a in range(model.nx)]
+            for n in range(l):
+                Dy = lin.Dy(A, D, M0, n * h)
+                rhs = -trA * P
+                for a in range(model.nx):
+                    rhs = rhs + 0.5 * Dy[a, a] * fou.apply_along(L2[a], P, a)
+                P = P + h * rhs
         elif model.integrator == INT_EULER:
             # implicit diffusion per substep (Sec. V.A): P_{n+1} = P_n / (1 - q/2 dt c''_n),
             # with c'' = -kappa^2 <= 0 and the diffusion taken at t_n, n = 0..l-1.
@@ -281,7 +314,8 @@ def predict(model, state: State, T: float):
             P = fou.idft_nd(S).real
         else:
             raise ValueError(model.integrator)
-        P = P * math.exp(-np.trace(A) * T)
+        if model.integrator != INT_FDM:   # the explicit scheme carries its own trace term
+            P = P * math.exp(-np.trace(A) * T)
     Phi = lin.expm(A * T)
     return State(Phi @ state.c, Phi @ M0, state.t + T, P), l
 
