@@ -58,7 +58,7 @@ typedef enum {
 } pmf_status;
 
 enum { PMF_GRID_FOURIER = 0, PMF_GRID_CHEBYSHEV = 1 };
-enum { PMF_INT_EXACT = 0, PMF_INT_RK4 = 1, PMF_INT_EULER = 2 };
+enum { PMF_INT_EXACT = 0, PMF_INT_RK4 = 1, PMF_INT_EULER = 2, PMF_INT_FDM = 3 };
 enum { PMF_INTERP_AUTO = 0, PMF_INTERP_LAGRANGE = 1 };
 enum { PMF_H_LINEAR = 0, PMF_H_CUBIC1 = 1, PMF_H_NORM = 2 };
 enum { PMF_FP64 = 0, PMF_FP32 = 1 };
@@ -79,11 +79,11 @@ typedef struct {
     double A[9];                /* row-major nx x nx drift matrix */
     double Q[9];                /* row-major nx x nx noise gain; D = Q Q^T */
     int grid;                   /* PMF_GRID_FOURIER or PMF_GRID_CHEBYSHEV */
-    int N[3];                   /* points per axis.  Fourier: even, 2^a 3^b, 4..256.
+    int N[3];                   /* points per axis.  Fourier: even, 2^a 3^b 5^c, 4..256.
                                    Chebyshev: 4..256 */
     double span_sigmas;         /* grid half-width in standard deviations (e.g. 8) */
     double t_nominal;           /* interval used by the grid design, > 0 */
-    int integrator;             /* PMF_INT_EXACT | PMF_INT_RK4 | PMF_INT_EULER
+    int integrator;             /* PMF_INT_EXACT | PMF_INT_RK4 | PMF_INT_EULER | PMF_INT_FDM
                                    (Chebyshev grids: RK4 only) */
     int substeps;               /* minimum number of substeps l (>= 1) */
     int precision;              /* PMF_FP64 or PMF_FP32 density; reductions are FP64 */
@@ -147,7 +147,16 @@ void pmf_destroy(pmf_filter* f);
  *           lambda(t) = -1/2 kappa^T D_y(t) kappa,  D_y(t) = M(t)^-1 D M(t)^-T;
  *   euler:  the product of 1 / (1 + h/2 kappa^T D_y(t_n) kappa), n = 0..l-1
  *           (implicit diffusion, Sec. V.A);
- * times e^{-tr(A) T} (the trace term of eq. easyFPE).  Mixed derivatives use the
+ * times e^{-tr(A) T} (the trace term of eq. easyFPE).
+ *   fdm:    the finite-difference baseline of Sec. III.B: l explicit steps of
+ *           eq. FDM (step matrices of eq. fdiff per axis, the trace term inside),
+ *           the nodes taken as interior nodes with zeros beyond both ends,
+ *           computed by the sine-transform route of eq. FST: DST-I along every
+ *           axis, the product over n of the step eigenvalues
+ *           1 - h tr(A) + h sum_a D_y,aa(t_n) (cos(j_a pi / (N_a + 1)) - 1),
+ *           DST-I back.  Needs diagonal A and D (Fourier grid; the designed
+ *           grids are axis-aligned, so D_y stays diagonal);
+ *           l = max(substeps, ceil(T max_t sum_a D_y,aa(t))) at t = 0, T/2, T.  Mixed derivatives use the
  * first-derivative symbol (no Nyquist term), squares keep it (eq. secDer).
  * Chebyshev grids: classic RK4 with dense differentiation matrices.
  * RK4 uses l = max(substeps, ceil(T lambda_max / 2.5)) substeps; lambda_max bounds

@@ -170,11 +170,20 @@ static pmf_status validate_model(const pmf_model* m) {
         const int n = m->N[a];
         if (n < 4 || n > 256) return fail(PMF_E_INVALID, "N per axis must be 4..256");
         if (m->grid == PMF_GRID_FOURIER && (n % 2 != 0 || make_plan(n).np < 0))
-            return fail(PMF_E_INVALID, "Fourier N must be even and of the form 2^a 3^b");
+            return fail(PMF_E_INVALID, "Fourier N must be even and of the form 2^a 3^b 5^c");
         ntot *= n;
     }
     if (ntot > (1L << 24)) return fail(PMF_E_INVALID, "grid larger than 2^24 points");
-    if (m->integrator < 0 || m->integrator > 2) return fail(PMF_E_INVALID, "unknown integrator");
+    if (m->integrator < 0 || m->integrator > 3) return fail(PMF_E_INVALID, "unknown integrator");
+    if (m->integrator == PMF_INT_FDM) {
+        if (m->grid != PMF_GRID_FOURIER) return fail(PMF_E_INVALID, "the finite-difference baseline needs a Fourier grid");
+        double Dm[9];
+        diffusion(*m, Dm);
+        for (int i = 0; i < m->nx; ++i)
+            for (int j = 0; j < m->nx; ++j)
+                if (i != j && (m->A[i * m->nx + j] != 0.0 || Dm[i * 3 + j] != 0.0))
+                    return fail(PMF_E_INVALID, "the finite-difference baseline needs diagonal A and D");
+    }
     if (m->grid == PMF_GRID_CHEBYSHEV && m->integrator != PMF_INT_RK4)
         return fail(PMF_E_INVALID, "Chebyshev grids support the RK4 integrator only");
     if (m->substeps < 1 || m->substeps > LMAX) return fail(PMF_E_INVALID, "substeps must be 1..4096");
@@ -353,6 +362,7 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     f->W = static_cast<double*>(A((size_t)model->nx * f->km.wstride * sizeof(double)));
     f->tab = static_cast<double*>(A((size_t)3 * TAB_STRIDE * sizeof(double)));
     f->desc = static_cast<DevDesc*>(A(sizeof(DevDesc)));
+    if (model->integrator == PMF_INT_FDM) f->D1 = A((size_t)3 * 256 * 256 * f->es);   // DST-I matrices
     if (model->grid == PMF_GRID_CHEBYSHEV) {
         f->D1 = A((size_t)3 * 256 * 256 * f->es);
         f->D2 = A((size_t)3 * 256 * 256 * f->es);
@@ -371,6 +381,26 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     if (e != hipSuccess) {
         pmf_destroy(f);
         return hip_fail(e, "upload tables");
+    }
+    if (model->integrator == PMF_INT_FDM) {
+        std::vector<double> sall((size_t)3 * 256 * 256, 0.0);
+        for (int a = 0; a < model->nx; ++a) {
+            const int n = model->N[a];
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    sall[(size_t)a * 256 * 256 + (size_t)i * n + j] =
+                        std::sin((double)(i + 1) * (j + 1) * M_PI / (double)(n + 1));
+        }
+        if (f->es == sizeof(double)) {
+            e = hipMemcpy(f->D1, sall.data(), sall.size() * 8, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> s32(sall.begin(), sall.end());
+            e = hipMemcpy(f->D1, s32.data(), s32.size() * 4, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            pmf_destroy(f);
+            return hip_fail(e, "upload sine-transform matrices");
+        }
     }
     if (model->grid == PMF_GRID_CHEBYSHEV) {
         std::vector<double> d1all((size_t)3 * 256 * 256, 0.0), d2all((size_t)3 * 256 * 256, 0.0);
@@ -474,6 +504,22 @@ pmf_status pmf_predict(pmf_filter* f, double T, void* stream) {
     const PredictArgs& pa = predict_args(f, T);
     e = launch_plan(pa, f->desc, f->coef, st);
     if (e != hipSuccess) return hip_fail(e, "plan");
+    if (f->model.integrator == PMF_INT_FDM) {
+        double trA = 0.0;
+        for (int i = 0; i < f->model.nx; ++i) trA += pa.A[i * 3 + i];
+        void* t1 = f->buf[(f->cur + 1) % 4];
+        void* t2 = f->buf[(f->cur + 2) % 4];
+        if (f->es == sizeof(double))
+            e = launch_predict_fdm<double>(f->km, f->desc, f->coef, static_cast<const double*>(f->D1),
+                                           static_cast<double*>(f->buf[f->cur]), static_cast<double*>(t1),
+                                           static_cast<double*>(t2), trA, st);
+        else
+            e = launch_predict_fdm<float>(f->km, f->desc, f->coef, static_cast<const float*>(f->D1),
+                                          static_cast<float*>(f->buf[f->cur]), static_cast<float*>(t1),
+                                          static_cast<float*>(t2), trA, st);
+        if (e != hipSuccess) return hip_fail(e, "predict (finite differences)");
+        return PMF_OK;
+    }
     if (f->model.grid == PMF_GRID_FOURIER) {
         if (f->es == sizeof(double))
             e = launch_predict_fourier<double>(f->km, f->desc, f->coef, f->cbuf, static_cast<double*>(f->buf[f->cur]), st);

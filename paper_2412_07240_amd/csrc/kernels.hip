@@ -80,6 +80,24 @@ template <typename C, typename T> __device__ inline void dft8(C* a, int s) {
     a[7] = csub(e[3], o3);
 }
 
+// 5-point DFT from t = a_1 + a_4, a_2 + a_3 and d = a_1 - a_4, a_2 - a_3 with
+// cos and sin of 2 pi / 5 and 4 pi / 5
+template <typename C, typename T> __device__ inline void dft5(C* a, int s) {
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+    const C t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+    const C d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+    const C m1 = cadd(a[0], cadd(cscale(t1, c1), cscale(t2, c2)));
+    const C m2 = cadd(a[0], cadd(cscale(t1, c2), cscale(t2, c1)));
+    const C r1 = cmul_si(cadd(cscale(d1, s1), cscale(d2, s2)), s);
+    const C r2 = cmul_si(csub(cscale(d1, s2), cscale(d2, s1)), s);
+    a[0] = cadd(a[0], cadd(t1, t2));
+    a[1] = cadd(m1, r1);
+    a[4] = csub(m1, r1);
+    a[2] = cadd(m2, r2);
+    a[3] = csub(m2, r2);
+}
+
 // One Stockham autosort pass over `nlines` lines held in LDS (pitch `pitch`).
 template <typename T, int R>
 __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* out, int n, int Ns,
@@ -109,6 +127,7 @@ __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* ou
         if (R == 3) dft3<C, T>(v, sign);
         if (R == 4) dft4<C, T>(v, sign);
         if (R == 8) dft8<C, T>(v, sign);
+        if (R == 5) dft5<C, T>(v, sign);
         const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
@@ -159,6 +178,7 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
         if (R == 8) stockham_pass<T, 8>(in, out, n, Ns, ntl, pitch, sign);
         else if (R == 4) stockham_pass<T, 4>(in, out, n, Ns, ntl, pitch, sign);
         else if (R == 3) stockham_pass<T, 3>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 5) stockham_pass<T, 5>(in, out, n, Ns, ntl, pitch, sign);
         else stockham_pass<T, 2>(in, out, n, Ns, ntl, pitch, sign);
         __syncthreads();
         C* tmp = in;
@@ -226,6 +246,26 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
                 lam = lb > lam ? lb : lam;
             }
             const double need = ceil(a.T * lam / RK4_STABLE_STEP);
+            if (need > (double)l) l = need > (double)a.lmax ? a.lmax + 1 : (int)need;
+        }
+        if (a.integ == PMF_INT_FDM && a.T > 0.0) {
+            // explicit step: h sum_a D_y,aa(t) <= 1 at t = 0, T/2, T
+            double lam = 0.0;
+            const double* Es[3] = {nullptr, a.emh, a.emT};
+            for (int q = 0; q < 3; ++q) {
+                double E[9], t1[9], Dy[9];
+                if (q == 0) {
+                    mat_copy(E, a.D);
+                } else {
+                    mat_mul(t1, Es[q], a.D, n);
+                    mat_mul_bt(E, t1, Es[q], n);
+                }
+                sandwich_inv(Dy, Mi, E, n);
+                double tr = 0.0;
+                for (int i = 0; i < n; ++i) tr += Dy[i * 3 + i];
+                lam = tr > lam ? tr : lam;
+            }
+            const double need = ceil(a.T * lam / FDM_STABLE_STEP);
             if (need > (double)l) l = need > (double)a.lmax ? a.lmax + 1 : (int)need;
         }
         if (l > a.lmax) {
@@ -1093,6 +1133,64 @@ hipError_t launch_copy(T* dst, const T* src, int ntot, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ finite-difference baseline
+// Sine-transform route of eq. FST: X <- S_a X along every axis (S_a[i][j] =
+// sin((i+1)(j+1) pi / (N_a+1)), the DST-I), times the product over the l steps
+// of the eigenvalues of the explicit step, times prod_a 2 / (N_a + 1) (R^-1 =
+// 2/(N+1) R), then S_a again.
+
+template <typename T>
+__global__ void k_fdm_gain(T* X, KModel m, const DevDesc* d, const double* coef, double trA) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m.ntot) return;
+    double cm1[3] = {0.0, 0.0, 0.0};   // cos(theta_a) - 1
+    double norm = 1.0;
+    int rem = j;
+    for (int a = m.nx - 1; a >= 0; --a) {
+        const int ia = rem % m.N[a];
+        rem /= m.N[a];
+        cm1[a] = cospi((double)(ia + 1) / (double)(m.N[a] + 1)) - 1.0;
+        norm *= 2.0 / (double)(m.N[a] + 1);
+    }
+    const int l = d->l;
+    const double h = d->h;
+    double g = norm;
+    for (int n = 0; n < l; ++n) {
+        const double* c = coef + 6 * n;   // packed 00, 11, 22, ...
+        double lam = 1.0 - h * trA;
+        for (int a = 0; a < m.nx; ++a) lam += h * c[a] * cm1[a];
+        g *= lam;
+    }
+    X[j] = (T)((double)X[j] * g);
+}
+
+template <typename T>
+hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, const T* S, T* X, T* t1, T* t2,
+                              double trA, hipStream_t st) {
+    const int g = cdiv(m.ntot, 256);
+    int strides[3];
+    for (int a = 0; a < m.nx; ++a) {
+        int s = 1;
+        for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
+        strides[a] = s;
+    }
+    T* cur = X;
+    for (int a = 0; a < m.nx; ++a) {
+        T* dst = (cur == t1) ? t2 : t1;
+        hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, S + (size_t)a * 256 * 256, cur, dst, m.N[a],
+                           strides[a], m.ntot, coef, -1, 1.0, 0);
+        cur = dst;
+    }
+    hipLaunchKernelGGL(k_fdm_gain<T>, dim3(g), dim3(256), 0, st, cur, m, d, coef, trA);
+    for (int a = 0; a < m.nx; ++a) {
+        T* dst = (a == m.nx - 1) ? X : ((cur == t1) ? t2 : t1);
+        hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, S + (size_t)a * 256 * 256, cur, dst, m.N[a],
+                           strides[a], m.ntot, coef, -1, 1.0, 0);
+        cur = dst;
+    }
+    return hipGetLastError();
+}
+
 #define PMF_INSTANTIATE(T)                                                                                   \
     template hipError_t launch_predict_fourier<T>(const KModel&, DevDesc*, const double*, void*, T*,         \
                                                   hipStream_t);                                              \
@@ -1106,6 +1204,8 @@ hipError_t launch_copy(T* dst, const T* src, int ntot, hipStream_t st) {
                                            T*, T*, T*, hipStream_t);                                         \
     template hipError_t launch_rk4_stage<T>(T*, T*, const T*, T*, int, const DevDesc*, int, hipStream_t);   \
     template hipError_t launch_scale_etr<T>(T*, int, const DevDesc*, hipStream_t);                           \
+    template hipError_t launch_predict_fdm<T>(const KModel&, const DevDesc*, const double*, const T*, T*, T*, T*, \
+                                              double, hipStream_t);                                            \
     template hipError_t launch_copy<T>(T*, const T*, int, hipStream_t);
 
 PMF_INSTANTIATE(float)

@@ -15,6 +15,7 @@ namespace pmf {
 
 constexpr int MAXNX = 3;
 constexpr int MAXMIX = 4;
+constexpr double FDM_STABLE_STEP = 1.0;   // h * sum_a D_y,aa kept at or below this (explicit FDM)
 constexpr int LMAX = 4096;            // largest substep count a predict may use
 constexpr int NPART = 16;             // doubles per reduction partial
 constexpr int RED_THREADS = 256;      // threads of every reduction block
@@ -274,6 +275,7 @@ PMF_HD FftPlan make_plan(int n) {
     while (n % 4 == 0) { p.r[p.np++] = 4; n /= 4; }
     while (n % 2 == 0) { p.r[p.np++] = 2; n /= 2; }
     while (n % 3 == 0) { p.r[p.np++] = 3; n /= 3; }
+    while (n % 5 == 0 && p.np < 8) { p.r[p.np++] = 5; n /= 5; }
     if (n != 1) p.np = -1;
     return p;
 }

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_common import Pair, l1, note
+from gpu_common import Pair, l1, note, run_free, run_lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -28,43 +28,6 @@ def ctx(B):
     c = B.pmf_ctx_create(0)
     yield c
     B.pmf_ctx_destroy(c)
-
-
-def run_free(B, ctx, sc, K, tol, ll_tol=1e-9, what=""):
-    p = Pair(B, ctx, sc.model, sc.prior)
-    try:
-        p.compare(tol, what=f"{what} create")
-        for k in range(K):
-            l_o = p.predict(sc.T)
-            assert B.pmf_last_substeps(p.f) == l_o, f"{what} substeps differ at cycle {k}"
-            p.compare(tol, what=f"{what} predict {k}")
-            ll, ll_o, status = p.update(sc.z[k])
-            if np.isnan(ll_o):
-                assert np.isnan(ll), (what, k, ll)      # both reject the update
-            else:
-                assert abs(ll - ll_o) <= ll_tol * max(1.0, abs(ll_o)), (what, k, ll, ll_o)
-            p.compare(tol, what=f"{what} update {k}")
-        mean, cov, st = B.pmf_moments(p.f, sc.model.nx)
-        m_o, C_o = oracle.moments(sc.model, p.st)
-        np.testing.assert_allclose(mean, m_o, atol=1e-9 if tol < 1e-8 else 1e-4)
-        np.testing.assert_allclose(cov, C_o, atol=1e-9 if tol < 1e-8 else 1e-4)
-    finally:
-        p.close()
-
-
-def run_lockstep(B, ctx, sc, K, tol, what=""):
-    p = Pair(B, ctx, sc.model, sc.prior)
-    try:
-        for k in range(K):
-            p.inject_oracle_state()
-            p.predict(sc.T)
-            p.compare(tol, grid_rtol=1e-11, what=f"{what} predict {k}")
-            p.inject_oracle_state()
-            ll, ll_o, status = p.update(sc.z[k])
-            assert abs(ll - ll_o) <= 1e-4 * max(1.0, abs(ll_o)), (what, k, ll, ll_o)
-            p.compare(tol, grid_rtol=1e-4, what=f"{what} update {k}")
-    finally:
-        p.close()
 
 
 def test_cfg1_1d_fp64_100_cycles(B, ctx):
