@@ -113,10 +113,13 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip latency / L1 / plain-path legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain device copy of known size (counter scaling)")
-    ap.add_argument("--workload", choices=("batched", "cheb3d", "serve"), default="batched",
+    ap.add_argument("--workload", choices=("batched", "cheb3d", "serve", "single", "convergence"),
+                    default="batched",
                     help="batched: the headline batched workload (default); cheb3d: one 3-D "
                          "Chebyshev filter on a 64^3 grid (RK4 on MFMA, range measurement); serve: "
-                         "many live tracks fed by Poisson arrivals through the serving runtime")
+                         "many live tracks fed by Poisson arrivals through the serving runtime; single: "
+                         "per-op latency of one 1-D (N 64, FP64) and one 2-D (128^2, FP64 and FP32) filter; "
+                         "convergence: spectral vs finite-difference time update against the heat kernel")
     ap.add_argument("--tracks", type=int, default=10000, help="serve: live tracks")
     ap.add_argument("--rates", type=str, default="1000,2000,5000,10000,20000,50000",
                     help="serve: offered request rates (requests/s; one request = predict + update)")
@@ -131,6 +134,10 @@ def main():
         return run_cheb3d(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "single":
+        return run_single(args)
+    if args.workload == "convergence":
+        return run_convergence(args)
     return run_batched(args)
 
 
@@ -504,6 +511,157 @@ def run_serve(args):
                                    "pmf_predict + pmf_update"},
         "roofline": None, "cpu_baseline": None,
     }
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ single filters
+
+def run_single(args):
+    """Latency-bound single filters: every op is followed by a host synchronisation
+    (the host needs the result before the next measurement), as a tracker would."""
+    import numpy as np
+    import workloads as W
+    import oracle
+    from paper_2412_07240_amd import binding as B
+
+    cases = [("1-D N=64 FP64, RK4 (>= 10 substeps), T = 0.1", W.config1(K=200)),
+             ("2-D 128^2 FP64, RK4, cubic measurement, T = 0.05", W.config2(K=200, precision=W.FP64)),
+             ("2-D 128^2 FP32, RK4, cubic measurement, T = 0.05", W.config2(K=200, precision=W.FP32))]
+    ctx = B.pmf_ctx_create(0)
+    res = []
+    n_cyc = args.steps * 5
+    for name, sc in cases:
+        m = sc.model
+        pts = int(np.prod(m.N[:m.nx]))
+        f = B.pmf_create(ctx, m, sc.prior)
+        k = 0
+        for _ in range(args.warmup):
+            B.pmf_predict(f, sc.T)
+            B.pmf_update(f, sc.z[k])
+            k += 1
+        B.pmf_stream_sync()
+        tp, tu = [], []
+        t0 = time.perf_counter()
+        for _ in range(n_cyc):
+            a = time.perf_counter()
+            B.pmf_predict(f, sc.T)
+            B.pmf_stream_sync()
+            b = time.perf_counter()
+            B.pmf_update(f, sc.z[k], want_loglik=True)   # synchronises to read the log-likelihood
+            c = time.perf_counter()
+            tp.append(b - a)
+            tu.append(c - b)
+            k += 1
+        el = time.perf_counter() - t0
+        # the last cycle against the oracle from the same pre-cycle state
+        _, c0, M0, t_, P0 = B.pmf_get_state(f)
+        st = oracle.State(np.array(c0), np.array(M0), t_, np.asarray(P0, float))
+        B.pmf_predict(f, sc.T)
+        B.pmf_update(f, sc.z[k])
+        st, _ = oracle.predict(m, st, sc.T)
+        st, _, _, _, _ = oracle.update(m, st, sc.z[k])
+        _, c1, M1, _, P1 = B.pmf_get_state(f)
+        mapped = oracle.interpolate(m, oracle.State(np.array(c1), np.array(M1), st.t, np.asarray(P1, float)),
+                                    st.c, st.M)
+        l1 = float(np.sum(oracle.quadrature_weights(m, st.M) * np.abs(mapped - st.P)))
+        B.pmf_destroy(f)
+        res.append({"case": name, "points": pts, "cycles": n_cyc, "points_per_s": pts * n_cyc / el,
+                    "predict_p50_ms": 1e3 * float(np.percentile(tp, 50)),
+                    "predict_p99_ms": 1e3 * float(np.percentile(tp, 99)),
+                    "update_p50_ms": 1e3 * float(np.percentile(tu, 50)),
+                    "update_p99_ms": 1e3 * float(np.percentile(tu, 99)),
+                    "l1_vs_fp64_oracle_one_cycle": l1})
+        log(f"bench single: {json.dumps(res[-1])}")
+    B.pmf_ctx_destroy(ctx)
+    out = {
+        "metric": METRIC, "value": res[1]["points_per_s"], "unit": "grid-point updates/s", "n_gpus": 1,
+        "steps": n_cyc, "warmup": args.warmup,
+        "ms_per_step": res[1]["predict_p50_ms"] + res[1]["update_p50_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "single filters, one op at a time with a host synchronisation after each; "
+                               "value is the 2-D 128^2 FP64 case"},
+        "single": res, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ convergence study
+
+CONV_N = (16, 20, 24, 30, 32, 40, 48, 50, 60, 64, 80, 96, 100, 120, 128, 150, 160, 180, 200, 240, 250)
+
+
+def _gm_density(x, w, mu, var):
+    import numpy as np
+    return np.sum(w * np.exp(-0.5 * (x[:, None] - mu) ** 2 / var) / np.sqrt(2.0 * np.pi * var), axis=1)
+
+
+def run_convergence(args):
+    """One time update of a 1-D density without advection (A = 0, D = 1, T = 0.05)
+    on the GPU, for N over a sweep, by the spectral integrators (exact in time;
+    implicit Euler with 10 and 100 substeps, the paper's Algorithm; RK4) and by
+    the finite-difference baseline (sine-transform route; substeps at the
+    stability limit, and at a quarter of it), each against the heat kernel
+    solution at the nodes.  Densities: one Gaussian and a three-component
+    Gaussian mixture; grid half-widths of 5 and 8 standard deviations."""
+    import numpy as np
+    import workloads as W
+    from paper_2412_07240_amd import binding as B
+
+    T = 0.05
+    dens = {"gaussian": (np.array([1.0]), np.array([0.0]), np.array([0.3])),
+            "mixture3": (np.array([0.3, 0.4, 0.3]), np.array([-1.2, 0.3, 1.5]), np.array([0.15, 0.1, 0.2]))}
+    methods = {"sd_exact": (W.INT_EXACT, 1), "sd_euler_l10": (W.INT_EULER, 10),
+               "sd_euler_l100": (W.INT_EULER, 100), "sd_rk4": (W.INT_RK4, 1), "fdm_dst": (W.INT_FDM, 1),
+               "fdm_dst_r025": (W.INT_FDM, 0)}
+    ctx = B.pmf_ctx_create(0)
+    rows = []
+    for dname, (w, mu, var) in dens.items():
+        prior = W.PriorSpec(w, mu[:, None], var[:, None, None])
+        for span in (5.0, 8.0):
+            for N in CONV_N:
+                for mname, (integ, lmin) in methods.items():
+                    m = W.ModelSpec(nx=1, A=np.zeros((1, 1)), Q=np.ones((1, 1)), N=(N,), span_sigmas=span,
+                                    t_nominal=T, integrator=integ, substeps=lmin, precision=W.FP64,
+                                    meas_kind=W.H_LINEAR, nz=1, H=np.ones((1, 1)), **W.gaussian_noise([[0.01]]))
+                    if lmin == 0:
+                        # finite differences at the mesh ratio h D / delta^2 = 1/4 (time error
+                        # below the spatial one) instead of the stability limit 1
+                        f = B.pmf_create(ctx, m.with_(substeps=1), prior)
+                        _, _, M0, _, _ = B.pmf_get_state(f)
+                        B.pmf_destroy(f)
+                        m = m.with_(substeps=int(np.ceil(4.0 * T / M0[0][0] ** 2)))
+                    f = B.pmf_create(ctx, m, prior)
+                    B.pmf_predict(f, T)
+                    l = B.pmf_last_substeps(f)
+                    _, c, M, _, P = B.pmf_get_state(f)
+                    B.pmf_destroy(f)
+                    x = c[0] + M[0][0] * (np.arange(N) - N // 2)
+                    ex = _gm_density(x, w, mu, var + T)
+                    err = np.asarray(P, float) - ex
+                    rows.append({"density": dname, "span": span, "N": N, "method": mname, "substeps": l,
+                                 "max_rel_err": float(np.max(np.abs(err)) / np.max(ex)),
+                                 "l1_err": float(abs(M[0][0]) * np.sum(np.abs(err)))})
+    B.pmf_ctx_destroy(ctx)
+    # slope of log(error) against log(N) for the finite differences (second order: -2)
+    slopes = {}
+    for dname in dens:
+        for span in (5.0, 8.0):
+            for meth in ("fdm_dst", "fdm_dst_r025"):
+                sel = [r for r in rows if r["density"] == dname and r["span"] == span and r["method"] == meth
+                       and r["N"] >= 100]
+                sl = np.polyfit(np.log([r["N"] for r in sel]), np.log([r["max_rel_err"] for r in sel]), 1)[0]
+                slopes[f"{dname}_span{span:g}_{meth}"] = float(sl)
+    at = {f"{r['density']}_span{r['span']:g}_{r['method']}_N{r['N']}": r["max_rel_err"]
+          for r in rows if r["N"] in (80, 200)}
+    out = {"metric": "max relative error of one time update vs the heat kernel", "value": None,
+           "unit": "relative error", "n_gpus": 1, "steps": len(rows), "warmup": 0, "ms_per_step": None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "1-D, A = 0, D = 1, T = 0.05; Gaussian N(0, 0.3) and mixture "
+                                  "0.3 N(-1.2, 0.15) + 0.4 N(0.3, 0.1) + 0.3 N(1.5, 0.2); spans 5 and 8 sigma",
+                      "N": list(CONV_N)},
+           "fdm_slope_N100_up": slopes, "at_N80_N200": at, "rows": rows,
+           "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
