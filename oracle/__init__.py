@@ -13,7 +13,8 @@ Every routine follows a definition of the paper written out directly:
 * the moving-grid Fokker-Planck equation of Sec. II.B (eqs. movFPEadv, easyFPE),
   integrated in physical grid space by classic RK4 (method of lines), or by the
   implicit Euler step of Sec. V.A, or exactly (a per-mode exponential), or by
-  the explicit finite-difference baseline of eq. FDM (step matrices of eq. fdiff);
+  the explicit finite-difference baseline of eq. FDM (step matrices of eq. fdiff),
+  or a sine-series variant of the spectral update (exact zero boundary values);
 * Chebyshev differentiation (Sec. IV.B) on Chebyshev-Gauss-Lobatto nodes;
 * the Bayes rule of Sec. I.A (eq. filt) applied point by point, with the
   normalisation of Sec. III.A (eq. PDF_pm).

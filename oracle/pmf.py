@@ -24,7 +24,7 @@ from . import fourier as fou
 from . import linear as lin
 
 FOURIER, CHEBYSHEV = 0, 1
-INT_EXACT, INT_RK4, INT_EULER, INT_FDM = 0, 1, 2, 3
+INT_EXACT, INT_RK4, INT_EULER, INT_FDM, INT_SINE = 0, 1, 2, 3, 4
 INTERP_AUTO, INTERP_LAGRANGE = 0, 1
 H_LINEAR, H_CUBIC1, H_NORM = 0, 1, 2
 
@@ -235,6 +235,13 @@ def fdm_step_matrix(n: int, a_t: float, b_t: float) -> np.ndarray:
     return b_t * np.eye(n) + a_t * (np.eye(n, k=1) + np.eye(n, k=-1))
 
 
+def sine_matrix(n: int) -> np.ndarray:
+    """S[i, l] = sin((i + 1)(l + 1) pi / (n + 1)): the sine modes of n interior
+    nodes with zeros beyond both ends (S S = (n + 1)/2 I)."""
+    j = np.arange(1, n + 1)
+    return np.sin(np.outer(j, j) * np.pi / (n + 1))
+
+
 def _operators(model):
     ops = []
     for a in range(model.nx):
@@ -304,6 +311,28 @@ def predict(model, state: State, T: float):
                 for a in range(model.nx):
                     rhs = rhs + 0.5 * Dy[a, a] * fou.apply_along(L2[a], P, a)
                 P = P + h * rhs
+        elif model.integrator == INT_SINE:
+            # sine-series variant of the spectral update: expand P in the sine modes
+            # of the grid with zeros beyond both ends (exact Dirichlet boundary); mode
+            # l_a has the second-derivative symbol -(l_a pi / (N_a + 1))^2 in index
+            # units and decays exactly by exp(-1/2 sum_a Wy_aa k_a^2)
+            if np.any(A != np.diag(np.diag(A))) or np.any(D != np.diag(np.diag(D))):
+                raise ValueError("the sine-series variant needs diagonal A and D")
+            Wy = np.linalg.inv(M0) @ lin.W_integral(A, D, T) @ np.linalg.inv(M0).T
+            coef = P
+            for a in range(model.nx):
+                n = model.N[a]
+                coef = fou.apply_along(sine_matrix(n) * (2.0 / (n + 1)), coef, a)
+            g = np.ones(P.shape)
+            for a in range(model.nx):
+                n = model.N[a]
+                k = np.arange(1, n + 1) * np.pi / (n + 1)
+                shape = [1] * model.nx
+                shape[a] = n
+                g = g * np.exp(-0.5 * Wy[a, a] * k ** 2).reshape(shape)
+            P = g * coef
+            for a in range(model.nx):
+                P = fou.apply_along(sine_matrix(model.N[a]), P, a)
         elif model.integrator == INT_EULER:
             # implicit diffusion per substep (Sec. V.A): P_{n+1} = P_n / (1 - q/2 dt c''_n),
             # with c'' = -kappa^2 <= 0 and the diffusion taken at t_n, n = 0..l-1.

@@ -146,3 +146,57 @@ def test_spectral_exact_integrator_outruns_fdm():
         e_sd, _ = _heat_case(64, W.INT_EXACT, mixture, span=6.0)
         e_fd, _ = _heat_case(64, W.INT_FDM, mixture, span=6.0)
         assert e_sd < 1e-8 and e_fd > 1e-4, (mixture, e_sd, e_fd)
+
+
+# ------------------------------------------------ sine-series variant of the spectral update
+
+def _sine_model(A, Q, N):
+    nx = len(N)
+    return W.ModelSpec(nx=nx, A=A, Q=Q, N=N, t_nominal=0.1, integrator=W.INT_SINE, substeps=1,
+                       precision=W.FP64, meas_kind=W.H_LINEAR, nz=nx, H=np.eye(nx),
+                       **W.gaussian_noise(0.01 * np.eye(nx)))
+
+
+def test_sine_modes_decay_exactly():
+    # a product of sine modes is an eigenfunction: it decays by exp(-1/2 sum_a Wy_aa k_a^2)
+    # times e^{-tr(A) T}, with W(T)_aa = D_aa (1 - e^{-2 a T}) / (2 a) for diagonal A
+    A = np.diag([-0.7, -0.2])
+    Q = np.diag([0.9, 0.4])
+    N = (24, 18)
+    d0 = np.array([0.2, 0.3])
+    T = 0.07
+    l0, l1 = 5, 11
+    i0, i1 = np.arange(1, N[0] + 1), np.arange(1, N[1] + 1)
+    P = np.outer(np.sin(i0 * l0 * np.pi / (N[0] + 1)), np.sin(i1 * l1 * np.pi / (N[1] + 1)))
+    st = oracle.State(np.zeros(2), np.diag(d0), 0.0, P)
+    out, _ = oracle.predict(_sine_model(A, Q, N), st, T)
+    a = np.diag(A)
+    Wd = np.diag(Q) ** 2 * (1.0 - np.exp(-2.0 * a * T)) / (2.0 * a)
+    Wy = Wd / d0 ** 2
+    k = np.array([l0 * np.pi / (N[0] + 1), l1 * np.pi / (N[1] + 1)])
+    g = math.exp(-np.trace(A) * T) * math.exp(-0.5 * float(np.sum(Wy * k ** 2)))
+    np.testing.assert_allclose(out.P, g * P, rtol=0, atol=1e-13)
+
+
+def test_sine_variant_equals_library_dst_route():
+    A = np.diag([-0.3])
+    Q = np.diag([0.8])
+    N = (37,)
+    rng = np.random.default_rng(9)
+    P = rng.uniform(0, 1, size=N)
+    d0 = 0.11
+    T = 0.02
+    out, _ = oracle.predict(_sine_model(A, Q, N), oracle.State(np.zeros(1), np.array([[d0]]), 0.0, P), T)
+    Wy = 0.64 * (1.0 - math.exp(0.6 * T)) / (-0.6) / d0 ** 2
+    k = np.arange(1, N[0] + 1) * np.pi / (N[0] + 1)
+    g = math.exp(0.3 * T) * np.exp(-0.5 * Wy * k ** 2)
+    ref = scipy.fft.dst(g * scipy.fft.dst(P, type=1), type=1) / (2.0 * (N[0] + 1))
+    np.testing.assert_allclose(out.P, ref, rtol=0, atol=1e-13)
+
+
+def test_sine_variant_matches_heat_kernel_on_a_wide_grid():
+    # a Gaussian negligible at the grid ends: the Dirichlet problem and the free one
+    # coincide to rounding, and the sine series resolves it spectrally
+    errs = [_heat_case(N, W.INT_SINE, True, span=8.0)[0] for N in (48, 64, 80, 128)]
+    assert errs[0] > errs[1] * 50 > errs[2] * 50 ** 2     # geometric, not algebraic
+    assert errs[3] < 1e-13, errs

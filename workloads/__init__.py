@@ -23,7 +23,7 @@ SEED_ROOT = 241207240
 
 # grid kinds, integrators, interpolation modes, measurement kinds, precisions
 FOURIER, CHEBYSHEV = 0, 1
-INT_EXACT, INT_RK4, INT_EULER, INT_FDM = 0, 1, 2, 3
+INT_EXACT, INT_RK4, INT_EULER, INT_FDM, INT_SINE = 0, 1, 2, 3, 4
 INTERP_AUTO, INTERP_LAGRANGE = 0, 1
 H_LINEAR, H_CUBIC1, H_NORM = 0, 1, 2
 FP64, FP32 = 0, 1
