@@ -598,7 +598,8 @@ def _gm_density(x, w, mu, var):
 def run_convergence(args):
     """One time update of a 1-D density without advection (A = 0, D = 1, T = 0.05)
     on the GPU, for N over a sweep, by the spectral integrators (exact in time;
-    implicit Euler with 10 and 100 substeps, the paper's Algorithm; RK4) and by
+    its sine-series variant, exact in time; implicit Euler with 10 and 100
+    substeps, the paper's Algorithm; RK4) and by
     the finite-difference baseline (sine-transform route; substeps at the
     stability limit, and at a quarter of it), each against the heat kernel
     solution at the nodes.  Densities: one Gaussian and a three-component
@@ -610,7 +611,7 @@ def run_convergence(args):
     T = 0.05
     dens = {"gaussian": (np.array([1.0]), np.array([0.0]), np.array([0.3])),
             "mixture3": (np.array([0.3, 0.4, 0.3]), np.array([-1.2, 0.3, 1.5]), np.array([0.15, 0.1, 0.2]))}
-    methods = {"sd_exact": (W.INT_EXACT, 1), "sd_euler_l10": (W.INT_EULER, 10),
+    methods = {"sd_exact": (W.INT_EXACT, 1), "sd_sine": (W.INT_SINE, 1), "sd_euler_l10": (W.INT_EULER, 10),
                "sd_euler_l100": (W.INT_EULER, 100), "sd_rk4": (W.INT_RK4, 1), "fdm_dst": (W.INT_FDM, 1),
                "fdm_dst_r025": (W.INT_FDM, 0)}
     ctx = B.pmf_ctx_create(0)

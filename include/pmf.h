@@ -58,7 +58,7 @@ typedef enum {
 } pmf_status;
 
 enum { PMF_GRID_FOURIER = 0, PMF_GRID_CHEBYSHEV = 1 };
-enum { PMF_INT_EXACT = 0, PMF_INT_RK4 = 1, PMF_INT_EULER = 2, PMF_INT_FDM = 3 };
+enum { PMF_INT_EXACT = 0, PMF_INT_RK4 = 1, PMF_INT_EULER = 2, PMF_INT_FDM = 3, PMF_INT_SINE = 4 };
 enum { PMF_INTERP_AUTO = 0, PMF_INTERP_LAGRANGE = 1 };
 enum { PMF_H_LINEAR = 0, PMF_H_CUBIC1 = 1, PMF_H_NORM = 2 };
 enum { PMF_FP64 = 0, PMF_FP32 = 1 };
@@ -83,7 +83,7 @@ typedef struct {
                                    Chebyshev: 4..256 */
     double span_sigmas;         /* grid half-width in standard deviations (e.g. 8) */
     double t_nominal;           /* interval used by the grid design, > 0 */
-    int integrator;             /* PMF_INT_EXACT | PMF_INT_RK4 | PMF_INT_EULER | PMF_INT_FDM
+    int integrator;             /* PMF_INT_EXACT | _RK4 | _EULER | _FDM | _SINE
                                    (Chebyshev grids: RK4 only) */
     int substeps;               /* minimum number of substeps l (>= 1) */
     int precision;              /* PMF_FP64 or PMF_FP32 density; reductions are FP64 */
@@ -156,7 +156,12 @@ void pmf_destroy(pmf_filter* f);
  *           1 - h tr(A) + h sum_a D_y,aa(t_n) (cos(j_a pi / (N_a + 1)) - 1),
  *           DST-I back.  Needs diagonal A and D (Fourier grid; the designed
  *           grids are axis-aligned, so D_y stays diagonal);
- *           l = max(substeps, ceil(T max_t sum_a D_y,aa(t))) at t = 0, T/2, T.  Mixed derivatives use the
+ *           l = max(substeps, ceil(T max_t sum_a D_y,aa(t))) at t = 0, T/2, T.
+ *   sine:   the sine-series variant of the spectral update (the non-periodic
+ *           alternative named in Sec. IV's notes): DST-I along every axis, each
+ *           sine mode times exp(-1/2 sum_a W_y,aa k_a^2) e^{-tr(A) T} with
+ *           k_a = j_a pi / (N_a + 1) (exact in time, zero beyond both grid ends),
+ *           DST-I back.  Diagonal A and D, Fourier grid, as fdm.  Mixed derivatives use the
  * first-derivative symbol (no Nyquist term), squares keep it (eq. secDer).
  * Chebyshev grids: classic RK4 with dense differentiation matrices.
  * RK4 uses l = max(substeps, ceil(T lambda_max / 2.5)) substeps; lambda_max bounds

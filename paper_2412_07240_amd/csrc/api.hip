@@ -174,15 +174,16 @@ static pmf_status validate_model(const pmf_model* m) {
         ntot *= n;
     }
     if (ntot > (1L << 24)) return fail(PMF_E_INVALID, "grid larger than 2^24 points");
-    if (m->integrator < 0 || m->integrator > 3) return fail(PMF_E_INVALID, "unknown integrator");
-    if (m->integrator == PMF_INT_FDM) {
-        if (m->grid != PMF_GRID_FOURIER) return fail(PMF_E_INVALID, "the finite-difference baseline needs a Fourier grid");
+    if (m->integrator < 0 || m->integrator > 4) return fail(PMF_E_INVALID, "unknown integrator");
+    if (m->integrator == PMF_INT_FDM || m->integrator == PMF_INT_SINE) {
+        if (m->grid != PMF_GRID_FOURIER)
+            return fail(PMF_E_INVALID, "the finite-difference and sine-series forms need a Fourier grid");
         double Dm[9];
         diffusion(*m, Dm);
         for (int i = 0; i < m->nx; ++i)
             for (int j = 0; j < m->nx; ++j)
                 if (i != j && (m->A[i * m->nx + j] != 0.0 || Dm[i * 3 + j] != 0.0))
-                    return fail(PMF_E_INVALID, "the finite-difference baseline needs diagonal A and D");
+                    return fail(PMF_E_INVALID, "the finite-difference and sine-series forms need diagonal A and D");
     }
     if (m->grid == PMF_GRID_CHEBYSHEV && m->integrator != PMF_INT_RK4)
         return fail(PMF_E_INVALID, "Chebyshev grids support the RK4 integrator only");
@@ -362,7 +363,8 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     f->W = static_cast<double*>(A((size_t)model->nx * f->km.wstride * sizeof(double)));
     f->tab = static_cast<double*>(A((size_t)3 * TAB_STRIDE * sizeof(double)));
     f->desc = static_cast<DevDesc*>(A(sizeof(DevDesc)));
-    if (model->integrator == PMF_INT_FDM) f->D1 = A((size_t)3 * 256 * 256 * f->es);   // DST-I matrices
+    if (model->integrator == PMF_INT_FDM || model->integrator == PMF_INT_SINE)
+        f->D1 = A((size_t)3 * 256 * 256 * f->es);   // DST-I matrices
     if (model->grid == PMF_GRID_CHEBYSHEV) {
         f->D1 = A((size_t)3 * 256 * 256 * f->es);
         f->D2 = A((size_t)3 * 256 * 256 * f->es);
@@ -382,7 +384,7 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
         pmf_destroy(f);
         return hip_fail(e, "upload tables");
     }
-    if (model->integrator == PMF_INT_FDM) {
+    if (model->integrator == PMF_INT_FDM || model->integrator == PMF_INT_SINE) {
         std::vector<double> sall((size_t)3 * 256 * 256, 0.0);
         for (int a = 0; a < model->nx; ++a) {
             const int n = model->N[a];
@@ -504,7 +506,8 @@ pmf_status pmf_predict(pmf_filter* f, double T, void* stream) {
     const PredictArgs& pa = predict_args(f, T);
     e = launch_plan(pa, f->desc, f->coef, st);
     if (e != hipSuccess) return hip_fail(e, "plan");
-    if (f->model.integrator == PMF_INT_FDM) {
+    if (f->model.integrator == PMF_INT_FDM || f->model.integrator == PMF_INT_SINE) {
+        const int sine = f->model.integrator == PMF_INT_SINE ? 1 : 0;
         double trA = 0.0;
         for (int i = 0; i < f->model.nx; ++i) trA += pa.A[i * 3 + i];
         void* t1 = f->buf[(f->cur + 1) % 4];
@@ -512,11 +515,11 @@ pmf_status pmf_predict(pmf_filter* f, double T, void* stream) {
         if (f->es == sizeof(double))
             e = launch_predict_fdm<double>(f->km, f->desc, f->coef, static_cast<const double*>(f->D1),
                                            static_cast<double*>(f->buf[f->cur]), static_cast<double*>(t1),
-                                           static_cast<double*>(t2), trA, st);
+                                           static_cast<double*>(t2), trA, sine, st);
         else
             e = launch_predict_fdm<float>(f->km, f->desc, f->coef, static_cast<const float*>(f->D1),
                                           static_cast<float*>(f->buf[f->cur]), static_cast<float*>(t1),
-                                          static_cast<float*>(t2), trA, st);
+                                          static_cast<float*>(t2), trA, sine, st);
         if (e != hipSuccess) return hip_fail(e, "predict (finite differences)");
         return PMF_OK;
     }

@@ -1278,6 +1278,8 @@ bool batch_fusable(const pmf_filter* f, std::string* why) {
     const pmf_model& m = f->model;
     if (m.grid != PMF_GRID_FOURIER) return *why = "Chebyshev grid", false;
     if (m.precision != PMF_FP32) return *why = "FP64 density", false;
+    if (m.integrator == PMF_INT_FDM || m.integrator == PMF_INT_SINE)
+        return *why = "finite-difference or sine-series time update", false;
     if (m.nx > 2) return *why = "nx > 2", false;
     if (m.nx == 2 && (m.N[0] > 128 || m.N[1] > 128)) return *why = "2-D N above 128", false;
     if (m.nx == 1 && m.N[0] > 256) return *why = "1-D N above 256", false;

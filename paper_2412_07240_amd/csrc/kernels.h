@@ -47,11 +47,12 @@ hipError_t launch_rk4_stage(T* q, T* y, const T* kf, T* acc, int ntot, const Dev
 template <typename T>
 hipError_t launch_scale_etr(T* q, int ntot, const DevDesc* d, hipStream_t st);
 
-// finite-difference baseline by the sine-transform route (S: DST-I matrices per
-// axis, 256 x 256 stride); t1, t2: two scratch densities; result in X
+// finite-difference baseline by the sine-transform route, or (sine != 0) the
+// sine-series variant of the spectral update (S: DST-I matrices per axis, 256 x
+// 256 stride); t1, t2: two scratch densities; result in X
 template <typename T>
 hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, const T* S, T* X, T* t1, T* t2,
-                              double trA, hipStream_t st);
+                              double trA, int sine, hipStream_t st);
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int ntot, hipStream_t st);
 

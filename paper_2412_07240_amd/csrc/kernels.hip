@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
         }
         s_l = l;
         const double h = a.T / l;
-        if (a.integ == PMF_INT_EXACT) {
+        if (a.integ == PMF_INT_EXACT || a.integ == PMF_INT_SINE) {
             double Wy[9];
             sandwich_inv(Wy, Mi, a.W, n);
             pack_sym(coef, Wy);
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
         d->etr = a.etr;
     }
     __syncthreads();
-    if (a.integ != PMF_INT_EXACT) {
+    if (a.integ != PMF_INT_EXACT && a.integ != PMF_INT_SINE) {
         const int l = s_l;
         const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
         for (int k = threadIdx.x; k < cnt; k += PLAN_THREADS) {
@@ -1139,8 +1139,11 @@ hipError_t launch_copy(T* dst, const T* src, int ntot, hipStream_t st) {
 // of the eigenvalues of the explicit step, times prod_a 2 / (N_a + 1) (R^-1 =
 // 2/(N+1) R), then S_a again.
 
+// sine: the sine-series variant of the spectral update instead: each sine mode
+// decays by exp(-1/2 sum_a Wy_aa k_a^2) e^{-tr(A) T}, k_a = (i_a + 1) pi / (N_a + 1)
+// (coef holds W_y packed 00, 11, 22, ... as for the exact integrator)
 template <typename T>
-__global__ void k_fdm_gain(T* X, KModel m, const DevDesc* d, const double* coef, double trA) {
+__global__ void k_fdm_gain(T* X, KModel m, const DevDesc* d, const double* coef, double trA, int sine) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m.ntot) return;
     double cm1[3] = {0.0, 0.0, 0.0};   // cos(theta_a) - 1
@@ -1152,21 +1155,33 @@ __global__ void k_fdm_gain(T* X, KModel m, const DevDesc* d, const double* coef,
         cm1[a] = cospi((double)(ia + 1) / (double)(m.N[a] + 1)) - 1.0;
         norm *= 2.0 / (double)(m.N[a] + 1);
     }
-    const int l = d->l;
-    const double h = d->h;
     double g = norm;
-    for (int n = 0; n < l; ++n) {
-        const double* c = coef + 6 * n;   // packed 00, 11, 22, ...
-        double lam = 1.0 - h * trA;
-        for (int a = 0; a < m.nx; ++a) lam += h * c[a] * cm1[a];
-        g *= lam;
+    if (sine) {
+        double q = 0.0;
+        rem = j;
+        for (int a = m.nx - 1; a >= 0; --a) {
+            const int ia = rem % m.N[a];
+            rem /= m.N[a];
+            const double k = M_PI * (double)(ia + 1) / (double)(m.N[a] + 1);
+            q += coef[a] * k * k;
+        }
+        g *= d->etr * exp(-0.5 * q);
+    } else {
+        const int l = d->l;
+        const double h = d->h;
+        for (int n = 0; n < l; ++n) {
+            const double* c = coef + 6 * n;   // packed 00, 11, 22, ...
+            double lam = 1.0 - h * trA;
+            for (int a = 0; a < m.nx; ++a) lam += h * c[a] * cm1[a];
+            g *= lam;
+        }
     }
     X[j] = (T)((double)X[j] * g);
 }
 
 template <typename T>
 hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, const T* S, T* X, T* t1, T* t2,
-                              double trA, hipStream_t st) {
+                              double trA, int sine, hipStream_t st) {
     const int g = cdiv(m.ntot, 256);
     int strides[3];
     for (int a = 0; a < m.nx; ++a) {
@@ -1181,7 +1196,7 @@ hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* c
                            strides[a], m.ntot, coef, -1, 1.0, 0);
         cur = dst;
     }
-    hipLaunchKernelGGL(k_fdm_gain<T>, dim3(g), dim3(256), 0, st, cur, m, d, coef, trA);
+    hipLaunchKernelGGL(k_fdm_gain<T>, dim3(g), dim3(256), 0, st, cur, m, d, coef, trA, sine);
     for (int a = 0; a < m.nx; ++a) {
         T* dst = (a == m.nx - 1) ? X : ((cur == t1) ? t2 : t1);
         hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, S + (size_t)a * 256 * 256, cur, dst, m.N[a],
@@ -1205,7 +1220,7 @@ hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* c
     template hipError_t launch_rk4_stage<T>(T*, T*, const T*, T*, int, const DevDesc*, int, hipStream_t);   \
     template hipError_t launch_scale_etr<T>(T*, int, const DevDesc*, hipStream_t);                           \
     template hipError_t launch_predict_fdm<T>(const KModel&, const DevDesc*, const double*, const T*, T*, T*, T*, \
-                                              double, hipStream_t);                                            \
+                                              double, int, hipStream_t);                                       \
     template hipError_t launch_copy<T>(T*, const T*, int, hipStream_t);
 
 PMF_INSTANTIATE(float)
