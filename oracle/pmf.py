@@ -26,7 +26,7 @@ from . import linear as lin
 FOURIER, CHEBYSHEV = 0, 1
 INT_EXACT, INT_RK4, INT_EULER, INT_FDM, INT_SINE = 0, 1, 2, 3, 4
 INTERP_AUTO, INTERP_LAGRANGE = 0, 1
-H_LINEAR, H_CUBIC1, H_NORM = 0, 1, 2
+H_LINEAR, H_CUBIC1, H_NORM, H_TERRAIN = 0, 1, 2, 3
 
 STATUS_OK = 0
 STATUS_DEGENERATE = 4
@@ -159,6 +159,14 @@ def measurement(model, X: np.ndarray) -> np.ndarray:
         return (model.hparam[0] * x1 + model.hparam[1] * x1 ** 3)[..., None]
     if model.meas_kind == H_NORM:
         return np.sqrt(np.sum(X * X, axis=-1))[..., None]
+    if model.meas_kind == H_TERRAIN:
+        # the terrain map of Sec. VI as an analytic function of the state:
+        # sum over components m of a_m cos(w_m . x + phi_m)
+        out = np.zeros(X.shape[:-1])
+        for row in np.asarray(model.terrain, float):
+            a, phi, w = row[0], row[1], row[2:2 + X.shape[-1]]
+            out = out + a * np.cos(X @ w + phi)
+        return out[..., None]
     raise ValueError(model.meas_kind)
 
 

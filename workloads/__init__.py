@@ -25,7 +25,7 @@ SEED_ROOT = 241207240
 FOURIER, CHEBYSHEV = 0, 1
 INT_EXACT, INT_RK4, INT_EULER, INT_FDM, INT_SINE = 0, 1, 2, 3, 4
 INTERP_AUTO, INTERP_LAGRANGE = 0, 1
-H_LINEAR, H_CUBIC1, H_NORM = 0, 1, 2
+H_LINEAR, H_CUBIC1, H_NORM, H_TERRAIN = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 
 
@@ -50,6 +50,8 @@ class ModelSpec:
     noise_w: np.ndarray = field(default_factory=lambda: np.ones(1))
     noise_mean: np.ndarray = field(default_factory=lambda: np.zeros((1, 1)))
     noise_cov: np.ndarray = field(default_factory=lambda: np.eye(1))
+    # H_TERRAIN: rows (a_m, phi_m, w_m[0..nx)), h(x) = sum_m a_m cos(w_m . x + phi_m)
+    terrain: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
 
     @property
     def D(self) -> np.ndarray:
@@ -107,6 +109,9 @@ def _h(model: ModelSpec, x: np.ndarray) -> np.ndarray:
         return np.array([model.hparam[0] * x[0] + model.hparam[1] * x[0] ** 3])
     if model.meas_kind == H_NORM:
         return np.array([np.sqrt(np.sum(x * x))])
+    if model.meas_kind == H_TERRAIN:
+        t = np.asarray(model.terrain, float)
+        return np.array([np.sum(t[:, 0] * np.cos(t[:, 2:] @ x + t[:, 1]))])
     raise ValueError(model.meas_kind)
 
 
@@ -187,6 +192,49 @@ def config3(K: int = 200, N: int = 64, precision: int = FP32) -> Scenario:
                       integrator=INT_RK4, substeps=1, precision=precision,
                       meas_kind=H_NORM, nz=1, **gaussian_noise([[0.1 ** 2]]))
     return simulate(model, prior, T, K, rng)
+
+
+def synthetic_terrain(rng: np.random.Generator, centre, n: int = 6, wavelengths=(150.0, 900.0),
+                      amplitudes=(2.0, 8.0)) -> np.ndarray:
+    """A smooth terrain map over the horizontal position (state components 0 and 2
+    of the coordinated-turn state): n cosines with random directions, wavelengths
+    and amplitudes, in the terrain-function form of ModelSpec.terrain.  Stands in
+    for the SRTM table of the paper's experiment (not available)."""
+    rows = []
+    for _ in range(n):
+        lam = rng.uniform(*wavelengths)
+        th = rng.uniform(0.0, 2.0 * np.pi)
+        k = 2.0 * np.pi / lam
+        a = rng.uniform(*amplitudes)
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        wx, wy = k * np.cos(th), k * np.sin(th)
+        # phase referred to the region's centre keeps the FP64 argument small
+        rows.append([a, phi - wx * centre[0] - wy * centre[1], wx, 0.0, wy, 0.0])
+    return np.array(rows)
+
+
+CT_TURN_RATE = np.pi / 6.0          # 30 degrees per second
+CT_PRIOR_MEAN = np.array([36569.0, 50.0, 55581.0, 50.0])
+CT_PRIOR_COV = np.diag([90.0, 160.0, 5.0, 5.0])
+
+
+def config6(K: int = 20, N: int = 34, precision: int = FP64, mc: int = 0,
+            integrator: int = INT_EXACT) -> Scenario:
+    """4-D coordinated turn with known turn rate (Sec. VI): state (p_x, v_x, p_y,
+    v_y), D = diag(0, 1, 0, 1), T_s = 1, the paper's prior, a synthetic terrain
+    measurement of the horizontal position with the two-component noise
+    0.5 N(0, 1) + 0.5 N(20, 1); N_pa points per axis.  The terrain is the same for
+    every Monte-Carlo run; mc selects the truth and measurement draws."""
+    al = CT_TURN_RATE
+    A = np.array([[0.0, 1.0, 0.0, 0.0], [0.0, 0.0, 0.0, -al], [0.0, 0.0, 0.0, 1.0], [0.0, al, 0.0, 0.0]])
+    Q = np.diag([0.0, 1.0, 0.0, 1.0])
+    terr = synthetic_terrain(rng_for(7, 0), (CT_PRIOR_MEAN[0], CT_PRIOR_MEAN[2]))
+    model = ModelSpec(nx=4, A=A, Q=Q, N=(N,) * 4, t_nominal=1.0, integrator=integrator, substeps=1,
+                      precision=precision, meas_kind=H_TERRAIN, nz=1, terrain=terr,
+                      noise_w=np.array([0.5, 0.5]), noise_mean=np.array([[0.0], [20.0]]),
+                      noise_cov=np.array([[[1.0]], [[1.0]]]))
+    prior = gaussian_prior(CT_PRIOR_MEAN, CT_PRIOR_COV)
+    return simulate(model, prior, 1.0, K, rng_for(7, 1 + mc))
 
 
 BATCH_SIZES = (32, 48, 64, 96, 128)
