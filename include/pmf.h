@@ -60,11 +60,12 @@ typedef enum {
 enum { PMF_GRID_FOURIER = 0, PMF_GRID_CHEBYSHEV = 1 };
 enum { PMF_INT_EXACT = 0, PMF_INT_RK4 = 1, PMF_INT_EULER = 2, PMF_INT_FDM = 3, PMF_INT_SINE = 4 };
 enum { PMF_INTERP_AUTO = 0, PMF_INTERP_LAGRANGE = 1 };
-enum { PMF_H_LINEAR = 0, PMF_H_CUBIC1 = 1, PMF_H_NORM = 2 };
+enum { PMF_H_LINEAR = 0, PMF_H_CUBIC1 = 1, PMF_H_NORM = 2, PMF_H_TERRAIN = 3 };
 enum { PMF_FP64 = 0, PMF_FP32 = 1 };
 
-#define PMF_MAX_NX 3
+#define PMF_MAX_NX 4
 #define PMF_MAX_MIX 4
+#define PMF_MAX_TERRAIN 8
 
 typedef struct {
     /* alloc(bytes, user, stream) -> device pointer or NULL; free(ptr, user, stream) */
@@ -75,12 +76,12 @@ typedef struct {
 
 /* Model of one filter (Sec. I, eqs. dynam/meas). */
 typedef struct {
-    int nx;                     /* state dimension, 1..3 */
-    double A[9];                /* row-major nx x nx drift matrix */
-    double Q[9];                /* row-major nx x nx noise gain; D = Q Q^T */
+    int nx;                     /* state dimension, 1..4 (Chebyshev grids: 1..3) */
+    double A[16];               /* row-major nx x nx drift matrix */
+    double Q[16];               /* row-major nx x nx noise gain; D = Q Q^T */
     int grid;                   /* PMF_GRID_FOURIER or PMF_GRID_CHEBYSHEV */
-    int N[3];                   /* points per axis.  Fourier: even, 2^a 3^b 5^c, 4..256.
-                                   Chebyshev: 4..256 */
+    int N[4];                   /* points per axis.  Fourier: even, 2^a 3^b 5^c 17^d,
+                                   4..256.  Chebyshev: 4..256 */
     double span_sigmas;         /* grid half-width in standard deviations (e.g. 8) */
     double t_nominal;           /* interval used by the grid design, > 0 */
     int integrator;             /* PMF_INT_EXACT | _RK4 | _EULER | _FDM | _SINE
@@ -92,10 +93,16 @@ typedef struct {
                                    axis aligned, else cubic Lagrange; PMF_INTERP_LAGRANGE:
                                    always cubic Lagrange */
     int meas_kind;              /* PMF_H_LINEAR: h = H x;  PMF_H_CUBIC1: h = a1 x1 + a3 x1^3
-                                   (hparam[0], hparam[1]);  PMF_H_NORM: h = ||x|| */
-    int nz;                     /* measurement dimension (1 for CUBIC1 and NORM), 1..3 */
-    double H[9];                /* row-major nz x nx (PMF_H_LINEAR) */
+                                   (hparam[0], hparam[1]);  PMF_H_NORM: h = ||x||;
+                                   PMF_H_TERRAIN: a smooth synthetic terrain map,
+                                   h = sum_m a_m cos(w_m . x + phi_m) (the table
+                                   function of Sec. VI replaced by an analytic one) */
+    int nz;                     /* measurement dimension (1 for CUBIC1, NORM, TERRAIN), 1..3 */
+    double H[12];               /* row-major nz x nx (PMF_H_LINEAR) */
     double hparam[4];
+    int nterrain;               /* PMF_H_TERRAIN: components, 1..PMF_MAX_TERRAIN */
+    double terrain[PMF_MAX_TERRAIN * 6];   /* component m at terrain[6m]: a_m, phi_m,
+                                              w_m[0..nx) */
     int noise_ncomp;            /* Gaussian-mixture components of v, 1..4 */
     double noise_w[4];          /* weights (normalised by the library) */
     double noise_mean[4 * 3];   /* component g: noise_mean[3g .. 3g+nz) */
@@ -106,20 +113,19 @@ typedef struct {
 typedef struct {
     int ncomp;                  /* 1..4 */
     double w[4];
-    double mean[4 * 3];         /* component g at mean[3g] */
-    double cov[4 * 9];          /* component g: row-major nx x nx at cov[9g] */
+    double mean[4 * 4];         /* component g at mean[4g] */
+    double cov[4 * 16];         /* component g: row-major nx x nx at cov[16g] */
 } pmf_prior;
 
 /* Header of the host image written by pmf_get_state; the density follows it
  * (prod(N) values of the filter's precision, C order). */
 typedef struct {
     unsigned int magic;         /* PMF_STATE_MAGIC */
-    int version;                /* 1 */
+    int version;                /* 2 */
     int nx, grid, precision, status;
-    int N[3];
-    int pad;
-    double c[3];
-    double M[9];                /* row-major */
+    int N[4];
+    double c[4];
+    double M[16];               /* row-major, row stride 4 */
     double t;
 } pmf_state_header;
 #define PMF_STATE_MAGIC 0x504d4631u

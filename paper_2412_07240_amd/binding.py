@@ -21,26 +21,31 @@ PMF_FP64, PMF_FP32 = 0, 1
 PMF_STATE_MAGIC = 0x504D4631
 
 
+PMF_MAX_NX, PMF_MAX_TERRAIN = 4, 8
+PMF_H_TERRAIN = 3
+
+
 class pmf_model(C.Structure):
     _fields_ = [
-        ("nx", C.c_int), ("A", C.c_double * 9), ("Q", C.c_double * 9), ("grid", C.c_int),
-        ("N", C.c_int * 3), ("span_sigmas", C.c_double), ("t_nominal", C.c_double),
+        ("nx", C.c_int), ("A", C.c_double * 16), ("Q", C.c_double * 16), ("grid", C.c_int),
+        ("N", C.c_int * 4), ("span_sigmas", C.c_double), ("t_nominal", C.c_double),
         ("integrator", C.c_int), ("substeps", C.c_int), ("precision", C.c_int), ("interp", C.c_int),
-        ("meas_kind", C.c_int), ("nz", C.c_int), ("H", C.c_double * 9), ("hparam", C.c_double * 4),
+        ("meas_kind", C.c_int), ("nz", C.c_int), ("H", C.c_double * 12), ("hparam", C.c_double * 4),
+        ("nterrain", C.c_int), ("terrain", C.c_double * (PMF_MAX_TERRAIN * 6)),
         ("noise_ncomp", C.c_int), ("noise_w", C.c_double * 4), ("noise_mean", C.c_double * 12),
         ("noise_cov", C.c_double * 36),
     ]
 
 
 class pmf_prior(C.Structure):
-    _fields_ = [("ncomp", C.c_int), ("w", C.c_double * 4), ("mean", C.c_double * 12),
-                ("cov", C.c_double * 36)]
+    _fields_ = [("ncomp", C.c_int), ("w", C.c_double * 4), ("mean", C.c_double * 16),
+                ("cov", C.c_double * 64)]
 
 
 class pmf_state_header(C.Structure):
     _fields_ = [("magic", C.c_uint), ("version", C.c_int), ("nx", C.c_int), ("grid", C.c_int),
-                ("precision", C.c_int), ("status", C.c_int), ("N", C.c_int * 3), ("pad", C.c_int),
-                ("c", C.c_double * 3), ("M", C.c_double * 9), ("t", C.c_double)]
+                ("precision", C.c_int), ("status", C.c_int), ("N", C.c_int * 4),
+                ("c", C.c_double * 4), ("M", C.c_double * 16), ("t", C.c_double)]
 
 
 PMF_OP_PREDICT, PMF_OP_UPDATE = 0, 1
@@ -151,8 +156,8 @@ def make_model(spec) -> pmf_model:
     _fill(m.A, np.asarray(spec.A, float).reshape(nx, nx))
     _fill(m.Q, np.asarray(spec.Q, float).reshape(nx, nx))
     m.grid = int(spec.grid)
-    _fill_int = list(spec.N) + [1] * (3 - nx)
-    for i in range(3):
+    _fill_int = list(spec.N)[:nx] + [1] * (4 - nx)
+    for i in range(4):
         m.N[i] = int(_fill_int[i])
     m.span_sigmas = float(spec.span_sigmas)
     m.t_nominal = float(spec.t_nominal)
@@ -165,6 +170,13 @@ def make_model(spec) -> pmf_model:
     if int(spec.meas_kind) == 0:
         _fill(m.H, np.asarray(spec.H, float).reshape(m.nz, nx))
     _fill(m.hparam, np.asarray(spec.hparam, float).ravel()[:4])
+    terr = getattr(spec, "terrain", None)
+    if int(spec.meas_kind) == PMF_H_TERRAIN and terr is not None:
+        terr = np.asarray(terr, float).reshape(-1, 2 + nx)
+        m.nterrain = len(terr)
+        for c, row in enumerate(terr):
+            for i, v in enumerate(row):
+                m.terrain[6 * c + i] = float(v)
     w = np.asarray(spec.noise_w, float).ravel()
     m.noise_ncomp = len(w)
     _fill(m.noise_w, w)
@@ -187,9 +199,9 @@ def make_prior(spec, nx: int) -> pmf_prior:
     covs = np.asarray(spec.cov, float).reshape(len(w), nx, nx)
     for g in range(len(w)):
         for i in range(nx):
-            p.mean[3 * g + i] = means[g, i]
+            p.mean[4 * g + i] = means[g, i]
             for j in range(nx):
-                p.cov[9 * g + i * nx + j] = covs[g, i, j]
+                p.cov[16 * g + i * nx + j] = covs[g, i, j]
     return p
 
 
@@ -270,7 +282,7 @@ def pmf_get_state(f):
     off = C.sizeof(pmf_state_header)
     P = np.frombuffer(bytes(buf)[off:], dtype=dt, count=int(np.prod(shape))).reshape(shape).copy()
     c = np.array(h.c[:nx])
-    M = np.array(h.M[:]).reshape(3, 3)[:nx, :nx].copy()
+    M = np.array(h.M[:]).reshape(4, 4)[:nx, :nx].copy()
     return h, c, M, h.t, P
 
 
@@ -280,17 +292,17 @@ def pmf_set_state(f, c, M, t, P, grid: int, precision: int) -> None:
     nx = P.ndim
     h = pmf_state_header()
     h.magic = PMF_STATE_MAGIC
-    h.version = 1
+    h.version = 2
     h.nx = nx
     h.grid = int(grid)
     h.precision = int(precision)
-    for i in range(3):
+    for i in range(4):
         h.N[i] = P.shape[i] if i < nx else 1
     Mm = np.asarray(M, float).reshape(nx, nx)
     for i in range(nx):
         h.c[i] = float(c[i])
         for j in range(nx):
-            h.M[3 * i + j] = float(Mm[i, j])
+            h.M[4 * i + j] = float(Mm[i, j])
     h.t = float(t)
     blob = bytes(h) + P.tobytes()
     buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)

@@ -41,16 +41,16 @@ void ctx_free(pmf_ctx* ctx, void* p, hipStream_t st) {
 // ---------------------------------------------------------------- host math
 
 static bool chol_ok(const double* S, int n) {
-    double L[9] = {0};
+    double L[MSQ] = {0};
     for (int i = 0; i < n; ++i)
         for (int j = 0; j <= i; ++j) {
-            double s = S[i * 3 + j];
-            for (int k = 0; k < j; ++k) s -= L[i * 3 + k] * L[j * 3 + k];
+            double s = S[i * MS + j];
+            for (int k = 0; k < j; ++k) s -= L[i * MS + k] * L[j * MS + k];
             if (i == j) {
                 if (!(s > 0.0)) return false;
-                L[i * 3 + i] = std::sqrt(s);
+                L[i * MS + i] = std::sqrt(s);
             } else {
-                L[i * 3 + j] = s / L[j * 3 + j];
+                L[i * MS + j] = s / L[j * MS + j];
             }
         }
     return true;
@@ -63,14 +63,14 @@ static void diffusion(const pmf_model& m, double* D) {
         for (int j = 0; j < n; ++j) {
             double s = 0.0;
             for (int k = 0; k < n; ++k) s += m.Q[i * n + k] * m.Q[j * n + k];
-            D[i * 3 + j] = s;
+            D[i * MS + j] = s;
         }
 }
 
 static void load_square(const double* src, int n, double* dst) {
     mat_zero(dst);
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) dst[i * 3 + j] = src[i * n + j];
+        for (int j = 0; j < n; ++j) dst[i * MS + j] = src[i * n + j];
 }
 
 // Chebyshev-Gauss-Lobatto nodes v_k = -cos(k pi / n), n = N+1, ascending.
@@ -147,13 +147,13 @@ static bool design_grid_host(const pmf_model& m, const double* Wnom, const doubl
                              Grid& g) {
     mat_zero(g.M);
     for (int a = 0; a < m.nx; ++a) {
-        const double v = cov[a * 3 + a] + Wnom[a * 3 + a];
+        const double v = cov[a * MS + a] + Wnom[a * MS + a];
         if (!(v > 0.0) || !std::isfinite(v)) return false;
         const double h = m.span_sigmas * std::sqrt(v);
-        g.M[a * 3 + a] = (m.grid == PMF_GRID_FOURIER) ? 2.0 * h / m.N[a] : h;
+        g.M[a * MS + a] = (m.grid == PMF_GRID_FOURIER) ? 2.0 * h / m.N[a] : h;
         g.c[a] = mean[a];
     }
-    for (int a = m.nx; a < 3; ++a) g.c[a] = 0.0;
+    for (int a = m.nx; a < MS; ++a) g.c[a] = 0.0;
     grid_finish(g, m.nx);
     return true;
 }
@@ -162,15 +162,16 @@ static bool design_grid_host(const pmf_model& m, const double* Wnom, const doubl
 
 static pmf_status validate_model(const pmf_model* m) {
     if (!m) return fail(PMF_E_INVALID, "model is NULL");
-    if (m->nx < 1 || m->nx > 3) return fail(PMF_E_INVALID, "nx must be 1..3");
+    if (m->nx < 1 || m->nx > MAXNX) return fail(PMF_E_INVALID, "nx must be 1..4");
     if (m->grid != PMF_GRID_FOURIER && m->grid != PMF_GRID_CHEBYSHEV)
         return fail(PMF_E_INVALID, "unknown grid kind");
+    if (m->grid == PMF_GRID_CHEBYSHEV && m->nx > 3) return fail(PMF_E_INVALID, "Chebyshev grids: nx must be 1..3");
     long ntot = 1;
     for (int a = 0; a < m->nx; ++a) {
         const int n = m->N[a];
         if (n < 4 || n > 256) return fail(PMF_E_INVALID, "N per axis must be 4..256");
         if (m->grid == PMF_GRID_FOURIER && (n % 2 != 0 || make_plan(n).np < 0))
-            return fail(PMF_E_INVALID, "Fourier N must be even and of the form 2^a 3^b 5^c");
+            return fail(PMF_E_INVALID, "Fourier N must be even and of the form 2^a 3^b 5^c 17^d");
         ntot *= n;
     }
     if (ntot > (1L << 24)) return fail(PMF_E_INVALID, "grid larger than 2^24 points");
@@ -178,11 +179,11 @@ static pmf_status validate_model(const pmf_model* m) {
     if (m->integrator == PMF_INT_FDM || m->integrator == PMF_INT_SINE) {
         if (m->grid != PMF_GRID_FOURIER)
             return fail(PMF_E_INVALID, "the finite-difference and sine-series forms need a Fourier grid");
-        double Dm[9];
+        double Dm[MSQ];
         diffusion(*m, Dm);
         for (int i = 0; i < m->nx; ++i)
             for (int j = 0; j < m->nx; ++j)
-                if (i != j && (m->A[i * m->nx + j] != 0.0 || Dm[i * 3 + j] != 0.0))
+                if (i != j && (m->A[i * m->nx + j] != 0.0 || Dm[i * MS + j] != 0.0))
                     return fail(PMF_E_INVALID, "the finite-difference and sine-series forms need diagonal A and D");
     }
     if (m->grid == PMF_GRID_CHEBYSHEV && m->integrator != PMF_INT_RK4)
@@ -195,16 +196,22 @@ static pmf_status validate_model(const pmf_model* m) {
     if (!(m->t_nominal > 0.0) || !std::isfinite(m->t_nominal)) return fail(PMF_E_INVALID, "t_nominal <= 0");
     for (int i = 0; i < m->nx * m->nx; ++i)
         if (!std::isfinite(m->A[i]) || !std::isfinite(m->Q[i])) return fail(PMF_E_INVALID, "non-finite A or Q");
-    if (m->meas_kind < 0 || m->meas_kind > 2) return fail(PMF_E_INVALID, "unknown measurement kind");
+    if (m->meas_kind < 0 || m->meas_kind > 3) return fail(PMF_E_INVALID, "unknown measurement kind");
     if (m->meas_kind == PMF_H_LINEAR) {
         if (m->nz < 1 || m->nz > 3) return fail(PMF_E_INVALID, "nz must be 1..3");
     } else if (m->nz != 1) {
         return fail(PMF_E_INVALID, "nonlinear measurements have nz = 1");
     }
+    if (m->meas_kind == PMF_H_TERRAIN) {
+        if (m->nterrain < 1 || m->nterrain > PMF_MAX_TERRAIN)
+            return fail(PMF_E_INVALID, "nterrain must be 1..8");
+        for (int i = 0; i < 6 * m->nterrain; ++i)
+            if (!std::isfinite(m->terrain[i])) return fail(PMF_E_INVALID, "non-finite terrain parameter");
+    }
     if (m->noise_ncomp < 1 || m->noise_ncomp > MAXMIX) return fail(PMF_E_INVALID, "noise_ncomp must be 1..4");
     for (int g = 0; g < m->noise_ncomp; ++g) {
         if (!(m->noise_w[g] > 0.0)) return fail(PMF_E_INVALID, "noise weights must be > 0");
-        double R[9];
+        double R[MSQ];
         load_square(m->noise_cov + 9 * g, m->nz, R);
         if (!chol_ok(R, m->nz)) return fail(PMF_E_INVALID, "noise covariance not positive definite");
     }
@@ -216,8 +223,8 @@ static pmf_status validate_prior(const pmf_prior* p, int nx) {
     if (p->ncomp < 1 || p->ncomp > MAXMIX) return fail(PMF_E_INVALID, "prior ncomp must be 1..4");
     for (int g = 0; g < p->ncomp; ++g) {
         if (!(p->w[g] > 0.0)) return fail(PMF_E_INVALID, "prior weights must be > 0");
-        double C[9];
-        load_square(p->cov + 9 * g, nx, C);
+        double C[MSQ];
+        load_square(p->cov + MSQ * g, nx, C);
         if (!chol_ok(C, nx)) return fail(PMF_E_INVALID, "prior covariance not positive definite");
     }
     return PMF_OK;
@@ -234,17 +241,25 @@ static void build_kmodel(const pmf_model& m, KModel& k, double* Wnom) {
     k.integ = m.integrator;
     k.prec = m.precision;
     k.ntot = 1;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < MS; ++a) {
         k.N[a] = a < m.nx ? m.N[a] : 1;
         k.ntot *= k.N[a];
     }
     for (int i = 0; i < m.nz; ++i)
-        for (int j = 0; j < m.nx; ++j) k.H[i * 3 + j] = m.H[i * m.nx + j];
+        for (int j = 0; j < m.nx; ++j) k.H[i * MS + j] = m.H[i * m.nx + j];
     for (int i = 0; i < 4; ++i) k.hp[i] = m.hparam[i];
+    if (m.meas_kind == PMF_H_TERRAIN) {
+        k.nterr = m.nterrain;
+        for (int c = 0; c < m.nterrain; ++c) {
+            k.terr[c][0] = m.terrain[6 * c];
+            k.terr[c][1] = m.terrain[6 * c + 1];
+            for (int a = 0; a < m.nx; ++a) k.terr[c][2 + a] = m.terrain[6 * c + 2 + a];
+        }
+    }
     double wsum = 0.0;
     for (int g = 0; g < m.noise_ncomp; ++g) wsum += m.noise_w[g];
     for (int g = 0; g < m.noise_ncomp; ++g) {
-        double R[9], Ri[9];
+        double R[MSQ], Ri[MSQ];
         load_square(m.noise_cov + 9 * g, m.nz, R);
         const double det = mat_inv(Ri, R, m.nz);
         mat_copy(k.nRi[g], Ri);
@@ -255,7 +270,7 @@ static void build_kmodel(const pmf_model& m, KModel& k, double* Wnom) {
     for (int a = 0; a < m.nx; ++a) maxn = m.N[a] > maxn ? m.N[a] : maxn;
     k.wstride = maxn * maxn;
     k.span = m.span_sigmas;
-    double A[9], D[9];
+    double A[MSQ], D[MSQ];
     load_square(m.A, m.nx, A);
     diffusion(m, D);
     w_integral(Wnom, A, D, m.t_nominal, m.nx);
@@ -264,7 +279,7 @@ static void build_kmodel(const pmf_model& m, KModel& k, double* Wnom) {
 }
 
 static void fill_tables(const pmf_model& m, std::vector<double>& tab) {
-    tab.assign((size_t)3 * TAB_STRIDE, 0.0);
+    tab.assign((size_t)MS * TAB_STRIDE, 0.0);
     for (int a = 0; a < m.nx; ++a) {
         double* t = tab.data() + (size_t)a * TAB_STRIDE;
         const int n = m.N[a];
@@ -359,12 +374,12 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     if (model->grid == PMF_GRID_FOURIER) f->cbuf = A(f->ntot * f->es * 2);
     f->part = static_cast<double*>(A((size_t)MAX_RED_BLOCKS * NPART * sizeof(double)));
     f->bfac = static_cast<double*>(A((size_t)MAX_RED_BLOCKS * sizeof(double)));
-    f->coef = static_cast<double*>(A((size_t)(2 * LMAX + 1) * 6 * sizeof(double)));
+    f->coef = static_cast<double*>(A((size_t)(2 * LMAX + 1) * PACK * sizeof(double)));
     f->W = static_cast<double*>(A((size_t)model->nx * f->km.wstride * sizeof(double)));
-    f->tab = static_cast<double*>(A((size_t)3 * TAB_STRIDE * sizeof(double)));
+    f->tab = static_cast<double*>(A((size_t)MS * TAB_STRIDE * sizeof(double)));
     f->desc = static_cast<DevDesc*>(A(sizeof(DevDesc)));
     if (model->integrator == PMF_INT_FDM || model->integrator == PMF_INT_SINE)
-        f->D1 = A((size_t)3 * 256 * 256 * f->es);   // DST-I matrices
+        f->D1 = A((size_t)MS * 256 * 256 * f->es);   // DST-I matrices
     if (model->grid == PMF_GRID_CHEBYSHEV) {
         f->D1 = A((size_t)3 * 256 * 256 * f->es);
         f->D2 = A((size_t)3 * 256 * 256 * f->es);
@@ -385,7 +400,7 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
         return hip_fail(e, "upload tables");
     }
     if (model->integrator == PMF_INT_FDM || model->integrator == PMF_INT_SINE) {
-        std::vector<double> sall((size_t)3 * 256 * 256, 0.0);
+        std::vector<double> sall((size_t)MS * 256 * 256, 0.0);
         for (int a = 0; a < model->nx; ++a) {
             const int n = model->N[a];
             for (int i = 0; i < n; ++i)
@@ -429,26 +444,26 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
 
     // prior moments -> first grid
     const int nx = model->nx;
-    double wsum = 0.0, mean[3] = {0, 0, 0}, cov[9];
+    double wsum = 0.0, mean[MS] = {0, 0, 0, 0}, cov[MSQ];
     mat_zero(cov);
     for (int g = 0; g < prior->ncomp; ++g) wsum += prior->w[g];
     for (int g = 0; g < prior->ncomp; ++g)
-        for (int i = 0; i < nx; ++i) mean[i] += prior->w[g] / wsum * prior->mean[3 * g + i];
+        for (int i = 0; i < nx; ++i) mean[i] += prior->w[g] / wsum * prior->mean[MS * g + i];
     KPrior kp;
     std::memset(&kp, 0, sizeof(kp));
     kp.ncomp = prior->ncomp;
     for (int g = 0; g < prior->ncomp; ++g) {
-        double C[9], Ci[9];
-        load_square(prior->cov + 9 * g, nx, C);
+        double C[MSQ], Ci[MSQ];
+        load_square(prior->cov + MSQ * g, nx, C);
         const double det = mat_inv(Ci, C, nx);
         mat_copy(kp.Ci[g], Ci);
         kp.lw[g] = std::log(prior->w[g] / wsum) - 0.5 * (nx * std::log(2.0 * M_PI) + std::log(det));
-        for (int i = 0; i < nx; ++i) kp.mean[g][i] = prior->mean[3 * g + i];
+        for (int i = 0; i < nx; ++i) kp.mean[g][i] = prior->mean[MS * g + i];
         const double wg = prior->w[g] / wsum;
         for (int i = 0; i < nx; ++i)
             for (int j = 0; j < nx; ++j)
-                cov[i * 3 + j] += wg * (C[i * 3 + j] + (prior->mean[3 * g + i] - mean[i]) *
-                                                           (prior->mean[3 * g + j] - mean[j]));
+                cov[i * MS + j] += wg * (C[i * MS + j] + (prior->mean[MS * g + i] - mean[i]) *
+                                                             (prior->mean[MS * g + j] - mean[j]));
     }
     DevDesc hd;
     std::memset(&hd, 0, sizeof(hd));
@@ -509,7 +524,7 @@ pmf_status pmf_predict(pmf_filter* f, double T, void* stream) {
     if (f->model.integrator == PMF_INT_FDM || f->model.integrator == PMF_INT_SINE) {
         const int sine = f->model.integrator == PMF_INT_SINE ? 1 : 0;
         double trA = 0.0;
-        for (int i = 0; i < f->model.nx; ++i) trA += pa.A[i * 3 + i];
+        for (int i = 0; i < f->model.nx; ++i) trA += pa.A[i * MS + i];
         void* t1 = f->buf[(f->cur + 1) % 4];
         void* t2 = f->buf[(f->cur + 2) % 4];
         if (f->es == sizeof(double))
@@ -603,7 +618,7 @@ pmf_status pmf_moments(pmf_filter* f, double* mean, double* cov, void* stream) {
     const int nx = f->model.nx;
     for (int i = 0; i < nx; ++i) {
         mean[i] = hd.mean[i];
-        for (int j = 0; j < nx; ++j) cov[i * nx + j] = hd.cov[i * 3 + j];
+        for (int j = 0; j < nx; ++j) cov[i * nx + j] = hd.cov[i * MS + j];
     }
     return take_status(f);
 }
@@ -640,13 +655,13 @@ pmf_status pmf_get_state(pmf_filter* f, void* host_buf, size_t* bytes) {
     pmf_state_header h;
     std::memset(&h, 0, sizeof(h));
     h.magic = PMF_STATE_MAGIC;
-    h.version = 1;
+    h.version = 2;
     h.nx = f->model.nx;
     h.grid = f->model.grid;
     h.precision = f->model.precision;
     h.status = hd.status;
-    for (int a = 0; a < 3; ++a) h.N[a] = a < f->model.nx ? f->model.N[a] : 1;
-    for (int a = 0; a < 3; ++a) h.c[a] = hd.g.c[a];
+    for (int a = 0; a < MS; ++a) h.N[a] = a < f->model.nx ? f->model.N[a] : 1;
+    for (int a = 0; a < MS; ++a) h.c[a] = hd.g.c[a];
     mat_copy(h.M, hd.g.M);
     h.t = hd.t;
     std::memcpy(out, &h, sizeof(h));
@@ -663,23 +678,23 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes) {
     if (bytes < sizeof(pmf_state_header)) return fail(PMF_E_INVALID, "image too small");
     pmf_state_header h;
     std::memcpy(&h, host_buf, sizeof(h));
-    if (h.magic != PMF_STATE_MAGIC || h.version != 1) return fail(PMF_E_INVALID, "not a pmf state image");
+    if (h.magic != PMF_STATE_MAGIC || h.version != 2) return fail(PMF_E_INVALID, "not a pmf state image");
     if (h.nx != f->model.nx || h.grid != f->model.grid || h.precision != f->model.precision)
         return fail(PMF_E_INVALID, "image of a different filter kind");
     for (int a = 0; a < f->model.nx; ++a)
         if (h.N[a] != f->model.N[a]) return fail(PMF_E_INVALID, "image of a different grid size");
     if (bytes < sizeof(h) + (size_t)f->ntot * f->es) return fail(PMF_E_INVALID, "image truncated");
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < MSQ; ++i)
         if (!std::isfinite(h.M[i])) return fail(PMF_E_INVALID, "non-finite grid");
     hipError_t e = hipSetDevice(f->ctx->device);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     DevDesc hd;
     if (e == hipSuccess) e = hipMemcpy(&hd, f->desc, sizeof(hd), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "set_state");
-    for (int a = 0; a < 3; ++a) hd.g.c[a] = a < f->model.nx ? h.c[a] : 0.0;
+    for (int a = 0; a < MS; ++a) hd.g.c[a] = a < f->model.nx ? h.c[a] : 0.0;
     mat_zero(hd.g.M);
     for (int i = 0; i < f->model.nx; ++i)
-        for (int j = 0; j < f->model.nx; ++j) hd.g.M[i * 3 + j] = h.M[i * 3 + j];
+        for (int j = 0; j < f->model.nx; ++j) hd.g.M[i * MS + j] = h.M[i * MS + j];
     grid_finish(hd.g, f->model.nx);
     if (!(hd.g.vol > 0.0)) return fail(PMF_E_INVALID, "singular grid matrix");
     hd.gn = hd.g;
@@ -752,7 +767,7 @@ const PredictArgs& predict_args(pmf_filter* f, double T) {
     load_square(f->model.A, n, a.A);
     diffusion(f->model, a.D);
     double tr = 0.0;
-    for (int i = 0; i < n; ++i) tr += a.A[i * 3 + i];
+    for (int i = 0; i < n; ++i) tr += a.A[i * MS + i];
     a.etr = std::exp(-tr * T);
     expm3(a.Phi, a.A, T, n);
     expm3(a.emh, a.A, -0.5 * T, n);
@@ -762,7 +777,7 @@ const PredictArgs& predict_args(pmf_filter* f, double T) {
     a.integ = f->model.integrator;
     a.nx = n;
     a.lmax = LMAX;
-    for (int i = 0; i < 3; ++i) a.rho[i] = f->km.rho[i];
+    for (int i = 0; i < MS; ++i) a.rho[i] = f->km.rho[i];
     f->have_pa = true;
     return a;
 }

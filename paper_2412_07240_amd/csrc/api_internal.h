@@ -25,7 +25,7 @@ struct pmf_filter {
     pmf_ctx* ctx = nullptr;
     pmf_model model{};
     pmf::KModel km{};
-    double Wnom[9] = {0};
+    double Wnom[pmf::MSQ] = {0};
     int ntot = 0;
     size_t es = 0;                 // bytes per density value
     void* buf[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -273,7 +273,7 @@ __device__ double seg_max(double v, const Seg& s, double* slots, int G) {
 __device__ __noinline__ int plan_substeps(const PredictArgs& a, const double* Mi, int n, int l) {
     double lam = 0.0;
     for (int q = 0; q < 3; ++q) {
-        double E[9], t1[9], Dy[9];
+        double E[MSQ], t1[MSQ], Dy[MSQ];
         if (q == 0) {
             mat_copy(E, a.D);
         } else {
@@ -284,7 +284,7 @@ __device__ __noinline__ int plan_substeps(const PredictArgs& a, const double* Mi
         sandwich_inv(Dy, Mi, E, n);
         double lb = 0.0;
         for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) lb += fabs(Dy[i * 3 + j]) * a.rho[i] * a.rho[j];
+            for (int j = 0; j < n; ++j) lb += fabs(Dy[i * MS + j]) * a.rho[i] * a.rho[j];
         lam = fmax(lam, 0.5 * lb);
     }
     const double need = ceil(a.T * lam / RK4_STABLE_STEP);
@@ -297,7 +297,7 @@ __device__ __noinline__ void plan_stage_coefs(const PredictArgs& a, const double
                                               double* coef) {
     const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
     const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
-    double Estep[9], Ek[9], t1[9], E[9], Dy[9], nxt[9];
+    double Estep[MSQ], Ek[MSQ], t1[MSQ], E[MSQ], Dy[MSQ], nxt[MSQ];
     expm3(Estep, a.A, -dt, n);
     mat_eye(Ek, n);
     for (int k = 0; k < cnt; ++k) {
@@ -305,7 +305,7 @@ __device__ __noinline__ void plan_stage_coefs(const PredictArgs& a, const double
         mat_mul_bt(E, t1, Ek, n);
         sandwich_inv(Dy, Mi, E, n);
         coef[3 * k + 0] = Dy[0];
-        coef[3 * k + 1] = Dy[4];
+        coef[3 * k + 1] = Dy[MS + 1];
         coef[3 * k + 2] = Dy[1];
         mat_mul(nxt, Ek, Estep, n);
         mat_copy(Ek, nxt);
@@ -322,7 +322,7 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     const DevDesc* d = I.d;
     constexpr int n = NX;   // compile-time: the small matrix loops unroll into registers
     Grid g = d->g;
-    double Mi[9];
+    double Mi[MSQ];
     mat_copy(Mi, g.Mi);
     int l = a.lmin;
     P.bad = 0;
@@ -333,10 +333,10 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     }
     const double h = a.T / l;
     if (a.integ == PMF_INT_EXACT) {
-        double Wy[9];
+        double Wy[MSQ];
         sandwich_inv(Wy, Mi, a.W, n);
         P.gc[0] = Wy[0];
-        P.gc[1] = Wy[4];
+        P.gc[1] = Wy[MS + 1];
         P.gc[2] = Wy[1];
     } else {
         plan_stage_coefs(a, Mi, n, l, h, I.coef);
@@ -346,7 +346,7 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     P.etr = a.etr;
     P.T = a.T;
     // grid follows x' = A x
-    double c2[3], M2[9];
+    double c2[MS], M2[MSQ];
     mat_vec(c2, a.Phi, g.c, n);
     mat_mul(M2, a.Phi, g.M, n);
     for (int i = 0; i < n; ++i) g.c[i] = c2[i];
@@ -356,15 +356,15 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     P.c[1] = n > 1 ? g.c[1] : 0.0;
     P.M[0] = g.M[0];
     P.M[1] = g.M[1];
-    P.M[2] = g.M[3];
-    P.M[3] = g.M[4];
+    P.M[2] = g.M[MS];
+    P.M[3] = g.M[MS + 1];
     P.Mi[0] = g.Mi[0];
     P.Mi[1] = g.Mi[1];
-    P.Mi[2] = g.Mi[3];
-    P.Mi[3] = g.Mi[4];
+    P.Mi[2] = g.Mi[MS];
+    P.Mi[3] = g.Mi[MS + 1];
     P.vol = g.vol;
     P.Wnom[0] = m.Wnom[0];
-    P.Wnom[1] = m.Wnom[4];
+    P.Wnom[1] = m.Wnom[MS + 1];
     P.span = m.span;
     P.integ = a.integ;
     P.interp = m.interp;
@@ -381,17 +381,17 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
         double r0[3], G[9], Rir0[3];
         for (int i = 0; i < nz; ++i) {
             double hc = 0.0;
-            for (int k = 0; k < n; ++k) hc += m.H[i * 3 + k] * g.c[k];
+            for (int k = 0; k < n; ++k) hc += m.H[i * MS + k] * g.c[k];
             r0[i] = z[i] - m.nmean[0][i] - hc;
             for (int b = 0; b < n; ++b) {
                 double s = 0.0;
-                for (int k = 0; k < n; ++k) s += m.H[i * 3 + k] * g.M[k * 3 + b];
+                for (int k = 0; k < n; ++k) s += m.H[i * MS + k] * g.M[k * MS + b];
                 G[i * 3 + b] = s;
             }
         }
         for (int i = 0; i < nz; ++i) {
             double s = 0.0;
-            for (int k = 0; k < nz; ++k) s += m.nRi[0][i * 3 + k] * r0[k];
+            for (int k = 0; k < nz; ++k) s += m.nRi[0][i * MS + k] * r0[k];
             Rir0[i] = s;
         }
         double rr = 0.0;
@@ -405,7 +405,7 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
             for (int b = 0; b < n; ++b) {
                 double t = 0.0;
                 for (int i = 0; i < nz; ++i)
-                    for (int k = 0; k < nz; ++k) t += G[i * 3 + a2] * m.nRi[0][i * 3 + k] * G[k * 3 + b];
+                    for (int k = 0; k < nz; ++k) t += G[i * 3 + a2] * m.nRi[0][i * MS + k] * G[k * 3 + b];
                 Qf[a2 * 2 + b] = t;
             }
         }
@@ -439,7 +439,7 @@ __device__ __noinline__ double floglik_general(const KModel& m, const FPlan& P, 
     x[1] = P.c[1] + P.M[2] * u0 + P.M[3] * u1;
     double hx[3] = {0, 0, 0};
     if (m.meas == PMF_H_LINEAR) {
-        for (int i = 0; i < m.nz; ++i) hx[i] = m.H[i * 3] * x[0] + (m.nx > 1 ? m.H[i * 3 + 1] * x[1] : 0.0);
+        for (int i = 0; i < m.nz; ++i) hx[i] = m.H[i * MS] * x[0] + (m.nx > 1 ? m.H[i * MS + 1] * x[1] : 0.0);
     } else if (m.meas == PMF_H_CUBIC1) {
         hx[0] = m.hp[0] * x[0] + m.hp[1] * x[0] * x[0] * x[0];
     } else {
@@ -451,7 +451,7 @@ __device__ __noinline__ double floglik_general(const KModel& m, const FPlan& P, 
         for (int i = 0; i < m.nz; ++i) r[i] = z[i] - hx[i] - m.nmean[g][i];
         double q = 0.0;
         for (int i = 0; i < m.nz; ++i)
-            for (int k = 0; k < m.nz; ++k) q += r[i] * m.nRi[g][i * 3 + k] * r[k];
+            for (int k = 0; k < m.nz; ++k) q += r[i] * m.nRi[g][i * MS + k] * r[k];
         terms[g] = m.lw[g] - 0.5 * q;
         best = fmax(best, terms[g]);
     }
@@ -717,20 +717,20 @@ __device__ void filter_commit(const FState& F, const BItem& I, double* ll_out) {
     DevDesc* d = I.d;
     Grid gg;
     mat_zero(gg.M);
-    for (int q = 0; q < 3; ++q) gg.c[q] = 0.0;
+    for (int q = 0; q < MS; ++q) gg.c[q] = 0.0;
     if (F.ok) {
         gg.c[0] = F.gnc[0];
         gg.c[1] = P.nx == 2 ? F.gnc[1] : 0.0;
         gg.M[0] = F.gnM[0];
-        if (P.nx == 2) gg.M[4] = F.gnM[3];
+        if (P.nx == 2) gg.M[MS + 1] = F.gnM[3];
     } else {
         gg.c[0] = P.c[0];
         gg.c[1] = P.c[1];
         gg.M[0] = P.M[0];
         if (P.nx == 2) {
             gg.M[1] = P.M[1];
-            gg.M[3] = P.M[2];
-            gg.M[4] = P.M[3];
+            gg.M[MS] = P.M[2];
+            gg.M[MS + 1] = P.M[3];
         }
     }
     grid_finish(gg, P.nx);
@@ -1280,6 +1280,7 @@ bool batch_fusable(const pmf_filter* f, std::string* why) {
     if (m.precision != PMF_FP32) return *why = "FP64 density", false;
     if (m.integrator == PMF_INT_FDM || m.integrator == PMF_INT_SINE)
         return *why = "finite-difference or sine-series time update", false;
+    if (m.meas_kind == PMF_H_TERRAIN) return *why = "terrain measurement", false;
     if (m.nx > 2) return *why = "nx > 2", false;
     if (m.nx == 2 && (m.N[0] > 128 || m.N[1] > 128)) return *why = "2-D N above 128", false;
     if (m.nx == 1 && m.N[0] > 256) return *why = "1-D N above 256", false;

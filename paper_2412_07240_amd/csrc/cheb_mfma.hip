@@ -74,7 +74,7 @@ __device__ inline void tile_store(float* T, const float4& v) {
 }
 
 // One pass (see the header).  Block = NB waves (64 NB threads), 16 lines.
-// coef holds the packed sets 00, 11, 22, 01, 02, 12 of D_y at the stage time.
+// coef holds the packed sets of D_y at the stage times (diagonal first, see pk).
 template <int NB, int KIND>
 __global__ void __launch_bounds__(64 * NB)
 k_cheb_pass(ChebGeom G, int axis, const float* __restrict__ D1, const float* __restrict__ D2,
@@ -125,17 +125,17 @@ k_cheb_pass(ChebGeom G, int axis, const float* __restrict__ D1, const float* __r
             for (int r = 0; r < 4; ++r) av[r] = acc[addr[r]];
         }
     }
-    const double* c = coef + 6 * cidx;
+    const double* c = coef + PACK * cidx;
     const float h = (float)d->h;
     float cP, cX = 1.f, cY = 0.f, cT = 0.f;
     if (KIND == PASS_LAST) {
         cP = 0.5f * (float)c[G.nx - 1];
-        cX = G.nx == 2 ? (float)c[3] : 1.f;
+        cX = G.nx == 2 ? (float)c[pk(0, 1)] : 1.f;
     } else if (KIND == PASS_MID) {
         cP = 0.5f * (float)c[1];
-        cX = (float)c[3];   // u = Dy_01 D1_1 y + Dy_02 t_2
-        cT = (float)c[4];
-        cY = (float)c[5];   // kf += Dy_12 D1_1 t_2
+        cX = (float)c[pk(0, 1)];   // u = Dy_01 D1_1 y + Dy_02 t_2
+        cT = (float)c[pk(0, 2)];
+        cY = (float)c[pk(1, 2)];   // kf += Dy_12 D1_1 t_2
     } else {
         cP = 0.5f * (float)c[0];
     }

@@ -14,8 +14,8 @@ constexpr int TAB_STRIDE = 1040;
 struct KPrior {
     int ncomp, pad[3];
     double lw[MAXMIX];          // log w_g - 1/2 log det(2 pi C_g)
-    double mean[MAXMIX][3];
-    double Ci[MAXMIX][9];
+    double mean[MAXMIX][MS];
+    double Ci[MAXMIX][MSQ];
 };
 
 template <typename T>

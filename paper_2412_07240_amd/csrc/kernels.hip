@@ -98,6 +98,29 @@ template <typename C, typename T> __device__ inline void dft5(C* a, int s) {
     a[3] = csub(m2, r2);
 }
 
+// R-point DFT by the definition (odd prime R without a factored butterfly, here
+// 17 for N = 34): the R roots of unity once, then X_k = sum_r a_r w^{(r k) mod R}
+template <typename C, typename T, int R> __device__ inline void dft_direct(C* a, int s) {
+    C w[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        T sn, cs;
+        sincospi_t((T)(2 * s * m) / (T)R, &sn, &cs);
+        w[m].x = cs;
+        w[m].y = sn;
+    }
+    C out[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        C acc = a[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(a[r], w[(r * k) % R]));
+        out[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) a[k] = out[k];
+}
+
 // One Stockham autosort pass over `nlines` lines held in LDS (pitch `pitch`).
 template <typename T, int R>
 __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* out, int n, int Ns,
@@ -128,6 +151,7 @@ __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* ou
         if (R == 4) dft4<C, T>(v, sign);
         if (R == 8) dft8<C, T>(v, sign);
         if (R == 5) dft5<C, T>(v, sign);
+        if (R == 17) dft_direct<C, T, 17>(v, sign);
         const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
@@ -179,6 +203,7 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
         else if (R == 4) stockham_pass<T, 4>(in, out, n, Ns, ntl, pitch, sign);
         else if (R == 3) stockham_pass<T, 3>(in, out, n, Ns, ntl, pitch, sign);
         else if (R == 5) stockham_pass<T, 5>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 17) stockham_pass<T, 17>(in, out, n, Ns, ntl, pitch, sign);
         else stockham_pass<T, 2>(in, out, n, Ns, ntl, pitch, sign);
         __syncthreads();
         C* tmp = in;
@@ -214,7 +239,7 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
 __device__ double lambda_bound_dev(const double* Dy, const double* rho, int n) {
     double s = 0.0;
     for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) s += fabs(Dy[a * 3 + b]) * rho[a] * rho[b];
+        for (int b = 0; b < n; ++b) s += fabs(Dy[a * MS + b]) * rho[a] * rho[b];
     return 0.5 * s;
 }
 
@@ -224,9 +249,9 @@ constexpr int PLAN_POW = 14;   // 2 LMAX + 1 < 2^14
 template <int NX>
 __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d, double* coef) {
     constexpr int n = NX;
-    __shared__ double pw[PLAN_POW][9];
+    __shared__ double pw[PLAN_POW][MSQ];
     __shared__ int s_l;
-    double Mi[9];
+    double Mi[MSQ];
     mat_copy(Mi, d->g.Mi);
     if (threadIdx.x == 0) {
         int l = a.lmin;
@@ -234,7 +259,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
             double lam = 0.0;
             const double* Es[3] = {nullptr, a.emh, a.emT};
             for (int q = 0; q < 3; ++q) {
-                double E[9], t1[9], Dy[9];
+                double E[MSQ], t1[MSQ], Dy[MSQ];
                 if (q == 0) {
                     mat_copy(E, a.D);
                 } else {
@@ -253,7 +278,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
             double lam = 0.0;
             const double* Es[3] = {nullptr, a.emh, a.emT};
             for (int q = 0; q < 3; ++q) {
-                double E[9], t1[9], Dy[9];
+                double E[MSQ], t1[MSQ], Dy[MSQ];
                 if (q == 0) {
                     mat_copy(E, a.D);
                 } else {
@@ -262,7 +287,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
                 }
                 sandwich_inv(Dy, Mi, E, n);
                 double tr = 0.0;
-                for (int i = 0; i < n; ++i) tr += Dy[i * 3 + i];
+                for (int i = 0; i < n; ++i) tr += Dy[i * MS + i];
                 lam = tr > lam ? tr : lam;
             }
             const double need = ceil(a.T * lam / FDM_STABLE_STEP);
@@ -275,18 +300,18 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
         s_l = l;
         const double h = a.T / l;
         if (a.integ == PMF_INT_EXACT || a.integ == PMF_INT_SINE) {
-            double Wy[9];
+            double Wy[MSQ];
             sandwich_inv(Wy, Mi, a.W, n);
             pack_sym(coef, Wy);
         } else {
             const double dt = (a.integ == PMF_INT_RK4) ? 0.5 * h : h;
-            double E[9];
+            double E[MSQ];
             expm3(E, a.A, -dt, n);
-            for (int i = 0; i < 9; ++i) pw[0][i] = E[i];
+            for (int i = 0; i < MSQ; ++i) pw[0][i] = E[i];
             for (int j = 1; j < PLAN_POW; ++j) {
-                double sq[9];
+                double sq[MSQ];
                 mat_mul(sq, pw[j - 1], pw[j - 1], n);
-                for (int i = 0; i < 9; ++i) pw[j][i] = sq[i];
+                for (int i = 0; i < MSQ; ++i) pw[j][i] = sq[i];
             }
         }
         d->l = l;
@@ -298,7 +323,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
         const int l = s_l;
         const int cnt = (a.integ == PMF_INT_RK4) ? 2 * l + 1 : l;
         for (int k = threadIdx.x; k < cnt; k += PLAN_THREADS) {
-            double Ek[9], nxt[9], t1[9], E[9], Dy[9];
+            double Ek[MSQ], nxt[MSQ], t1[MSQ], E[MSQ], Dy[MSQ];
             mat_eye(Ek, n);
             for (int j = 0; j < PLAN_POW; ++j)
                 if ((k >> j) & 1) {
@@ -308,12 +333,12 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
             mat_mul(t1, Ek, a.D, n);
             mat_mul_bt(E, t1, Ek, n);
             sandwich_inv(Dy, Mi, E, n);
-            pack_sym(coef + 6 * k, Dy);
+            pack_sym(coef + PACK * k, Dy);
         }
     }
     if (threadIdx.x == 0) {
         // grid follows x' = A x over T
-        double c2[3], M2[9];
+        double c2[MS], M2[MSQ];
         mat_vec(c2, a.Phi, d->g.c, n);
         mat_mul(M2, a.Phi, d->g.M, n);
         for (int i = 0; i < n; ++i) d->g.c[i] = c2[i];
@@ -325,10 +350,14 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
 
 // ------------------------------------------------------------------ spectral gain
 
+// kappa^T S kappa from the packed S (00, 11, 22, 33, 01, 02, 03, 12, 13, 23):
+// squares with the second-derivative wavenumbers, cross terms with the first
 template <typename T>
 __device__ inline T sigma_of(const double* p, const T* k1, const T* k2) {
-    return (T)p[0] * k2[0] + (T)p[1] * k2[1] + (T)p[2] * k2[2] +
-           (T)2 * ((T)p[3] * k1[0] * k1[1] + (T)p[4] * k1[0] * k1[2] + (T)p[5] * k1[1] * k1[2]);
+    const T sq = (T)p[0] * k2[0] + (T)p[1] * k2[1] + (T)p[2] * k2[2] + (T)p[3] * k2[3];
+    const T cr = (T)p[4] * k1[0] * k1[1] + (T)p[5] * k1[0] * k1[2] + (T)p[6] * k1[0] * k1[3] +
+                 (T)p[7] * k1[1] * k1[2] + (T)p[8] * k1[1] * k1[3] + (T)p[9] * k1[2] * k1[3];
+    return sq + (T)2 * cr;
 }
 
 template <typename T>
@@ -336,13 +365,13 @@ __device__ T mode_gain(int integ, int l, T h, const double* coef, const T* k1, c
     if (integ == PMF_INT_EXACT) return exp_t((T)-0.5 * sigma_of<T>(coef, k1, k2));
     T g = (T)1;
     if (integ == PMF_INT_EULER) {
-        for (int n = 0; n < l; ++n) g = g / ((T)1 + (T)0.5 * h * sigma_of<T>(coef + 6 * n, k1, k2));
+        for (int n = 0; n < l; ++n) g = g / ((T)1 + (T)0.5 * h * sigma_of<T>(coef + PACK * n, k1, k2));
         return g;
     }
     for (int n = 0; n < l; ++n) {
-        const T la = (T)-0.5 * sigma_of<T>(coef + 12 * n, k1, k2);
-        const T lb = (T)-0.5 * sigma_of<T>(coef + 12 * n + 6, k1, k2);
-        const T lc = (T)-0.5 * sigma_of<T>(coef + 12 * n + 12, k1, k2);
+        const T la = (T)-0.5 * sigma_of<T>(coef + 2 * PACK * n, k1, k2);
+        const T lb = (T)-0.5 * sigma_of<T>(coef + 2 * PACK * n + PACK, k1, k2);
+        const T lc = (T)-0.5 * sigma_of<T>(coef + 2 * PACK * n + 2 * PACK, k1, k2);
         const T hh = (T)0.5 * h;
         const T y2 = (T)1 + hh * la;
         const T y3 = (T)1 + hh * lb * y2;
@@ -364,7 +393,7 @@ template <typename T>
 __global__ void k_gain(KModel m, const DevDesc* d, const double* coef, typename V2<T>::t* X) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m.ntot) return;
-    T k1[3] = {0, 0, 0}, k2[3] = {0, 0, 0};
+    T k1[MS] = {0, 0, 0, 0}, k2[MS] = {0, 0, 0, 0};
     int rem = e;
     for (int a = m.nx - 1; a >= 0; --a) {
         const int s = rem % m.N[a];
@@ -408,7 +437,7 @@ __device__ inline bool node_on_boundary(const KModel& m, const int* idx) {
 __device__ inline void to_phys(const Grid& g, int nx, const double* u, double* x) {
     for (int i = 0; i < nx; ++i) {
         double s = g.c[i];
-        for (int k = 0; k < nx; ++k) s += g.M[i * 3 + k] * u[k];
+        for (int k = 0; k < nx; ++k) s += g.M[i * MS + k] * u[k];
         x[i] = s;
     }
 }
@@ -419,11 +448,19 @@ __device__ double loglik_at(const KModel& m, const double* x, const double* z) {
     if (m.meas == PMF_H_LINEAR) {
         for (int i = 0; i < m.nz; ++i) {
             double s = 0.0;
-            for (int k = 0; k < m.nx; ++k) s += m.H[i * 3 + k] * x[k];
+            for (int k = 0; k < m.nx; ++k) s += m.H[i * MS + k] * x[k];
             hx[i] = s;
         }
     } else if (m.meas == PMF_H_CUBIC1) {
         hx[0] = m.hp[0] * x[0] + m.hp[1] * x[0] * x[0] * x[0];
+    } else if (m.meas == PMF_H_TERRAIN) {
+        double s = 0.0;
+        for (int c = 0; c < m.nterr; ++c) {
+            double ph = m.terr[c][1];
+            for (int k = 0; k < m.nx; ++k) ph += m.terr[c][2 + k] * x[k];
+            s += m.terr[c][0] * cos(ph);
+        }
+        hx[0] = s;
     } else {
         double s = 0.0;
         for (int k = 0; k < m.nx; ++k) s += x[k] * x[k];
@@ -435,7 +472,7 @@ __device__ double loglik_at(const KModel& m, const double* x, const double* z) {
         for (int i = 0; i < m.nz; ++i) r[i] = z[i] - hx[i] - m.nmean[g][i];
         double q = 0.0;
         for (int i = 0; i < m.nz; ++i)
-            for (int k = 0; k < m.nz; ++k) q += r[i] * m.nRi[g][i * 3 + k] * r[k];
+            for (int k = 0; k < m.nz; ++k) q += r[i] * m.nRi[g][i * MS + k] * r[k];
         terms[g] = m.lw[g] - 0.5 * q;
         best = terms[g] > best ? terms[g] : best;
     }
@@ -443,6 +480,17 @@ __device__ double loglik_at(const KModel& m, const double* x, const double* z) {
     double acc = 0.0;
     for (int g = 0; g < m.ncomp; ++g) acc += exp(terms[g] - best);
     return best + log(acc);
+}
+
+// per-thread FP64 sums of a weighted node: S0, S1[a] (u_a), S2[pk(a,b)] (u_a u_b),
+// boundary mass
+constexpr int NACC = 16;
+__device__ inline void acc_point(double* acc, double w, const double* u, bool boundary) {
+    acc[0] += w;
+    for (int a = 0; a < MS; ++a) acc[1 + a] += w * u[a];
+    for (int a = 0; a < MS; ++a)
+        for (int b = a; b < MS; ++b) acc[5 + pk(a, b)] += w * u[a] * u[b];
+    if (boundary) acc[NACC - 1] += w;
 }
 
 // fixed-order block reduction of NV doubles per thread (RED_THREADS threads)
@@ -474,12 +522,12 @@ __device__ double block_max(double v, double* sh) {
 
 // ------------------------------------------------------------------ likelihood + sums
 // mode 0: sums of the density only; mode 1: P_out = P * exp(loglik - s_b) and its sums.
-// Partial b: {s_b, S0, S1[3], S2[6] (00,11,22,01,02,12), Sboundary}, block-relative.
+// Partial b: {s_b, S0, S1[4], S2[10] (packed as pk), Sboundary}, block-relative.
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS)
 k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T* Pout,
             double* part, int chunk, int mode) {
-    __shared__ double sh[11 * RED_THREADS];
+    __shared__ double sh[NACC * RED_THREADS];
     const int b = blockIdx.x;
     const int lo = b * chunk;
     const int hi = min(m.ntot, lo + chunk);
@@ -488,46 +536,36 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
     if (mode == 1) {
         double mx = -INFINITY;
         for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
-            double u[3] = {0, 0, 0}, x[3];
-            int idx[3];
+            double u[MS] = {0, 0, 0, 0}, x[MS];
+            int idx[MS];
             node_coords(m, tab, j, u, idx);
             to_phys(g, m.nx, u, x);
             mx = fmax(mx, loglik_at(m, x, z.v));
         }
         sb = block_max(mx, sh);
     }
-    double acc[11];
-    for (int q = 0; q < 11; ++q) acc[q] = 0.0;
+    double acc[NACC];
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
     for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
-        double u[3] = {0, 0, 0};
-        int idx[3] = {0, 0, 0};
+        double u[MS] = {0, 0, 0, 0};
+        int idx[MS] = {0, 0, 0, 0};
         node_coords(m, tab, j, u, idx);
         T v = P[j];
         if (mode == 1) {
-            double x[3];
+            double x[MS];
             to_phys(g, m.nx, u, x);
             const double L = loglik_at(m, x, z.v);
             v = v * exp_t((T)(L - sb));
             Pout[j] = v;
         }
         const double w = node_qw(m, tab, idx) * (double)v;
-        acc[0] += w;
-        acc[1] += w * u[0];
-        acc[2] += w * u[1];
-        acc[3] += w * u[2];
-        acc[4] += w * u[0] * u[0];
-        acc[5] += w * u[1] * u[1];
-        acc[6] += w * u[2] * u[2];
-        acc[7] += w * u[0] * u[1];
-        acc[8] += w * u[0] * u[2];
-        acc[9] += w * u[1] * u[2];
-        if (node_on_boundary(m, idx)) acc[10] += w;
+        acc_point(acc, w, u, node_on_boundary(m, idx));
     }
-    block_sum<11>(acc, sh);
+    block_sum<NACC>(acc, sh);
     if (threadIdx.x == 0) {
         double* p = part + (size_t)b * NPART;
         p[0] = sb;
-        for (int q = 0; q < 11; ++q) p[1 + q] = acc[q];
+        for (int q = 0; q < NACC; ++q) p[1 + q] = acc[q];
     }
 }
 
@@ -535,10 +573,10 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
 __device__ void combine_partials(const double* part, int nb, double* s_out, double* S) {
     double s = -INFINITY;
     for (int b = 0; b < nb; ++b) s = fmax(s, part[b * NPART]);
-    for (int q = 0; q < 11; ++q) S[q] = 0.0;
+    for (int q = 0; q < NACC; ++q) S[q] = 0.0;
     for (int b = 0; b < nb; ++b) {
         const double f = (s == -INFINITY) ? 0.0 : exp(part[b * NPART] - s);
-        for (int q = 0; q < 11; ++q) S[q] += f * part[b * NPART + 1 + q];
+        for (int q = 0; q < NACC; ++q) S[q] += f * part[b * NPART + 1 + q];
     }
     *s_out = s;
 }
@@ -546,29 +584,28 @@ __device__ void combine_partials(const double* part, int nb, double* s_out, doub
 // mean and covariance from sums in computational coordinates u (x = c + M u)
 __device__ void moments_from_sums(const Grid& g, int nx, const double* S, double* mean, double* cov) {
     const double S0 = S[0];
-    double ub[3] = {S[1] / S0, S[2] / S0, S[3] / S0};
-    double Cu[9];
+    double ub[MS] = {S[1] / S0, S[2] / S0, S[3] / S0, S[4] / S0};
+    double Cu[MSQ];
     mat_zero(Cu);
-    const int i2[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
     for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < nx; ++b) Cu[a * 3 + b] = S[i2[a][b]] / S0 - ub[a] * ub[b];
-    double mu[3];
+        for (int b = 0; b < nx; ++b) Cu[a * MS + b] = S[5 + pk(a, b)] / S0 - ub[a] * ub[b];
+    double mu[MS];
     mat_vec(mu, g.M, ub, nx);
     for (int a = 0; a < nx; ++a) mean[a] = g.c[a] + mu[a];
-    double t1[9], C[9];
+    double t1[MSQ], C[MSQ];
     mat_mul(t1, g.M, Cu, nx);
     mat_mul_bt(C, t1, g.M, nx);
     for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < nx; ++b) cov[a * 3 + b] = 0.5 * (C[a * 3 + b] + C[b * 3 + a]);
+        for (int b = 0; b < nx; ++b) cov[a * MS + b] = 0.5 * (C[a * MS + b] + C[b * MS + a]);
 }
 
 __device__ bool design_grid_dev(const KModel& m, const double* mean, const double* cov, Grid& gn) {
     mat_zero(gn.M);
     for (int a = 0; a < m.nx; ++a) {
-        const double v = cov[a * 3 + a] + m.Wnom[a * 3 + a];
+        const double v = cov[a * MS + a] + m.Wnom[a * MS + a];
         if (!(v > 0.0) || !isfinite(v)) return false;
         const double h = m.span * sqrt(v);
-        gn.M[a * 3 + a] = (m.grid == PMF_GRID_FOURIER) ? 2.0 * h / m.N[a] : h;
+        gn.M[a * MS + a] = (m.grid == PMF_GRID_FOURIER) ? 2.0 * h / m.N[a] : h;
         gn.c[a] = mean[a];
     }
     grid_finish(gn, m.nx);
@@ -579,7 +616,7 @@ __device__ bool design_grid_dev(const KModel& m, const double* mean, const doubl
 // new grid.  On failure: ok = 0 and the DEGENERATE bit.
 __global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s, S[11];
+    double s, S[NACC];
     combine_partials(part, nb, &s, S);
     const double mass = d->g.vol * S[0];
     d->ok = 1;
@@ -590,7 +627,7 @@ __global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int 
         d->mass = mass;
         d->loglik = s + log(mass);
         moments_from_sums(d->g, m.nx, S, d->mean, d->cov);
-        d->bfrac = S[10] / S[0];
+        d->bfrac = S[NACC - 1] / S[0];
         if (d->bfrac > BOUNDARY_TOL) d->status |= ST_BOUNDARY;
         for (int b = 0; b < nb; ++b) bfac[b] = exp(part[b * NPART] - s) / mass;
         if (!design_grid_dev(m, d->mean, d->cov, d->gn)) d->ok = 0;
@@ -599,7 +636,7 @@ __global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int 
         bool aligned = true;
         for (int a = 0; a < m.nx; ++a)
             for (int b = 0; b < m.nx; ++b)
-                if (a != b && d->g.M[a * 3 + b] != 0.0) aligned = false;
+                if (a != b && d->g.M[a * MS + b] != 0.0) aligned = false;
         d->sep = (m.interp == PMF_INTERP_AUTO && aligned) ? 1 : 0;
     }
     if (!d->ok) {
@@ -611,7 +648,7 @@ __global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int 
 // After k_like_pass(mode 0): mass, moments and 1/mass (in bfac[0..nb)).
 __global__ void k_sums_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s, S[11];
+    double s, S[NACC];
     combine_partials(part, nb, &s, S);
     const double mass = d->g.vol * S[0];
     d->mass = mass;
@@ -641,10 +678,10 @@ __global__ void k_interp_weights(KModel m, const DevDesc* d, const double* tab, 
     const int jp = e / n, j = e - jp * n;
     const Grid& go = d->g;
     const Grid& gn = d->gn;
-    const double xn = gn.c[a] + gn.M[a * 3 + a] * tab[a * TAB_STRIDE + jp];
+    const double xn = gn.c[a] + gn.M[a * MS + a] * tab[a * TAB_STRIDE + jp];
     double w = 0.0;
     if (m.grid == PMF_GRID_FOURIER) {
-        const double nu = (xn - go.c[a]) * go.Mi[a * 3 + a] + (double)(n / 2);
+        const double nu = (xn - go.c[a]) * go.Mi[a * MS + a] + (double)(n / 2);
         if (nu >= 0.0 && nu <= (double)(n - 1)) {
             const double dd = nu - (double)j;
             if (dd == 0.0) {
@@ -654,7 +691,7 @@ __global__ void k_interp_weights(KModel m, const DevDesc* d, const double* tab, 
             }
         }
     } else {
-        const double u = (xn - go.c[a]) * go.Mi[a * 3 + a];
+        const double u = (xn - go.c[a]) * go.Mi[a * MS + a];
         if (u >= -1.0 && u <= 1.0) {
             const double* v = tab + a * TAB_STRIDE + TAB_V;
             const double* beta = tab + a * TAB_STRIDE + TAB_BETA;
@@ -684,7 +721,7 @@ template <typename T>
 __global__ void __launch_bounds__(RED_THREADS)
 k_interp_axis(KModel m, const DevDesc* d, const double* tab, const double* Wall, int a,
               const T* in, T* out, double* part, int chunk, int want_sums) {
-    __shared__ double sh[11 * RED_THREADS];
+    __shared__ double sh[NACC * RED_THREADS];
     if (!d->sep) return;
     const int n = m.N[a];
     int s = 1;
@@ -692,8 +729,8 @@ k_interp_axis(KModel m, const DevDesc* d, const double* tab, const double* Wall,
     const double* W = Wall + (size_t)a * m.wstride;
     const int lo = blockIdx.x * chunk;
     const int hi = min(m.ntot, lo + chunk);
-    double acc[11];
-    for (int q = 0; q < 11; ++q) acc[q] = 0.0;
+    double acc[NACC];
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
     for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
         const int i = j % s;
         const int jp = (j / s) % n;
@@ -703,28 +740,19 @@ k_interp_axis(KModel m, const DevDesc* d, const double* tab, const double* Wall,
         for (int k = 0; k < n; ++k) v += W[jp * n + k] * (double)src[(size_t)k * s];
         out[j] = (T)v;
         if (want_sums) {
-            double u[3] = {0, 0, 0};
-            int idx[3] = {0, 0, 0};
+            double u[MS] = {0, 0, 0, 0};
+            int idx[MS] = {0, 0, 0, 0};
             node_coords(m, tab, j, u, idx);
             const double w = node_qw(m, tab, idx) * (double)(T)v;
-            acc[0] += w;
-            acc[1] += w * u[0];
-            acc[2] += w * u[1];
-            acc[3] += w * u[2];
-            acc[4] += w * u[0] * u[0];
-            acc[5] += w * u[1] * u[1];
-            acc[6] += w * u[2] * u[2];
-            acc[7] += w * u[0] * u[1];
-            acc[8] += w * u[0] * u[2];
-            acc[9] += w * u[1] * u[2];
+            acc_point(acc, w, u, false);
         }
     }
     if (want_sums) {
-        block_sum<11>(acc, sh);
+        block_sum<NACC>(acc, sh);
         if (threadIdx.x == 0) {
             double* p = part + (size_t)blockIdx.x * NPART;
             p[0] = 0.0;
-            for (int q = 0; q < 11; ++q) p[1 + q] = acc[q];
+            for (int q = 0; q < NACC; ++q) p[1 + q] = acc[q];
         }
     }
 }
@@ -744,25 +772,24 @@ template <typename T>
 __global__ void __launch_bounds__(RED_THREADS)
 k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T* out,
                   double* part, int chunk) {
-    __shared__ double sh[11 * RED_THREADS];
+    __shared__ double sh[NACC * RED_THREADS];
     if (d->sep) return;
     const Grid& go = d->g;
     const Grid& gn = d->gn;
     const int lo = blockIdx.x * chunk;
     const int hi = min(m.ntot, lo + chunk);
-    double acc[11];
-    for (int q = 0; q < 11; ++q) acc[q] = 0.0;
+    double acc[NACC];
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
     for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
-        double u[3] = {0, 0, 0}, x[3], r[3], nu[3] = {0, 0, 0};
-        int idx[3] = {0, 0, 0};
+        double u[MS] = {0, 0, 0, 0}, x[MS], r[MS], nu[MS] = {0, 0, 0, 0};
+        int idx[MS] = {0, 0, 0, 0};
         node_coords(m, tab, j, u, idx);
         to_phys(gn, m.nx, u, x);
         for (int a = 0; a < m.nx; ++a) r[a] = x[a] - go.c[a];
         mat_vec(nu, go.Mi, r, m.nx);
         bool inside = true;
-        int base[3] = {0, 0, 0};
-        int tapidx[3][4];
-        double tw[3][4];
+        int tapidx[MS][4];
+        double tw[MS][4];
         for (int a = 0; a < m.nx; ++a) {
             const int n = m.N[a];
             if (m.grid == PMF_GRID_FOURIER) {
@@ -798,7 +825,6 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
                     if (kk < 1 || kk > n) tw[a][k] = 0.0;
                 }
             }
-            (void)base;
         }
         double val = 0.0;
         if (inside) {
@@ -814,7 +840,7 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
                             rs += tw[1][k1] * (double)in[(size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]];
                     val += tw[0][k0] * rs;
                 }
-            } else {
+            } else if (m.nx == 3) {
                 for (int k0 = 0; k0 < 4; ++k0) {
                     if (tw[0][k0] == 0.0) continue;
                     double ps = 0.0;
@@ -830,27 +856,38 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
                     }
                     val += tw[0][k0] * ps;
                 }
+            } else {
+                for (int k0 = 0; k0 < 4; ++k0) {
+                    if (tw[0][k0] == 0.0) continue;
+                    double s1 = 0.0;
+                    for (int k1 = 0; k1 < 4; ++k1) {
+                        if (tw[1][k1] == 0.0) continue;
+                        double s2 = 0.0;
+                        for (int k2 = 0; k2 < 4; ++k2) {
+                            if (tw[2][k2] == 0.0) continue;
+                            const size_t row =
+                                (((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2] + tapidx[2][k2]) * m.N[3];
+                            double s3 = 0.0;
+                            for (int k3 = 0; k3 < 4; ++k3)
+                                if (tw[3][k3] != 0.0) s3 += tw[3][k3] * (double)in[row + tapidx[3][k3]];
+                            s2 += tw[2][k2] * s3;
+                        }
+                        s1 += tw[1][k1] * s2;
+                    }
+                    val += tw[0][k0] * s1;
+                }
             }
         }
         const T vt = (T)val;
         out[j] = vt;
         const double w = node_qw(m, tab, idx) * (double)vt;
-        acc[0] += w;
-        acc[1] += w * u[0];
-        acc[2] += w * u[1];
-        acc[3] += w * u[2];
-        acc[4] += w * u[0] * u[0];
-        acc[5] += w * u[1] * u[1];
-        acc[6] += w * u[2] * u[2];
-        acc[7] += w * u[0] * u[1];
-        acc[8] += w * u[0] * u[2];
-        acc[9] += w * u[1] * u[2];
+        acc_point(acc, w, u, false);
     }
-    block_sum<11>(acc, sh);
+    block_sum<NACC>(acc, sh);
     if (threadIdx.x == 0) {
         double* p = part + (size_t)blockIdx.x * NPART;
         p[0] = 0.0;
-        for (int q = 0; q < 11; ++q) p[1 + q] = acc[q];
+        for (int q = 0; q < NACC; ++q) p[1 + q] = acc[q];
     }
 }
 
@@ -859,7 +896,7 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
 __global__ void k_interp_finalize(KModel m, DevDesc* d, const double* part, int nb) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (!d->ok) return;
-    double s, S[11];
+    double s, S[NACC];
     combine_partials(part, nb, &s, S);
     const double mass2 = d->gn.vol * S[0];
     if (!isfinite(mass2) || !(mass2 > 0.0)) {
@@ -886,17 +923,17 @@ __global__ void k_final_scale(T* out, const T* old, int ntot, const DevDesc* d) 
 __global__ void k_prior(KModel m, KPrior pr, const DevDesc* d, const double* tab, void* Pv, int prec) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m.ntot) return;
-    double u[3] = {0, 0, 0}, x[3];
-    int idx[3];
+    double u[MS] = {0, 0, 0, 0}, x[MS];
+    int idx[MS];
     node_coords(m, tab, j, u, idx);
     to_phys(d->g, m.nx, u, x);
     double best = -INFINITY, terms[MAXMIX];
     for (int g = 0; g < pr.ncomp; ++g) {
-        double r[3];
+        double r[MS];
         for (int i = 0; i < m.nx; ++i) r[i] = x[i] - pr.mean[g][i];
         double q = 0.0;
         for (int i = 0; i < m.nx; ++i)
-            for (int k = 0; k < m.nx; ++k) q += r[i] * pr.Ci[g][i * 3 + k] * r[k];
+            for (int k = 0; k < m.nx; ++k) q += r[i] * pr.Ci[g][i * MS + k] * r[k];
         terms[g] = pr.lw[g] - 0.5 * q;
         best = terms[g] > best ? terms[g] : best;
     }
@@ -1010,8 +1047,10 @@ hipError_t launch_plan(const PredictArgs& a, DevDesc* d, double* coef, hipStream
         hipLaunchKernelGGL(k_plan<1>, dim3(1), dim3(PLAN_THREADS), 0, st, a, d, coef);
     else if (a.nx == 2)
         hipLaunchKernelGGL(k_plan<2>, dim3(1), dim3(PLAN_THREADS), 0, st, a, d, coef);
-    else
+    else if (a.nx == 3)
         hipLaunchKernelGGL(k_plan<3>, dim3(1), dim3(PLAN_THREADS), 0, st, a, d, coef);
+    else
+        hipLaunchKernelGGL(k_plan<4>, dim3(1), dim3(PLAN_THREADS), 0, st, a, d, coef);
     return hipGetLastError();
 }
 
@@ -1053,15 +1092,10 @@ hipError_t launch_interp(const KModel& m, DevDesc* d, const double* tab, double*
     int maxn = 0;
     for (int a = 0; a < m.nx; ++a) maxn = m.N[a] > maxn ? m.N[a] : maxn;
     hipLaunchKernelGGL(k_interp_weights, dim3(cdiv(maxn * maxn, 256), m.nx), dim3(256), 0, st, m, d, tab, W);
-    T* seq[4] = {post, res, nullptr, nullptr};
-    if (m.nx == 2) {
-        seq[1] = tmp;
-        seq[2] = res;
-    } else if (m.nx == 3) {
-        seq[1] = tmp;
-        seq[2] = post;
-        seq[3] = res;
-    }
+    // axis passes alternate between tmp and post and end in res
+    T* seq[MS + 1] = {post, res, nullptr, nullptr, nullptr};
+    for (int a = 1; a < m.nx; ++a) seq[a] = (a % 2) ? tmp : post;
+    seq[m.nx] = res;
     for (int a = 0; a < m.nx; ++a)
         hipLaunchKernelGGL(k_interp_axis<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, W, a, seq[a],
                            seq[a + 1], part, chunk, a == m.nx - 1 ? 1 : 0);
@@ -1090,8 +1124,6 @@ hipError_t launch_cheb_rhs(const KModel& m, const T* D1, const T* D2, const doub
     const int nx = m.nx;
     const int ntot = m.ntot;
     const int g = cdiv(ntot, 256);
-    const int sidx[3] = {0, 1, 2};
-    const int cross[3][3] = {{-1, 3, 4}, {3, -1, 5}, {4, 5, -1}};
     int strides[3];
     for (int a = 0; a < nx; ++a) {
         int s = 1;
@@ -1100,7 +1132,7 @@ hipError_t launch_cheb_rhs(const KModel& m, const T* D1, const T* D2, const doub
     }
     for (int a = 0; a < nx; ++a) {
         hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, D2 + (size_t)a * 256 * 256, y, kf, m.N[a],
-                           strides[a], ntot, coef, 6 * k + sidx[a], 0.5, a > 0 ? 1 : 0);
+                           strides[a], ntot, coef, PACK * k + pk(a, a), 0.5, a > 0 ? 1 : 0);
     }
     T* tb[3] = {nullptr, t1, t2};
     for (int b = 1; b < nx; ++b) {
@@ -1110,7 +1142,7 @@ hipError_t launch_cheb_rhs(const KModel& m, const T* D1, const T* D2, const doub
     for (int a = 0; a < nx; ++a)
         for (int b = a + 1; b < nx; ++b)
             hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, D1 + (size_t)a * 256 * 256, tb[b], kf,
-                               m.N[a], strides[a], ntot, coef, 6 * k + cross[a][b], 1.0, 1);
+                               m.N[a], strides[a], ntot, coef, PACK * k + pk(a, b), 1.0, 1);
     return hipGetLastError();
 }
 
@@ -1146,7 +1178,7 @@ template <typename T>
 __global__ void k_fdm_gain(T* X, KModel m, const DevDesc* d, const double* coef, double trA, int sine) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m.ntot) return;
-    double cm1[3] = {0.0, 0.0, 0.0};   // cos(theta_a) - 1
+    double cm1[MS] = {0.0, 0.0, 0.0, 0.0};   // cos(theta_a) - 1
     double norm = 1.0;
     int rem = j;
     for (int a = m.nx - 1; a >= 0; --a) {
@@ -1170,7 +1202,7 @@ __global__ void k_fdm_gain(T* X, KModel m, const DevDesc* d, const double* coef,
         const int l = d->l;
         const double h = d->h;
         for (int n = 0; n < l; ++n) {
-            const double* c = coef + 6 * n;   // packed 00, 11, 22, ...
+            const double* c = coef + PACK * n;   // packed diagonal first
             double lam = 1.0 - h * trA;
             for (int a = 0; a < m.nx; ++a) lam += h * c[a] * cm1[a];
             g *= lam;
@@ -1183,7 +1215,7 @@ template <typename T>
 hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, const T* S, T* X, T* t1, T* t2,
                               double trA, int sine, hipStream_t st) {
     const int g = cdiv(m.ntot, 256);
-    int strides[3];
+    int strides[MS];
     for (int a = 0; a < m.nx; ++a) {
         int s = 1;
         for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
