@@ -113,13 +113,16 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip latency / L1 / plain-path legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain device copy of known size (counter scaling)")
-    ap.add_argument("--workload", choices=("batched", "cheb3d", "serve", "single", "convergence"),
+    ap.add_argument("--workload", choices=("batched", "cheb3d", "serve", "single", "convergence", "ct4d"),
                     default="batched",
                     help="batched: the headline batched workload (default); cheb3d: one 3-D "
                          "Chebyshev filter on a 64^3 grid (RK4 on MFMA, range measurement); serve: "
                          "many live tracks fed by Poisson arrivals through the serving runtime; single: "
                          "per-op latency of one 1-D (N 64, FP64) and one 2-D (128^2, FP64 and FP32) filter; "
-                         "convergence: spectral vs finite-difference time update against the heat kernel")
+                         "convergence: spectral vs finite-difference time update against the heat kernel; "
+                         "ct4d: the 4-D coordinated turn with terrain measurements, N_pa = 34, Monte Carlo "
+                         "RMSE / ASTD")
+    ap.add_argument("--mc", type=int, default=20, help="ct4d: Monte-Carlo runs")
     ap.add_argument("--tracks", type=int, default=10000, help="serve: live tracks")
     ap.add_argument("--rates", type=str, default="1000,2000,5000,10000,20000,50000",
                     help="serve: offered request rates (requests/s; one request = predict + update)")
@@ -138,6 +141,8 @@ def main():
         return run_single(args)
     if args.workload == "convergence":
         return run_convergence(args)
+    if args.workload == "ct4d":
+        return run_ct4d(args)
     return run_batched(args)
 
 
@@ -662,6 +667,66 @@ def run_convergence(args):
                                   "0.3 N(-1.2, 0.15) + 0.4 N(0.3, 0.1) + 0.3 N(1.5, 0.2); spans 5 and 8 sigma",
                       "N": list(CONV_N)},
            "fdm_slope_N100_up": slopes, "at_N80_N200": at, "rows": rows,
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ 4-D coordinated turn
+
+def run_ct4d(args):
+    """The paper's numerical illustration at one-GPU scale: coordinated turn with
+    known turn rate, N_pa = 34 (34^4 = 1,336,336 points), the synthetic terrain in
+    place of the SRTM map, mixture measurement noise; RMSE and ASTD per state
+    component over Monte-Carlo runs (steps k = 0..K, the filtering estimate after
+    each update, the prior at k = 0), and the time per predict + update."""
+    import numpy as np
+    import workloads as W
+    from paper_2412_07240_amd import binding as B
+
+    K = args.steps
+    N = 34
+    ctx = B.pmf_ctx_create(0)
+    se = np.zeros(4)
+    var = np.zeros(4)
+    cnt = 0
+    times = []
+    status_bits = 0
+    for mc in range(args.mc):
+        sc = W.config6(K=K, N=N, precision=W.FP32, mc=mc)
+        f = B.pmf_create(ctx, sc.model, sc.prior)
+        m0 = sc.prior.mean[0]
+        se += (sc.truth[0] - m0) ** 2
+        var += np.diag(sc.prior.cov[0])
+        cnt += 1
+        for k in range(K):
+            B.pmf_stream_sync()
+            t0 = time.perf_counter()
+            B.pmf_predict(f, sc.T)
+            B.pmf_update(f, sc.z[k], want_loglik=True)
+            times.append(time.perf_counter() - t0)
+            mean, cov, st = B.pmf_moments(f, 4)
+            status_bits |= int(st)
+            se += (sc.truth[k + 1] - mean) ** 2
+            var += np.diag(cov)
+            cnt += 1
+        B.pmf_destroy(f)
+        log(f"bench ct4d: run {mc} done, {1e3 * np.median(times):.2f} ms per cycle")
+    B.pmf_ctx_destroy(ctx)
+    pts = N ** 4
+    warm = times[args.warmup:] if len(times) > args.warmup else times
+    ms = 1e3 * float(np.median(warm))
+    out = {"metric": METRIC, "value": pts / (ms * 1e-3), "unit": "grid-point updates/s", "n_gpus": 1,
+           "steps": len(warm), "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "4-D coordinated turn (turn rate 30 deg/s, D = diag(0,1,0,1), T_s = 1), "
+                                  "N_pa = 34 (1,336,336 points), synthetic terrain measurement, noise "
+                                  "0.5 N(0,1) + 0.5 N(20,1); one step = predict + update",
+                      "mc_runs": args.mc, "steps_per_run": K},
+           "rmse": {"p_x": float(np.sqrt(se[0] / cnt)), "v_x": float(np.sqrt(se[1] / cnt)),
+                    "p_y": float(np.sqrt(se[2] / cnt)), "v_y": float(np.sqrt(se[3] / cnt))},
+           "astd": {"p_x": float(np.sqrt(var[0] / cnt)), "v_x": float(np.sqrt(var[1] / cnt)),
+                    "p_y": float(np.sqrt(var[2] / cnt)), "v_y": float(np.sqrt(var[3] / cnt))},
+           "status_bits": status_bits, "p99_ms_per_step": 1e3 * float(np.percentile(warm, 99)),
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 

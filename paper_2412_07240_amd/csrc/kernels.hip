@@ -569,15 +569,20 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
     }
 }
 
-// Combine partials in block order: returns S0..Sb relative to the global shift.
-__device__ void combine_partials(const double* part, int nb, double* s_out, double* S) {
-    double s = -INFINITY;
-    for (int b = 0; b < nb; ++b) s = fmax(s, part[b * NPART]);
-    for (int q = 0; q < NACC; ++q) S[q] = 0.0;
-    for (int b = 0; b < nb; ++b) {
+// Combine the per-block partials (all RED_THREADS threads of one block, fixed
+// tree order): S0..Sb relative to the global shift, in every thread.
+__device__ void combine_partials(const double* part, int nb, double* s_out, double* S, double* sh) {
+    double mx = -INFINITY;
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) mx = fmax(mx, part[b * NPART]);
+    const double s = block_max(mx, sh);
+    double acc[NACC];
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) {
         const double f = (s == -INFINITY) ? 0.0 : exp(part[b * NPART] - s);
-        for (int q = 0; q < NACC; ++q) S[q] += f * part[b * NPART + 1 + q];
+        for (int q = 0; q < NACC; ++q) acc[q] += f * part[b * NPART + 1 + q];
     }
+    block_sum<NACC>(acc, sh);
+    for (int q = 0; q < NACC; ++q) S[q] = acc[q];
     *s_out = s;
 }
 
@@ -613,14 +618,19 @@ __device__ bool design_grid_dev(const KModel& m, const double* mean, const doubl
 }
 
 // After k_like_pass(mode 1): normaliser, log-likelihood, moments, block factors,
-// new grid.  On failure: ok = 0 and the DEGENERATE bit.
-__global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// new grid.  On failure: ok = 0 and the DEGENERATE bit.  One block.
+__global__ void __launch_bounds__(RED_THREADS)
+k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
+    __shared__ double sh[NACC * RED_THREADS];
     double s, S[NACC];
-    combine_partials(part, nb, &s, S);
+    combine_partials(part, nb, &s, S, sh);
     const double mass = d->g.vol * S[0];
+    const bool good = isfinite(s) && isfinite(mass) && mass > 0.0;
+    if (good)
+        for (int b = threadIdx.x; b < nb; b += RED_THREADS) bfac[b] = exp(part[b * NPART] - s) / mass;
+    if (threadIdx.x != 0) return;
     d->ok = 1;
-    if (!isfinite(s) || !isfinite(mass) || !(mass > 0.0)) {
+    if (!good) {
         d->ok = 0;
     } else {
         d->s = s;
@@ -629,7 +639,6 @@ __global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int 
         moments_from_sums(d->g, m.nx, S, d->mean, d->cov);
         d->bfrac = S[NACC - 1] / S[0];
         if (d->bfrac > BOUNDARY_TOL) d->status |= ST_BOUNDARY;
-        for (int b = 0; b < nb; ++b) bfac[b] = exp(part[b * NPART] - s) / mass;
         if (!design_grid_dev(m, d->mean, d->cov, d->gn)) d->ok = 0;
         // separable spectral interpolation when the old grid is axis aligned
         // (the new one always is); otherwise cubic Lagrange
@@ -645,15 +654,17 @@ __global__ void k_update_finalize(KModel m, DevDesc* d, const double* part, int 
     }
 }
 
-// After k_like_pass(mode 0): mass, moments and 1/mass (in bfac[0..nb)).
-__global__ void k_sums_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// After k_like_pass(mode 0): mass, moments and 1/mass (in bfac[0..nb)).  One block.
+__global__ void __launch_bounds__(RED_THREADS)
+k_sums_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
+    __shared__ double sh[NACC * RED_THREADS];
     double s, S[NACC];
-    combine_partials(part, nb, &s, S);
+    combine_partials(part, nb, &s, S, sh);
     const double mass = d->g.vol * S[0];
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) bfac[b] = 1.0 / mass;
+    if (threadIdx.x != 0) return;
     d->mass = mass;
     moments_from_sums(d->g, m.nx, S, d->mean, d->cov);
-    for (int b = 0; b < nb; ++b) bfac[b] = 1.0 / mass;
 }
 
 template <typename T>
@@ -892,12 +903,14 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
 }
 
 // New grid's mass -> 1/mass, commit the grid.  A zero / non-finite mass rejects
-// the update (state unchanged).
-__global__ void k_interp_finalize(KModel m, DevDesc* d, const double* part, int nb) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (!d->ok) return;
+// the update (state unchanged).  One block.
+__global__ void __launch_bounds__(RED_THREADS)
+k_interp_finalize(KModel m, DevDesc* d, const double* part, int nb) {
+    __shared__ double sh[NACC * RED_THREADS];
+    if (!d->ok) return;   // uniform over the block
     double s, S[NACC];
-    combine_partials(part, nb, &s, S);
+    combine_partials(part, nb, &s, S, sh);
+    if (threadIdx.x != 0) return;
     const double mass2 = d->gn.vol * S[0];
     if (!isfinite(mass2) || !(mass2 > 0.0)) {
         d->ok = 0;
@@ -1066,13 +1079,13 @@ hipError_t launch_like(const KModel& m, const DevDesc* d, const double* tab, con
 
 hipError_t launch_update_finalize(const KModel& m, DevDesc* d, const double* part, int nb, double* bfac,
                                   hipStream_t st) {
-    hipLaunchKernelGGL(k_update_finalize, dim3(1), dim3(1), 0, st, m, d, part, nb, bfac);
+    hipLaunchKernelGGL(k_update_finalize, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac);
     return hipGetLastError();
 }
 
 hipError_t launch_sums_finalize(const KModel& m, DevDesc* d, const double* part, int nb, double* bfac,
                                 hipStream_t st) {
-    hipLaunchKernelGGL(k_sums_finalize, dim3(1), dim3(1), 0, st, m, d, part, nb, bfac);
+    hipLaunchKernelGGL(k_sums_finalize, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac);
     return hipGetLastError();
 }
 
@@ -1101,7 +1114,7 @@ hipError_t launch_interp(const KModel& m, DevDesc* d, const double* tab, double*
                            seq[a + 1], part, chunk, a == m.nx - 1 ? 1 : 0);
     hipLaunchKernelGGL(k_interp_lagrange<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, post, res, part,
                        chunk);
-    hipLaunchKernelGGL(k_interp_finalize, dim3(1), dim3(1), 0, st, m, d, part, nb);
+    hipLaunchKernelGGL(k_interp_finalize, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb);
     return hipGetLastError();
 }
 
