@@ -372,8 +372,8 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     };
     for (int i = 0; i < 4; ++i) f->buf[i] = A(f->ntot * f->es);
     if (model->grid == PMF_GRID_FOURIER) f->cbuf = A(f->ntot * f->es * 2);
-    f->part = static_cast<double*>(A((size_t)MAX_RED_BLOCKS * NPART * sizeof(double)));
-    f->bfac = static_cast<double*>(A((size_t)MAX_RED_BLOCKS * sizeof(double)));
+    f->part = static_cast<double*>(A((size_t)f->nb * NPART * sizeof(double)));
+    f->bfac = static_cast<double*>(A((size_t)f->nb * sizeof(double)));
     f->coef = static_cast<double*>(A((size_t)(2 * LMAX + 1) * PACK * sizeof(double)));
     f->W = static_cast<double*>(A((size_t)model->nx * f->km.wstride * sizeof(double)));
     f->tab = static_cast<double*>(A((size_t)MS * TAB_STRIDE * sizeof(double)));

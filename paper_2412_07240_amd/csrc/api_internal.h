@@ -52,7 +52,7 @@ struct pmf_filter {
 
 namespace pmf {
 
-constexpr int MAX_RED_BLOCKS = 512;
+constexpr int MAX_RED_BLOCKS = 2048;   // reduction blocks of 1024 points (more: longer chunks)
 
 extern thread_local std::string g_last_error;
 pmf_status fail(pmf_status s, const std::string& msg);
