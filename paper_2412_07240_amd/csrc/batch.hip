@@ -467,6 +467,11 @@ __device__ inline double floglik(const FPlan& P, const KModel& m, double u0, dou
     return floglik_general(m, P, u0, u1, z);
 }
 
+// al + u0 (be + ga u0), one rounding order everywhere it is evaluated
+__device__ __forceinline__ double qpoly(double al, double be, double ga, double u0) {
+    return fma(u0, fma(ga, u0, be), al);
+}
+
 // trigonometric interpolant of the n samples Po[0..n) at index position nu (1-D)
 __device__ __noinline__ float trig_interp_1d(const float* Po, int n, double nu) {
     const double fl = floor(nu);
@@ -946,10 +951,24 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     const double u0first = (NX == 2) ? (double)tr - half0 : uj;
     constexpr double du0 = (NX == 2) ? (double)RPS : 0.0;
     if (act) {
-        double u0 = u0first;
-        for (int r = tr; r < N0; r += RPS, u0 += du0) {
-            const double L = Pg.fast ? al + u0 * (be + ga * u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
-            mx = fmax(mx, L);
+        if (Pg.fast && (NX == 1 || ga < 0.0)) {
+            // a concave quadratic along this thread's rows u0 = u0first + k RPS:
+            // its maximum over them sits at the row nearest the vertex (or a
+            // neighbour, within rounding)
+            const int cnt = (N0 - tr + RPS - 1) / RPS;
+            int ks = 0;
+            if (NX == 2) {
+                const double kv = (-be / (2.0 * ga) - u0first) / du0;
+                ks = kv <= 0.0 ? 0 : (kv >= (double)(cnt - 1) ? cnt - 1 : (int)rint(kv));
+            }
+            for (int k = ks - 1; k <= ks + 1; ++k)
+                if (k >= 0 && k < cnt) mx = fmax(mx, qpoly(al, be, ga, u0first + (double)k * du0));
+        } else {
+            double u0 = u0first;
+            for (int r = tr; r < N0; r += RPS, u0 += du0) {
+                const double L = Pg.fast ? qpoly(al, be, ga, u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
+                mx = fmax(mx, L);
+            }
         }
     }
     mx = cseg_max<G, SEGW>(mx, slots);
@@ -964,7 +983,7 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
         float* po = Po + tr * RS + g * RP + j;
 #pragma unroll 2
         for (int r = tr; r < N0; r += RPS, u0 += du0, pr += RPS * RS, po += RPS * RS) {
-            const double L = Pg.fast ? al + u0 * (be + ga * u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
+            const double L = Pg.fast ? qpoly(al, be, ga, u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
             const float v = *pr * __expf((float)(L - sh));
             *po = v;
             const double w = (double)v;
