@@ -347,6 +347,7 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     P.T = a.T;
     // grid follows x' = A x
     double c2[MS], M2[MSQ];
+    mat_zero(M2);
     mat_vec(c2, a.Phi, g.c, n);
     mat_mul(M2, a.Phi, g.M, n);
     for (int i = 0; i < n; ++i) g.c[i] = c2[i];
@@ -662,11 +663,12 @@ __device__ void filter_design(FState& F, const double* acc, int NX, int n0, int 
     if (!F.ok) return;
     F.inv_mass = 1.0 / mass;
     F.loglik = F.s + log(mass);
-    const double ub0 = acc[1] / S0, ub1 = acc[2] / S0;
-    const double C00 = acc[3] / S0 - ub0 * ub0;
-    const double C11 = acc[4] / S0 - ub1 * ub1;
-    const double C01 = acc[5] / S0 - ub0 * ub1;
-    if (acc[6] / S0 > BOUNDARY_TOL) F.bits = PMF_W_BOUNDARY;
+    const double iS0 = 1.0 / S0;
+    const double ub0 = acc[1] * iS0, ub1 = acc[2] * iS0;
+    const double C00 = acc[3] * iS0 - ub0 * ub0;
+    const double C11 = acc[4] * iS0 - ub1 * ub1;
+    const double C01 = acc[5] * iS0 - ub0 * ub1;
+    if (acc[6] * iS0 > BOUNDARY_TOL) F.bits = PMF_W_BOUNDARY;
     double mean0, mean1, cov00, cov11;
     if (NX == 2) {
         mean0 = P.c[0] + P.M[0] * ub0 + P.M[1] * ub1;
@@ -739,8 +741,19 @@ __device__ void filter_commit(const FState& F, const BItem& I, double* ll_out) {
         }
     }
     grid_finish(gg, P.nx);
-    d->g = gg;
-    d->gn = gg;
+    // the batched grid is at most 2 x 2: only that block of the descriptor
+    // changes (the rest is zero since the filter was created)
+    d->g.c[0] = gg.c[0];
+    d->g.c[1] = gg.c[1];
+    d->g.M[0] = gg.M[0];
+    d->g.M[1] = gg.M[1];
+    d->g.M[MS] = gg.M[MS];
+    d->g.M[MS + 1] = gg.M[MS + 1];
+    d->g.Mi[0] = gg.Mi[0];
+    d->g.Mi[1] = gg.Mi[1];
+    d->g.Mi[MS] = gg.Mi[MS];
+    d->g.Mi[MS + 1] = gg.Mi[MS + 1];
+    d->g.vol = gg.vol;
     d->t += P.T;
     d->l = P.l;
     d->h = P.h;
@@ -786,12 +799,20 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     const int tid = threadIdx.x;
     const int Gact = GI.G;   // filters present (<= G)
 
+    // plans into LDS, one 8-byte word per thread (one round trip for the group)
+    constexpr int PW = sizeof(FPlan) / sizeof(double);
+    static_assert(sizeof(FPlan) % sizeof(double) == 0, "FPlan is copied as doubles");
+    for (int e = tid; e < G * PW; e += NT) {
+        const int g = e / PW, w = e - g * PW;
+        const int gg = g < Gact ? g : 0;
+        reinterpret_cast<double*>(&FS[g].p)[w] = reinterpret_cast<const double*>(&plans[GI.first + gg])[w];
+    }
     if (tid < G) {
         const int gg = tid < Gact ? tid : 0;
-        FS[tid].p = plans[GI.first + gg];
         const BItem& I = items[GI.first + gg];
-        FS[tid].pin = I.P[FS[tid].p.par];
-        FS[tid].pout = I.P[1 - FS[tid].p.par];
+        const int par = plans[GI.first + gg].par;
+        FS[tid].pin = I.P[par];
+        FS[tid].pout = I.P[1 - par];
     }
     for (int i = tid; i < H1; i += NT) {
         float sn, cs;
@@ -812,7 +833,8 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     __syncthreads();
 
     // ---- load: super-row L = r*G + g holds row r of filter g as complex pairs
-#pragma unroll 1
+    // (unrolled: every load of the thread is in flight before the first wait)
+#pragma unroll
     for (int e = tid; e < G * N0 * H1; e += NT) {
         const int L = e / H1, k = e - L * H1;
         const int r = L / G, g = L - r * G;

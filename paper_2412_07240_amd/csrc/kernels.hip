@@ -339,6 +339,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan(PredictArgs a, DevDesc* d
     if (threadIdx.x == 0) {
         // grid follows x' = A x over T
         double c2[MS], M2[MSQ];
+        mat_zero(M2);
         mat_vec(c2, a.Phi, d->g.c, n);
         mat_mul(M2, a.Phi, d->g.M, n);
         for (int i = 0; i < n; ++i) d->g.c[i] = c2[i];
