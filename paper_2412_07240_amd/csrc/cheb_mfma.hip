@@ -198,6 +198,107 @@ k_cheb_pass(ChebGeom G, int axis, const float* __restrict__ D1, const float* __r
     }
 }
 
+// 3-D with square planes (N_1 = N_2 = n): the last- and middle-axis passes fused.
+// A workgroup owns plane i0 (all of it in LDS) and a chunk of 16 columns j2.
+//   step 1 (last axis, lines j1):    t2 = D1_2 y,  kp = 1/2 Dy_22 D2_2 y   on the chunk
+//   step 2 (middle axis, lines j2):  kf = kp + 1/2 Dy_11 D2_1 y + Dy_12 D1_1 t2,
+//                                    u  = Dy_01 D1_1 y + Dy_02 t2
+// so t2 never leaves LDS and one launch replaces two.  Wave w takes lines
+// 16w .. 16w+15 in step 1 and output rows 16w .. 16w+15 in step 2.
+template <int NB>
+__global__ void __launch_bounds__(64 * NB)
+k_cheb_plane(int n0, const float* __restrict__ D1, const float* __restrict__ D2, const double* __restrict__ coef,
+             int cidx, const float* __restrict__ y, float* __restrict__ kf, float* __restrict__ u) {
+    constexpr int n = 16 * NB, TS = n + 4, CS = CL + 1;
+    __shared__ float Yp[n * TS];      // the plane, Yp[j1][j2]
+    __shared__ float T2[n * CS];      // t2 on the chunk, T2[j1][j2 - 16c]
+    __shared__ float KP[n * CS];      // 1/2 Dy_22 D2_2 y on the chunk
+    const int c = blockIdx.x, i0 = blockIdx.y;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = l & 15, lk = l >> 4;
+    const float* yp = y + (size_t)i0 * n * n;
+    // ---- issue the global loads: the plane, the rows of the four matrices
+    float4 vp[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int e = threadIdx.x + q * 64 * NB;   // float4 index in the plane
+        vp[q] = *reinterpret_cast<const float4*>(yp + 4 * e);
+    }
+    const float* D1a2 = D1 + (size_t)2 * 256 * 256;   // axis 2
+    const float* D2a2 = D2 + (size_t)2 * 256 * 256;
+    const float* D1a1 = D1 + (size_t)1 * 256 * 256;   // axis 1
+    const float* D2a1 = D2 + (size_t)1 * 256 * 256;
+    float4 s1[NB], s2[NB], m1[NB], m2[NB];
+    {
+        const size_t rc = (size_t)(16 * c + li) * n + 4 * lk;   // chunk rows of the axis-2 matrices
+        const size_t rw = (size_t)(16 * w + li) * n + 4 * lk;   // this wave's rows of the axis-1 matrices
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) {
+            s1[kb] = *reinterpret_cast<const float4*>(D1a2 + rc + 16 * kb);
+            s2[kb] = *reinterpret_cast<const float4*>(D2a2 + rc + 16 * kb);
+            m1[kb] = *reinterpret_cast<const float4*>(D1a1 + rw + 16 * kb);
+            m2[kb] = *reinterpret_cast<const float4*>(D2a1 + rw + 16 * kb);
+        }
+    }
+    const double* cc = coef + PACK * cidx;
+    const float c22h = 0.5f * (float)cc[2], c11h = 0.5f * (float)cc[1];
+    const float c12 = (float)cc[pk(1, 2)], c01 = (float)cc[pk(0, 1)], c02 = (float)cc[pk(0, 2)];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int e = threadIdx.x + q * 64 * NB;
+        const int r = e / (n / 4), k4 = e - r * (n / 4);
+        *reinterpret_cast<float4*>(Yp + r * TS + 4 * k4) = vp[q];
+    }
+    __syncthreads();
+
+    // ---- step 1: lines j1 = 16w + li, output rows j2 = 16c + 4lk + r
+    {
+        floatx4 P = {0.f, 0.f, 0.f, 0.f}, X = P;
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) {
+            const float4 b = *reinterpret_cast<const float4*>(Yp + (16 * w + li) * TS + 16 * kb + 4 * lk);
+            P = mfma4(s2[kb], b, P);
+            X = mfma4(s1[kb], b, X);
+        }
+        const int j1 = 16 * w + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T2[j1 * CS + 4 * lk + r] = X[r];
+            KP[j1 * CS + 4 * lk + r] = c22h * P[r];
+        }
+    }
+    __syncthreads();
+
+    // ---- step 2: lines j2 = 16c + li, output rows j1 = 16w + 4lk + r
+    floatx4 P = {0.f, 0.f, 0.f, 0.f}, X = P, Y = P;
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) {
+        const int k0 = 16 * kb + 4 * lk;
+        float4 by, bt;
+        by.x = Yp[(k0 + 0) * TS + 16 * c + li];
+        by.y = Yp[(k0 + 1) * TS + 16 * c + li];
+        by.z = Yp[(k0 + 2) * TS + 16 * c + li];
+        by.w = Yp[(k0 + 3) * TS + 16 * c + li];
+        bt.x = T2[(k0 + 0) * CS + li];
+        bt.y = T2[(k0 + 1) * CS + li];
+        bt.z = T2[(k0 + 2) * CS + li];
+        bt.w = T2[(k0 + 3) * CS + li];
+        P = mfma4(m2[kb], by, P);
+        X = mfma4(m1[kb], by, X);
+        Y = mfma4(m1[kb], bt, Y);
+    }
+    float* kfp = kf + (size_t)i0 * n * n;
+    float* up = u + (size_t)i0 * n * n;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j1 = 16 * w + 4 * lk + r;
+        const size_t a = (size_t)j1 * n + 16 * c + li;
+        kfp[a] = KP[j1 * CS + li] + c11h * P[r] + c12 * Y[r];
+        up[a] = c01 * X[r] + c02 * T2[j1 * CS + li];
+    }
+    (void)n0;
+}
+
 bool cheb_mfma_available(pmf_filter* f) {
     if (f->model.grid != PMF_GRID_CHEBYSHEV || f->model.precision != PMF_FP32) return false;
     if (f->model.nx < 2) return false;
@@ -237,6 +338,29 @@ static hipError_t launch_pass_n(const ChebGeom& G, int axis, pmf_filter* f, int 
     return hipErrorInvalidValue;
 }
 
+static hipError_t launch_plane(const ChebGeom& G, pmf_filter* f, int cidx, const float* y, float* kf, float* u,
+                               hipStream_t st) {
+    const float* D1 = static_cast<const float*>(f->D1);
+    const float* D2 = static_cast<const float*>(f->D2);
+    const dim3 grid(G.N[2] / CL, G.N[0]);
+#define PMF_PLANE_CASE(nb)                                                                                  \
+    case nb:                                                                                                \
+        hipLaunchKernelGGL(k_cheb_plane<nb>, grid, dim3(64 * nb), 0, st, G.N[0], D1, D2, f->coef, cidx, y, kf, u); \
+        return hipGetLastError();
+    switch (G.N[2] / 16) {
+        PMF_PLANE_CASE(1)
+        PMF_PLANE_CASE(2)
+        PMF_PLANE_CASE(3)
+        PMF_PLANE_CASE(4)
+        PMF_PLANE_CASE(5)
+        PMF_PLANE_CASE(6)
+        PMF_PLANE_CASE(7)
+        PMF_PLANE_CASE(8)
+    }
+#undef PMF_PLANE_CASE
+    return hipErrorInvalidValue;
+}
+
 pmf_status cheb_predict_mfma(pmf_filter* f, int l, hipStream_t st) {
     ChebGeom G;
     G.nx = f->model.nx;
@@ -257,15 +381,21 @@ pmf_status cheb_predict_mfma(pmf_filter* f, int l, hipStream_t st) {
     hipError_t e = hipSuccess;
     const int nx = G.nx;
     float* u = t1;   // D1_0 operand of the first-axis pass
+    // square planes: the last- and middle-axis passes run fused
+    const bool plane = nx == 3 && G.N[1] == G.N[2];
     for (int n = 0; n < l && e == hipSuccess; ++n) {
         // coefficient sets at the substep start, midpoint (twice) and end
         const int ks[4] = {2 * n, 2 * n + 1, 2 * n + 1, 2 * n + 2};
         for (int stg = 1; stg <= 4 && e == hipSuccess; ++stg) {
             const float* in = (stg == 1) ? q : y;
             const int k = ks[stg - 1];
-            e = launch_pass_n<PASS_LAST>(G, nx - 1, f, k, stg, in, nullptr, kf, nx == 3 ? t2 : u, q, y, acc, st);
-            if (e == hipSuccess && nx == 3)
-                e = launch_pass_n<PASS_MID>(G, 1, f, k, stg, in, t2, kf, u, q, y, acc, st);
+            if (plane) {
+                e = launch_plane(G, f, k, in, kf, u, st);
+            } else {
+                e = launch_pass_n<PASS_LAST>(G, nx - 1, f, k, stg, in, nullptr, kf, nx == 3 ? t2 : u, q, y, acc, st);
+                if (e == hipSuccess && nx == 3)
+                    e = launch_pass_n<PASS_MID>(G, 1, f, k, stg, in, t2, kf, u, q, y, acc, st);
+            }
             if (e == hipSuccess) e = launch_pass_n<PASS_FIRST>(G, 0, f, k, stg, in, u, kf, nullptr, q, y, acc, st);
         }
     }
