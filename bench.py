@@ -384,7 +384,7 @@ def run_cheb3d(args):
                    "points": pts, "T": sc.T, "substeps": subs, "reductions": "f64"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "pmf::k_cheb_pass (all passes of a predict)",
+                     "kernel": "pmf::k_cheb_plane + pmf::k_cheb_pass (all passes of a predict)",
                      "predict_ms": float(np.mean(pred_ms)),
                      "us_per_substep": 1e3 * sum(pred_ms) / lsum,
                      "algorithmic_flops_per_predict": flops / args.steps},

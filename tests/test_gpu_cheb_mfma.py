@@ -78,6 +78,15 @@ def test_mfma_3d_ragged_axes(B, ctx):
     lockstep_predicts(B, ctx, m, sc.prior, 2e-4, [None], "cheb3d-ragged")
 
 
+def test_mfma_3d_plane_pass_rectangular(B, ctx):
+    # square planes (N_1 = N_2 = 48) on a shorter first axis (N_0 = 32): the fused
+    # plane pass with 3-wave workgroups and three 16-column chunks per plane
+    note("case: Chebyshev 3-D N=(32,48,48) FP32 (MFMA, fused plane pass), T=0.01")
+    sc = W.config3(K=1, N=16, precision=W.FP32)
+    m = sc.model.with_(N=(32, 48, 48))
+    lockstep_predicts(B, ctx, m, sc.prior, 0.01, [None], "cheb3d-plane-rect")
+
+
 def test_mfma_2d_sheared(B, ctx):
     note("case: Chebyshev 2-D N=(64,32) FP32 (MFMA), sheared A, linear measurement")
     sc = W.config3(K=2, N=16, precision=W.FP32)
