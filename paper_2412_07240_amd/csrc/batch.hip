@@ -23,6 +23,11 @@ constexpr int FUSED_THREADS = 1024;
 constexpr int FUSED_LMAX = 64;
 
 constexpr int GMAX = 16;            // filters of one size packed into a workgroup
+constexpr int CPLX_BUDGET = 9400;   // complex LDS entries per buffer (2 buffers)
+
+// zero rows around a 2-D posterior in LDS (one above, one below): with the row
+// pads they let every cubic stencil read its 4 x 4 taps without bounds checks
+constexpr int guard_rows(int n0) { return n0 > 1 ? 2 : 0; }
 
 struct FConst {
     KModel m;
@@ -944,7 +949,20 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     cur = cfft<H1, N0 * G, PITCH, 1, +1, true>(oth, cur, twr);
     oth = (cur == bufA) ? bufB : bufA;
     const float* Pr = reinterpret_cast<const float*>(cur);   // predicted: (r, g, j) at r*RS + g*RP + j
-    float* Po = reinterpret_cast<float*>(oth);               // posterior, same layout
+    // posterior, same layout, starting one row into the buffer (2-D): rows -1 and
+    // N0 and the two pad floats of every row are zeroed here (positions the
+    // likelihood pass does not write, so no barrier is needed)
+    float* Po = reinterpret_cast<float*>(oth) + guard_rows(N0) / 2 * RS;
+    if constexpr (NX == 2) {
+        for (int e = tid; e < RS; e += NT) {
+            Po[e - RS] = 0.f;
+            Po[N0 * RS + e] = 0.f;
+        }
+        for (int e = tid; e < N0 * G * 2; e += NT) {
+            const int rg = e >> 1;
+            Po[rg * RP + N1 + (e & 1)] = 0.f;
+        }
+    }
 
     // ---- likelihood (FP64 Horner in u0 per thread), shift, multiply, FP64 sums
     const int tr = tid / TPR;
@@ -1061,35 +1079,19 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
             for (int r = tr; r < N0; r += RPS, nu0 += dn0, nu1 += dn1) {
                 float val = 0.f;
                 if (nu0 >= 0.0 && nu0 <= (double)(N0 - 1) && nu1 >= 0.0 && nu1 <= (double)(N1 - 1)) {
-                    const int i0 = (int)nu0, i1 = (int)nu1;   // floor: nu >= 0
+                    // stencil base at most N - 2: on the last node the weights are
+                    // exactly (0, 0, 1, 0), the node's value as with base N - 1
+                    const int i0 = min((int)nu0, N0 - 2), i1 = min((int)nu1, N1 - 2);   // floor: nu >= 0
                     float w0[4], w1[4];
                     cubic_weights((float)(nu0 - i0), w0);
                     cubic_weights((float)(nu1 - i1), w1);
-                    if (i0 >= 1 && i0 <= N0 - 3 && i1 >= 1 && i1 <= N1 - 3) {
-                        // interior: the 4 x 4 stencil at constant offsets from one base
-                        const float* p = Pog + (i0 - 1) * RS + (i1 - 1);
+                    // the 4 x 4 stencil at constant offsets from one base; taps outside
+                    // the grid read the zero guard rows and row pads
+                    const float* p = Pog + (i0 - 1) * RS + (i1 - 1);
 #pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const float* row = p + a * RS;
-                            val += w0[a] * (w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3]);
-                        }
-                    } else {
-                        int ra[4], cb[4];
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const int rr = i0 - 1 + a, cc = i1 - 1 + a;
-                            const bool okr = rr >= 0 && rr < N0, okc = cc >= 0 && cc < N1;
-                            ra[a] = okr ? rr : i0;
-                            cb[a] = okc ? cc : i1;
-                            if (!okr) w0[a] = 0.f;
-                            if (!okc) w1[a] = 0.f;
-                        }
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const float* row = Pog + ra[a] * RS;
-                            val += w0[a] * (w1[0] * row[cb[0]] + w1[1] * row[cb[1]] + w1[2] * row[cb[2]] +
-                                            w1[3] * row[cb[3]]);
-                        }
+                    for (int a = 0; a < 4; ++a) {
+                        const float* row = p + a * RS;
+                        val += w0[a] * (w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3]);
                     }
                 }
                 val *= inv_mass;
@@ -1135,7 +1137,8 @@ constexpr int group_g() {
     constexpr int pitch = N1 / 2 + 1;
     constexpr int seg = pow2_ceil(N1) < 32 ? 32 : pow2_ceil(N1);
     int G = 1;
-    while (G < GMAX && N0 * (2 * G) * pitch <= 8704 && (2 * G) * seg <= FUSED_THREADS) G *= 2;
+    while (G < GMAX && (N0 + guard_rows(N0)) * (2 * G) * pitch <= CPLX_BUDGET && (2 * G) * seg <= FUSED_THREADS)
+        G *= 2;
     return G;
 }
 
@@ -1146,7 +1149,7 @@ k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__
     for (;;) {
         if (threadIdx.x == 0) pmf_item = atomicAdd(ctr, 1);
         __syncthreads();
-        const int it = pmf_item;
+        const int it = __builtin_amdgcn_readfirstlane(pmf_item);
         __syncthreads();
         if (it >= ngroups) break;
         const GItem GI = groups[it];
@@ -1248,8 +1251,6 @@ struct BatchCache {
 };
 
 namespace pmf {
-
-constexpr int CPLX_BUDGET = 8704;   // complex LDS entries per buffer (2 buffers)
 
 static void cache_free(pmf_ctx* ctx, BatchCache* c) {
     if (!c) return;
@@ -1380,7 +1381,7 @@ static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sort
         }
         gi.G = cnt;
         groups.push_back(gi);
-        maxcplx = std::max(maxcplx, gi.n0 * G * pitch);
+        maxcplx = std::max(maxcplx, (gi.n0 + guard_rows(gi.n0)) * G * pitch);
     }
     return maxcplx;
 }
