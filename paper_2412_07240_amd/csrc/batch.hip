@@ -613,12 +613,36 @@ __device__ inline void cseg_sum(double* v, double* slots) {
     constexpr int RPS = FUSED_THREADS / TPR;
     constexpr int PER_ROW = TPR / SW, PER_SEG = SEGW / SW;
     constexpr int NSLOT = FUSED_THREADS / SW;
+    if constexpr (NV == 1) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
+        for (int o = SW >> 1; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
+        if ((threadIdx.x & (SW - 1)) == 0 && (int)threadIdx.x < RPS * TPR) slots[(threadIdx.x / SW) * 8] = v[0];
+    } else {
+        // reduce-scatter of up to 8 values over the SW-lane part: three halving
+        // exchanges leave value q in the lanes whose bits SW/2, SW/4, SW/8 spell q,
+        // the remaining butterflies sum it over those lanes (10 shuffles, not 6 NV)
+        static_assert(NV <= 8, "at most 8 values");
+        double w[8];
 #pragma unroll
-        for (int o = SW >> 1; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
-    if ((threadIdx.x & (SW - 1)) == 0 && (int)threadIdx.x < RPS * TPR)
-        for (int q = 0; q < NV; ++q) slots[(threadIdx.x / SW) * 8 + q] = v[q];
+        for (int q = 0; q < 8; ++q) w[q] = q < NV ? v[q] : 0.0;
+        const int lane = threadIdx.x & (SW - 1);
+        int q = 0;
+#pragma unroll
+        for (int half = 4, o = SW >> 1; half >= 1; half >>= 1, o >>= 1) {
+            const bool hi = (lane & o) != 0;
+#pragma unroll
+            for (int k = 0; k < half; ++k) {
+                const double mine = hi ? w[half + k] : w[k];
+                const double give = hi ? w[k] : w[half + k];
+                w[k] = mine + __shfl_xor(give, o);
+            }
+            q += hi ? half : 0;
+        }
+#pragma unroll
+        for (int o = SW >> 4; o > 0; o >>= 1) w[0] += __shfl_xor(w[0], o);
+        if ((lane & (SW / 8 - 1)) == 0 && q < NV && (int)threadIdx.x < RPS * TPR)
+            slots[(threadIdx.x / SW) * 8 + q] = w[0];
+    }
     __syncthreads();
     // one thread per (filter, value) sums that filter's slots in a fixed order
     double* res = slots + NSLOT * 8;
