@@ -25,9 +25,17 @@ constexpr int FUSED_LMAX = 64;
 constexpr int GMAX = 16;            // filters of one size packed into a workgroup
 constexpr int CPLX_BUDGET = 9400;   // complex LDS entries per buffer (2 buffers)
 
-// zero rows around a 2-D posterior in LDS (one above, one below): with the row
-// pads they let every cubic stencil read its 4 x 4 taps without bounds checks
+// zero rows around a 2-D posterior in LDS (one above, one below, and the two
+// floats before the upper one, where the stencil of node (0, 0) reads its corner
+// tap): with the row pads they let every cubic stencil read its 4 x 4 taps
+// without bounds checks
 constexpr int guard_rows(int n0) { return n0 > 1 ? 2 : 0; }
+
+// complex LDS entries of one buffer for a group of G filters of n0 rows of
+// `pitch` entries (the posterior's guard included)
+constexpr int group_cplx(int n0, int G, int pitch) {
+    return (n0 + guard_rows(n0)) * G * pitch + (n0 > 1 ? 1 : 0);
+}
 
 struct FConst {
     KModel m;
@@ -810,6 +818,7 @@ __shared__ int pmf_item;
 
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) const float cgfloat;
+typedef __attribute__((address_space(1))) const unsigned long long cgu64;   // a complex pair
 
 template <int N0, int N1, int NX, int G>
 __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restrict__ items, const FPlan* __restrict__ plans,
@@ -839,9 +848,12 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     if (tid < G) {
         const int gg = tid < Gact ? tid : 0;
         const BItem& I = items[GI.first + gg];
+        // both buffers and the parity loaded independently (one round trip)
+        float* const p0 = I.P[0];
+        float* const p1 = I.P[1];
         const int par = plans[GI.first + gg].par;
-        FS[tid].pin = I.P[par];
-        FS[tid].pout = I.P[1 - par];
+        FS[tid].pin = par ? p1 : p0;
+        FS[tid].pout = par ? p0 : p1;
     }
     for (int i = tid; i < H1; i += NT) {
         float sn, cs;
@@ -861,19 +873,32 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     }
     __syncthreads();
 
-    // ---- load: super-row L = r*G + g holds row r of filter g as complex pairs
-    // (unrolled: every load of the thread is in flight before the first wait)
+    // ---- load: super-row L = r*G + g holds row r of filter g as complex pairs.
+    // Every load of the thread is issued before the first wait: the addresses are
+    // clamped to valid ones (an absent filter reads filter 0, a surplus element the
+    // last one) and the values discarded afterwards.
+    {
+        constexpr int TOT = G * N0 * H1, NE = (TOT + NT - 1) / NT;
+        unsigned long long ld[NE];
 #pragma unroll
-    for (int e = tid; e < G * N0 * H1; e += NT) {
-        const int L = e / H1, k = e - L * H1;
-        const int r = L / G, g = L - r * G;
-        float2 v = make_float2(0.f, 0.f);
-        if (g < Gact) {
-            cgfloat* src = (cgfloat*)FS[g].pin + 2 * (r * H1 + k);
-            const float sc = (float)FS[g].p.pscale;
-            v = make_float2(src[0] * sc, src[1] * sc);
+        for (int i = 0; i < NE; ++i) {
+            const int e = min(tid + i * NT, TOT - 1);
+            const int L = e / H1, k = e - L * H1;
+            const int r = L / G, g = L - r * G;
+            ld[i] = ((cgu64*)FS[g < Gact ? g : 0].pin)[r * H1 + k];
         }
-        bufA[L * PITCH + k] = v;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+            const int e = tid + i * NT;
+            if (TOT % NT == 0 || e < TOT) {
+                const int L = e / H1, k = e - L * H1;
+                const int r = L / G, g = L - r * G;
+                // absent filters read filter 0's (finite) values: scaled to zero
+                const float sc = g < Gact ? (float)FS[g].p.pscale : 0.f;
+                bufA[L * PITCH + k] = make_float2(__uint_as_float((unsigned int)ld[i]) * sc,
+                                                  __uint_as_float((unsigned int)(ld[i] >> 32)) * sc);
+            }
+        }
     }
     __syncthreads();
     // ---- forward: rows (r2c), columns
@@ -973,15 +998,15 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     cur = cfft<H1, N0 * G, PITCH, 1, +1, true>(oth, cur, twr);
     oth = (cur == bufA) ? bufB : bufA;
     const float* Pr = reinterpret_cast<const float*>(cur);   // predicted: (r, g, j) at r*RS + g*RP + j
-    // posterior, same layout, starting one row into the buffer (2-D): rows -1 and
-    // N0 and the two pad floats of every row are zeroed here (positions the
-    // likelihood pass does not write, so no barrier is needed)
-    float* Po = reinterpret_cast<float*>(oth) + guard_rows(N0) / 2 * RS;
+    // posterior, same layout, starting one row and two floats into the buffer
+    // (2-D): row -1 with the two floats before it, row N0 and the two pad floats
+    // of every row are zeroed here (positions the likelihood pass does not write,
+    // so no barrier is needed)
+    constexpr int PO_OFF = NX == 2 ? RS + 2 : 0;
+    float* Po = reinterpret_cast<float*>(oth) + PO_OFF;
     if constexpr (NX == 2) {
-        for (int e = tid; e < RS; e += NT) {
-            Po[e - RS] = 0.f;
-            Po[N0 * RS + e] = 0.f;
-        }
+        for (int e = tid; e < RS + 2; e += NT) Po[e - PO_OFF] = 0.f;
+        for (int e = tid; e < RS; e += NT) Po[N0 * RS + e] = 0.f;
         for (int e = tid; e < N0 * G * 2; e += NT) {
             const int rg = e >> 1;
             Po[rg * RP + N1 + (e & 1)] = 0.f;
@@ -1161,8 +1186,7 @@ constexpr int group_g() {
     constexpr int pitch = N1 / 2 + 1;
     constexpr int seg = pow2_ceil(N1) < 32 ? 32 : pow2_ceil(N1);
     int G = 1;
-    while (G < GMAX && (N0 + guard_rows(N0)) * (2 * G) * pitch <= CPLX_BUDGET && (2 * G) * seg <= FUSED_THREADS)
-        G *= 2;
+    while (G < GMAX && group_cplx(N0, 2 * G, pitch) <= CPLX_BUDGET && (2 * G) * seg <= FUSED_THREADS) G *= 2;
     return G;
 }
 
@@ -1405,7 +1429,7 @@ static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sort
         }
         gi.G = cnt;
         groups.push_back(gi);
-        maxcplx = std::max(maxcplx, (gi.n0 + guard_rows(gi.n0)) * G * pitch);
+        maxcplx = std::max(maxcplx, group_cplx(gi.n0, G, pitch));
     }
     return maxcplx;
 }

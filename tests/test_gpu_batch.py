@@ -151,6 +151,57 @@ def test_batch_full_size_sampled(B, ctx):
             B.pmf_destroy(f)
 
 
+def _corner_state(sc, k):
+    """A state whose next regrid reads the old grid's corner: the old grid is the
+    new one (as the oracle designs it) moved back by e^{-AT} and shifted by half a
+    cell along both index axes, so new node (0, 0) sits at old index (1/2, 1/2)
+    and its cubic stencil takes taps from row -1 and column -1."""
+    import scipy.linalg
+    import scipy.stats
+    m = sc.model
+    st = oracle.create(m, sc.prior)
+    Phi_inv = scipy.linalg.expm(-np.asarray(m.A, float) * sc.T)
+    for _ in range(2):
+        s1, _ = oracle.predict(m, st, sc.T)
+        s2, *_ = oracle.update(m, s1, sc.z[k])
+        M0 = Phi_inv @ s2.M
+        c0 = Phi_inv @ (s2.c - 0.5 * s2.M @ np.ones(2))
+        X = oracle.nodes(m, c0, M0)
+        P = sum(w * scipy.stats.multivariate_normal(mu, C).pdf(X)
+                for w, mu, C in zip(sc.prior.w, sc.prior.mean, sc.prior.cov))
+        st = oracle.State(c0, M0, 0.0, P / (oracle.quadrature_weights(m, M0) * P).sum())
+    # where new node (0, 0) falls on the moved old grid
+    s1, _ = oracle.predict(m, st, sc.T)
+    s2, *_ = oracle.update(m, s1, sc.z[k])
+    N = np.asarray(m.N)
+    x00 = s2.c + s2.M @ (-(N // 2)).astype(float)
+    nu = np.linalg.solve(s1.M, x00 - s1.c) + N // 2
+    assert np.all(nu > 0.05) and np.all(nu < 0.95), nu
+    return st
+
+
+def test_batch_regrid_reads_corner_taps(B, ctx):
+    """Regression: the stencil of new node (0, 0) reads old row -1 and column -1,
+    which must be zero guard positions in LDS (not whatever the memory held)."""
+    scs = W.batched_workload(20, K=1)
+    note(f"case: 20 filters set up so that node (0, 0) regrids from the old grid's corner cell, "
+         f"sizes {sorted(set(sc.model.N[0] for sc in scs))}")
+    fs = make(B, ctx, scs)
+    try:
+        before = []
+        for f, sc in zip(fs, scs):
+            st = _corner_state(sc, 0)
+            B.pmf_set_state(f, st.c, st.M, st.t, st.P, sc.model.grid, sc.model.precision)
+            before.append(B.pmf_get_state(f)[1:])
+        lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, 0), want_loglik=True)
+        what = "corner regrid"
+        _K[what] = 0
+        check_against_oracle(B, fs, scs, before, lls, what)
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
 def test_batch_replays_are_deterministic(B, ctx):
     note("case: two identical batches give bitwise equal densities")
     scs = W.batched_workload(24, K=3)
