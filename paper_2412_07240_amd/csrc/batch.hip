@@ -74,6 +74,10 @@ struct FState {
     FPlan p;
     const float* pin;
     float* pout;
+    DevDesc* d;             // the filter's descriptor, model and row of z, fetched
+    const KModel* km;       // once per group (no pointer chase later)
+    const double* zrow;
+    int idx;
     double s, inv_mass, loglik;
     double amap[4], bmap[2];
     double gnc[2], gnM[4], gnvol;
@@ -756,9 +760,9 @@ __device__ void filter_design(FState& F, const double* acc, int NX, int n0, int 
 }
 
 // thread 0..G-1: write back descriptor and log-likelihood of filter tid
-__device__ void filter_commit(const FState& F, const BItem& I, double* ll_out) {
+__device__ void filter_commit(const FState& F, double* ll_out) {
     const FPlan& P = F.p;
-    DevDesc* d = I.d;
+    DevDesc* d = F.d;
     Grid gg;
     mat_zero(gg.M);
     for (int q = 0; q < MS; ++q) gg.c[q] = 0.0;
@@ -800,12 +804,12 @@ __device__ void filter_commit(const FState& F, const BItem& I, double* ll_out) {
         d->loglik = F.loglik;
         d->status |= F.bits;
         d->pscale = F.pscale2;
-        ll_out[I.idx] = F.loglik;
+        ll_out[F.idx] = F.loglik;
     } else {
         d->loglik = NAN;
         d->status |= PMF_E_DEGENERATE | F.bits | (P.bad ? PMF_E_INVALID : 0);
         d->pscale = 1.0;
-        ll_out[I.idx] = NAN;
+        ll_out[F.idx] = NAN;
     }
 }
 
@@ -848,12 +852,19 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     if (tid < G) {
         const int gg = tid < Gact ? tid : 0;
         const BItem& I = items[GI.first + gg];
-        // both buffers and the parity loaded independently (one round trip)
+        // the item's fields and the parity loaded independently (one round trip)
         float* const p0 = I.P[0];
         float* const p1 = I.P[1];
+        DevDesc* const d = I.d;
+        const FConst* const k = I.k;
+        const int idx = I.idx;
         const int par = plans[GI.first + gg].par;
         FS[tid].pin = par ? p1 : p0;
         FS[tid].pout = par ? p0 : p1;
+        FS[tid].d = d;
+        FS[tid].km = &k->m;
+        FS[tid].zrow = zall + (size_t)idx * nzmax;
+        FS[tid].idx = idx;
     }
     for (int i = tid; i < H1; i += NT) {
         float sn, cs;
@@ -1021,8 +1032,8 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     const bool act = tr < RPS && j < N1 && g < Gact;
     constexpr double half0 = (double)(N0 / 2), half1 = (double)(N1 / 2);
     const int gi = act ? g : 0;
-    const double* zg = zall + (size_t)items[GI.first + gi].idx * nzmax;
-    const KModel& mg = items[GI.first + gi].k->m;
+    const double* zg = FS[gi].zrow;
+    const KModel& mg = *FS[gi].km;
     const FPlan& Pg = FS[gi].p;
     // log l = alpha + beta u0 + gamma u0^2 along this thread's rows (fast path)
     const double uj = (double)j - half1;
@@ -1171,7 +1182,7 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
         gfloat* Pout = (gfloat*)FS[g].pout;
         for (int r = tr; r < N0; r += RPS) Pout[r * N1 + j] = Pr[r * RS + g * RP + j];
     }
-    if (tid < Gact) filter_commit(FS[tid], items[GI.first + tid], ll_out);
+    if (tid < Gact) filter_commit(FS[tid], ll_out);
     __syncthreads();
 }
 
