@@ -135,90 +135,36 @@ __device__ inline void fdft8(float2* a, int s) {
     a[3] = f2add(e[3], o3);
     a[7] = f2sub(e[3], o3);
 }
-
-
-// x / d for 0 <= x < 2^31 by multiply and shift (d fixed for a loop)
-struct FDiv {
-    uint32_t m, s;
-};
-__device__ inline FDiv fdiv_make(uint32_t d) {
-    uint32_t s = 0;
-    while ((1u << s) < d) ++s;
-    // m = floor(2^32 (2^s - d) / d) + 1; the quotient is never within 2^-20 of an
-    // integer for the divisors used here (d <= 2^16), so FP64 division is exact enough
-    const double q = 4294967296.0 * (double)((1u << s) - d) / (double)d;
-    FDiv f;
-    f.m = (uint32_t)floor(q) + 1u;
-    f.s = s;
-    return f;
-}
-__device__ inline int fdiv(int x, FDiv f) { return (int)((__umulhi((uint32_t)x, f.m) + (uint32_t)x) >> f.s); }
-
-// One Stockham pass over nlines lines; element i of line L at L*ls + i*es.
-// tw[m] = e^{-2 pi i m / n}.
-template <int R>
-__device__ void fpass(const float2* __restrict__ in, float2* __restrict__ out, int n, int Ns, int nlines, int ls,
-                      int es, int sign, const float2* __restrict__ tw, bool line_fast) {
-    const int nb = n / R;
-    const int tot = nlines * nb;
-    const int tws = n / (Ns * R);
-    const FDiv dnb = fdiv_make(nb), dnl = fdiv_make(nlines), dns = fdiv_make(Ns);
-    for (int w = threadIdx.x; w < tot; w += blockDim.x) {
-        int line, j;
-        if (line_fast) {
-            j = fdiv(w, dnl);
-            line = w - j * nlines;
-        } else {
-            line = fdiv(w, dnb);
-            j = w - line * nb;
-        }
-        const float2* src = in + line * ls;
-        float2* dst = out + line * ls;
-        float2 v[R];
+// 16 points as 4 x 4: four 4-point DFTs over n1 (x[4 n1 + n2]), twiddles
+// W16^(n2 k1), four 4-point DFTs over n2; output k1 + 4 k2
+__device__ inline void fdft16(float2* a, int s) {
+    float2 y[4][4];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * es];
-        const int q = fdiv(j, dns);
-        const int k = j - q * Ns;
-        if (k) {
+    for (int n2 = 0; n2 < 4; ++n2) {
+        float2 t[4] = {a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]};
+        fdft4(t, s);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 t = tw[k * r * tws];
-                if (sign > 0) t.y = -t.y;
-                v[r] = f2mul(v[r], t);
-            }
-        }
-        if (R == 2) fdft2(v);
-        if (R == 3) fdft3(v, sign);
-        if (R == 4) fdft4(v, sign);
-        if (R == 8) fdft8(v, sign);
-        const int base = q * Ns * R + k;
+        for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+    }
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, r = 0.70710678118654752440f;
+    y[1][1] = f2mul(y[1][1], make_float2(c1, s * s1));
+    y[1][2] = f2mul(y[1][2], make_float2(r, s * r));
+    y[1][3] = f2mul(y[1][3], make_float2(s1, s * c1));
+    y[2][1] = f2mul(y[2][1], make_float2(r, s * r));
+    y[2][2] = f2si(y[2][2], s);
+    y[2][3] = f2mul(y[2][3], make_float2(-r, s * r));
+    y[3][1] = f2mul(y[3][1], make_float2(s1, s * c1));
+    y[3][2] = f2mul(y[3][2], make_float2(-r, s * r));
+    y[3][3] = f2mul(y[3][3], make_float2(-c1, -s * s1));
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[(base + r * Ns) * es] = v[r];
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        fdft4(t, s);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
     }
 }
 
-// FFT of length n on nlines lines, ping-ponging between a and b; returns the
-// buffer holding the result (natural order).
-__device__ float2* ffft(float2* a, float2* b, int n, int nlines, int ls, int es, int sign, const float2* tw,
-                        bool line_fast) {
-    const FftPlan p = make_plan(n);
-    int Ns = 1;
-    float2* in = a;
-    float2* out = b;
-    for (int q = 0; q < p.np; ++q) {
-        const int R = p.r[q];
-        if (R == 8) fpass<8>(in, out, n, Ns, nlines, ls, es, sign, tw, line_fast);
-        else if (R == 4) fpass<4>(in, out, n, Ns, nlines, ls, es, sign, tw, line_fast);
-        else if (R == 3) fpass<3>(in, out, n, Ns, nlines, ls, es, sign, tw, line_fast);
-        else fpass<2>(in, out, n, Ns, nlines, ls, es, sign, tw, line_fast);
-        __syncthreads();
-        float2* t = in;
-        in = out;
-        out = t;
-        Ns *= R;
-    }
-    return in;
-}
 
 // ---------------------------------------------------------------- segmented reductions
 // Threads map onto points as (tr, g, j): TPR = G * seg threads per "super-row",
@@ -522,29 +468,37 @@ __device__ inline void cubic_weights(float t, float* w) {
 // Specialised at compile time per group type (N0 x N1 grid, G filters side by
 // side): every loop bound, divisor and radix plan is a constant.
 
+// Radices of an n-point FFT, first pass first: the power-of-two part 2^e in as
+// few passes as possible (8s, with one 16 when e = 1 mod 3 and e >= 4, two 16s
+// when e = 2 mod 3 and e >= 8), the first pass (no twiddles) taking the largest
+// radix, then 3s.
 constexpr int radix_at(int n, int i) {
-    int k = 0;
-    while (n % 8 == 0 && n > 1) {
-        if (k == i) return 8;
-        n /= 8;
-        ++k;
-    }
-    while (n % 4 == 0) {
-        if (k == i) return 4;
-        n /= 4;
-        ++k;
-    }
+    int e = 0;
     while (n % 2 == 0) {
-        if (k == i) return 2;
         n /= 2;
-        ++k;
+        ++e;
     }
+    int r[16] = {};
+    int k = 0;
+    if (e % 3 == 1 && e >= 4) {
+        r[k++] = 16;
+        e -= 4;
+    } else if (e % 3 == 2 && e >= 8) {
+        r[k++] = 16;
+        r[k++] = 16;
+        e -= 8;
+    }
+    while (e >= 3) {
+        r[k++] = 8;
+        e -= 3;
+    }
+    if (e == 2) r[k++] = 4;
+    if (e == 1) r[k++] = 2;
     while (n % 3 == 0) {
-        if (k == i) return 3;
+        r[k++] = 3;
         n /= 3;
-        ++k;
     }
-    return 0;
+    return i < k ? r[i] : 0;
 }
 constexpr int num_passes(int n) {
     int k = 0;
@@ -558,6 +512,7 @@ constexpr int pow2_ceil(int v) {
 }
 
 template <int R> __device__ inline void fdft(float2* v, int sign) {
+    if constexpr (R == 16) fdft16(v, sign);
     if constexpr (R == 2) fdft2(v);
     if constexpr (R == 3) fdft3(v, sign);
     if constexpr (R == 4) fdft4(v, sign);
