@@ -285,25 +285,35 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     const DevDesc* d = I.d;
     constexpr int n = NX;   // compile-time: the small matrix loops unroll into registers
     Grid g = d->g;
-    double Mi[MSQ];
-    mat_copy(Mi, g.Mi);
     int l = a.lmin;
     P.bad = 0;
-    if (a.integ == PMF_INT_RK4 && a.T > 0.0) l = plan_substeps(a, Mi, n, l);
-    if (l > FUSED_LMAX) {
-        l = FUSED_LMAX;
-        P.bad = 1;
+    if (a.integ == PMF_INT_EXACT) {
+        // W_y = M^-1 W M^-T on the 2 x 2 (or 1 x 1) block, in registers
+        const double m00 = g.Mi[0], m01 = g.Mi[1], m10 = g.Mi[MS], m11 = g.Mi[MS + 1];
+        const double w00 = a.W[0], w01 = a.W[1], w10 = a.W[MS], w11 = a.W[MS + 1];
+        if (n == 2) {
+            const double t00 = m00 * w00 + m01 * w10, t01 = m00 * w01 + m01 * w11;
+            const double t10 = m10 * w00 + m11 * w10, t11 = m10 * w01 + m11 * w11;
+            P.gc[0] = t00 * m00 + t01 * m01;
+            P.gc[1] = t10 * m10 + t11 * m11;
+            P.gc[2] = t00 * m10 + t01 * m11;
+        } else {
+            P.gc[0] = m00 * w00 * m00;
+            P.gc[1] = 0.0;
+            P.gc[2] = 0.0;
+        }
+    } else {
+        // the stage planners take M^-1 through memory: a copy of their own
+        double Mi[MSQ];
+        mat_copy(Mi, g.Mi);
+        if (a.integ == PMF_INT_RK4 && a.T > 0.0) l = plan_substeps(a, Mi, n, l);
+        if (l > FUSED_LMAX) {
+            l = FUSED_LMAX;
+            P.bad = 1;
+        }
+        plan_stage_coefs(a, Mi, n, l, a.T / l, I.coef);
     }
     const double h = a.T / l;
-    if (a.integ == PMF_INT_EXACT) {
-        double Wy[MSQ];
-        sandwich_inv(Wy, Mi, a.W, n);
-        P.gc[0] = Wy[0];
-        P.gc[1] = Wy[MS + 1];
-        P.gc[2] = Wy[1];
-    } else {
-        plan_stage_coefs(a, Mi, n, l, h, I.coef);
-    }
     P.l = l;
     P.h = h;
     P.etr = a.etr;
@@ -380,14 +390,21 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     Pout = P;
 }
 
-// one thread per filter; thread 0 also clears the work counter of the fused launch
+// One thread per filter; thread 0 also clears the work counter of the fused
+// launch.  zsrc: the step's measurements (rows of nzmax, possibly in mapped host
+// memory); zdst (optional): device copy of them for the fused kernel.
 __global__ void k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
-                             const double* __restrict__ zall, int nzmax, int* __restrict__ ctr) {
+                             const double* __restrict__ zsrc, double* __restrict__ zdst, int nzmax,
+                             int* __restrict__ ctr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *ctr = 0;
     if (i >= n) return;
     const BItem& I = items[i];
-    const double* z = zall + (size_t)I.idx * nzmax;
+    const double* zs = zsrc + (size_t)I.idx * nzmax;
+    double z[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < nzmax && q < 3; ++q) z[q] = zs[q];
+    if (zdst)
+        for (int q = 0; q < nzmax && q < 3; ++q) zdst[(size_t)I.idx * nzmax + q] = z[q];
     if (I.nx == 2)
         plan_one<2>(I, z, plans[i]);
     else
@@ -1255,13 +1272,14 @@ struct BatchCache {
     double* d_z = nullptr;
     double* d_ll = nullptr;
     int* d_ctr = nullptr;
-    double* h_z[2] = {nullptr, nullptr};
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    double* h_z[2] = {nullptr, nullptr};      // pinned staging of z, one per slot
+    double* hz_dev[2] = {nullptr, nullptr};   // the same memory as the device reads it
+    hipEvent_t ev[2] = {nullptr, nullptr};    // the step that read slot i has finished
     int slot = 0;
     size_t lds = 0;
     int grid = 0, bufcplx = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};          // one step per staging slot
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 namespace pmf {
@@ -1269,8 +1287,10 @@ namespace pmf {
 static void cache_free(pmf_ctx* ctx, BatchCache* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    if (c->exec) (void)hipGraphExecDestroy(c->exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (int i = 0; i < 2; ++i) {
+        if (c->exec[i]) (void)hipGraphExecDestroy(c->exec[i]);
+        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+    }
     ctx_free(ctx, c->d_items, nullptr);
     ctx_free(ctx, c->d_groups, nullptr);
     ctx_free(ctx, c->d_plans, nullptr);
@@ -1462,7 +1482,8 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     if (e == hipSuccess)
         e = hipMemcpy(c->d_groups, groups.data(), sizeof(GItem) * groups.size(), hipMemcpyHostToDevice);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-        e = hipHostMalloc(reinterpret_cast<void**>(&c->h_z[i]), sizeof(double) * n * nzmax, hipHostMallocDefault);
+        e = hipHostMalloc(reinterpret_cast<void**>(&c->h_z[i]), sizeof(double) * n * nzmax, hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hz_dev[i]), c->h_z[i], 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
     }
     if (e != hipSuccess) return hip_fail(e, "batch setup");
@@ -1478,18 +1499,21 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     e = hipGetDeviceProperties(&prop, ctx->device);
     if (e != hipSuccess) return hip_fail(e, "device properties");
     c->grid = std::min(c->ngroups, per_cu * prop.multiProcessorCount);
-    // the step as a graph: plan every filter (and clear the work counter), fused kernel
+    // the step as a graph, one per staging slot: plan every filter (reading its z
+    // from the slot's mapped host memory, clearing the work counter), fused kernel
     hipStream_t cap;
     e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, cap, c->d_items, c->d_plans, n, c->d_z,
-                           nzmax, c->d_ctr);
-        hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, cap, c->d_groups, c->ngroups,
-                           c->d_items, c->d_plans, c->d_ctr, c->d_z, nzmax, c->d_ll, c->bufcplx);
-        e = hipStreamEndCapture(cap, &c->graph);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, cap, c->d_items, c->d_plans, n,
+                               c->hz_dev[i], c->d_z, nzmax, c->d_ctr);
+            hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, cap, c->d_groups, c->ngroups,
+                               c->d_items, c->d_plans, c->d_ctr, c->d_z, nzmax, c->d_ll, c->bufcplx);
+            e = hipStreamEndCapture(cap, &c->graph[i]);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->exec[i], c->graph[i], nullptr, nullptr, 0);
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return hip_fail(e, "graph capture");
     return PMF_OK;
@@ -1654,8 +1678,8 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
         e = hipMemcpyAsync(db->d_groups, db->h_groups, sizeof(GItem) * ng, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(db->d_z, db->h_z, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "served batch upload");
-    hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, db->d_items, db->d_plans, n, db->d_z, 3,
-                       db->d_ctr);
+    hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, db->d_items, db->d_plans, n, db->d_z,
+                       nullptr, 3, db->d_ctr);
     hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, db->d_groups, ng, db->d_items,
                        db->d_plans, db->d_ctr, db->d_z, 3, db->d_ll, maxcplx);
     e = hipGetLastError();
@@ -1705,15 +1729,14 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
         }
         c = ctx->batch;
     }
-    // stage z in pinned memory (two slots, each reused only after its copy finished)
+    // stage z in mapped pinned memory (two slots, each reused only after the step
+    // that read it finished); the planning kernel reads it there, no separate copy
     const int slot = c->slot;
     c->slot ^= 1;
     e = hipEventSynchronize(c->ev[slot]);
     if (e != hipSuccess) return hip_fail(e, "staging wait");
     std::memcpy(c->h_z[slot], z, sizeof(double) * n * nzmax);
-    e = hipMemcpyAsync(c->d_z, c->h_z[slot], sizeof(double) * n * nzmax, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipEventRecord(c->ev[slot], st);
-    if (e == hipSuccess && ctx->profile) {
+    if (ctx->profile) {
         // same kernels as the graph, launched directly with events around the fused one
         if ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {
             for (int q = 0; q < 2 && e == hipSuccess; ++q) {
@@ -1728,7 +1751,7 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             ctx->ev_used++;
             ctx->ev_stream = st;
             hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, c->d_items, c->d_plans, n,
-                               c->d_z, c->nzmax, c->d_ctr);
+                               c->hz_dev[slot], c->d_z, c->nzmax, c->d_ctr);
             e = hipEventRecord(t0, st);
             if (e == hipSuccess) {
                 hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups,
@@ -1738,9 +1761,10 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             }
             if (e == hipSuccess) e = hipEventRecord(t1, st);
         }
-    } else if (e == hipSuccess) {
-        e = hipGraphLaunch(c->exec, st);
+    } else {
+        e = hipGraphLaunch(c->exec[slot], st);
     }
+    if (e == hipSuccess) e = hipEventRecord(c->ev[slot], st);
     if (e == hipSuccess && loglik) e = hipMemcpyAsync(loglik, c->d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return PMF_OK;
