@@ -351,35 +351,55 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     P.qb[0] = P.qb[1] = 0.0;
     P.qQ[0] = P.qQ[1] = P.qQ[2] = 0.0;
     if (P.fast) {
+        // fixed trip counts (nz <= 3; rows past nz weighted zero): every load of the
+        // model is independent of nz and issued up front, and the arrays stay in
+        // registers
         const int nz = m.nz;
-        double r0[3], G[9], Rir0[3];
-        for (int i = 0; i < nz; ++i) {
+        double r0[3], G[6], Rir0[3], Ri[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Ri[i * 3 + k] = (i < nz && k < nz) ? m.nRi[0][i * MS + k] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const bool on = i < nz;
             double hc = 0.0;
+#pragma unroll
             for (int k = 0; k < n; ++k) hc += m.H[i * MS + k] * g.c[k];
-            r0[i] = z[i] - m.nmean[0][i] - hc;
+            r0[i] = on ? z[i] - m.nmean[0][i] - hc : 0.0;
+#pragma unroll
             for (int b = 0; b < n; ++b) {
                 double s = 0.0;
+#pragma unroll
                 for (int k = 0; k < n; ++k) s += m.H[i * MS + k] * g.M[k * MS + b];
-                G[i * 3 + b] = s;
+                G[i * 2 + b] = on ? s : 0.0;
             }
         }
-        for (int i = 0; i < nz; ++i) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
             double s = 0.0;
-            for (int k = 0; k < nz; ++k) s += m.nRi[0][i * MS + k] * r0[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s += Ri[i * 3 + k] * r0[k];
             Rir0[i] = s;
         }
         double rr = 0.0;
-        for (int i = 0; i < nz; ++i) rr += r0[i] * Rir0[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) rr += r0[i] * Rir0[i];
         P.q0 = m.lw[0] - 0.5 * rr;
         double Qf[4] = {0, 0, 0, 0};
+#pragma unroll
         for (int a2 = 0; a2 < n; ++a2) {
             double s = 0.0;
-            for (int i = 0; i < nz; ++i) s += G[i * 3 + a2] * Rir0[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) s += G[i * 2 + a2] * Rir0[i];
             P.qb[a2] = s;
+#pragma unroll
             for (int b = 0; b < n; ++b) {
                 double t = 0.0;
-                for (int i = 0; i < nz; ++i)
-                    for (int k = 0; k < nz; ++k) t += G[i * 3 + a2] * m.nRi[0][i * MS + k] * G[k * 3 + b];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) t += G[i * 2 + a2] * Ri[i * 3 + k] * G[k * 2 + b];
                 Qf[a2 * 2 + b] = t;
             }
         }
@@ -393,7 +413,7 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
 // One thread per filter; thread 0 also clears the work counter of the fused
 // launch.  zsrc: the step's measurements (rows of nzmax, possibly in mapped host
 // memory); zdst (optional): device copy of them for the fused kernel.
-__global__ void k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
+__global__ void __launch_bounds__(64) k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
                              const double* __restrict__ zsrc, double* __restrict__ zdst, int nzmax,
                              int* __restrict__ ctr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
