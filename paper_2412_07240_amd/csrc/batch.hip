@@ -170,65 +170,8 @@ __device__ inline void fdft16(float2* a, int s) {
 // Threads map onto points as (tr, g, j): TPR = G * seg threads per "super-row",
 // seg = next power of two >= n1.  Every filter's threads form aligned segments of
 // sw = min(seg, 64) lanes, so a filter's partials are reduced in a fixed order:
-// xor-shuffles inside the segment, then slots in LDS summed by thread g.
-
-struct Seg {
-    int seg, sw, tpr, rps, tr, g, j;
-    bool active;
-};
-
-__device__ inline Seg seg_map(int G, int seg, int n1) {
-    Seg s;
-    s.seg = seg;
-    s.sw = seg < 64 ? seg : 64;
-    s.tpr = G * seg;
-    s.rps = blockDim.x / s.tpr;
-    s.tr = threadIdx.x / s.tpr;
-    const int tt = threadIdx.x - s.tr * s.tpr;
-    s.g = tt / seg;
-    s.j = tt - s.g * seg;
-    s.active = s.tr < s.rps && s.j < n1;
-    return s;
-}
-
-template <int NV>
-__device__ void seg_sum(double* v, const Seg& s, double* slots, int G) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q)
-        for (int o = s.sw >> 1; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
-    if ((threadIdx.x & (s.sw - 1)) == 0 && s.tr < s.rps)
-        for (int q = 0; q < NV; ++q) slots[(threadIdx.x / s.sw) * 8 + q] = v[q];
-    __syncthreads();
-    if ((int)threadIdx.x < G) {
-        const int g = threadIdx.x;
-        const int per_row = s.tpr / s.sw, per_seg = s.seg / s.sw;
-        double acc[NV];
-        for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-        for (int tr = 0; tr < s.rps; ++tr)
-            for (int h = 0; h < per_seg; ++h) {
-                const int slot = tr * per_row + g * per_seg + h;
-                for (int q = 0; q < NV; ++q) acc[q] += slots[slot * 8 + q];
-            }
-        for (int q = 0; q < NV; ++q) v[q] = acc[q];
-    }
-    __syncthreads();
-}
-
-__device__ double seg_max(double v, const Seg& s, double* slots, int G) {
-    for (int o = s.sw >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    if ((threadIdx.x & (s.sw - 1)) == 0 && s.tr < s.rps) slots[(threadIdx.x / s.sw) * 8] = v;
-    __syncthreads();
-    if ((int)threadIdx.x < G) {
-        const int g = threadIdx.x;
-        const int per_row = s.tpr / s.sw, per_seg = s.seg / s.sw;
-        double r = -INFINITY;
-        for (int tr = 0; tr < s.rps; ++tr)
-            for (int h = 0; h < per_seg; ++h) r = fmax(r, slots[(tr * per_row + g * per_seg + h) * 8]);
-        v = r;
-    }
-    __syncthreads();
-    return v;
-}
+// shuffles inside the segment part (cseg_sum / cseg_max below), then slots in LDS
+// summed by one thread per value.
 
 // ---------------------------------------------------------------- planning (one thread per filter)
 
@@ -609,7 +552,7 @@ __device__ inline float2* cfft(float2* in, float2* out, const float2* tw) {
     }
 }
 
-// segmented reductions with compile-time mapping (see Seg above)
+// segmented reductions with compile-time mapping (the mapping is described above)
 template <int G, int SEGW, int NV>
 __device__ inline void cseg_sum(double* v, double* slots) {
     constexpr int SW = SEGW < 64 ? SEGW : 64;
