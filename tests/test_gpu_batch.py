@@ -202,6 +202,53 @@ def test_batch_regrid_reads_corner_taps(B, ctx):
             B.pmf_destroy(f)
 
 
+def _slow_path_scenarios():
+    """2-D FP32 filters that take the fused kernel's general branches: RK4 and
+    implicit-Euler gains from per-stage coefficient tables, a cubic and a range
+    measurement and a two-component mixture noise (log-likelihood per node
+    instead of the linear-Gaussian quadratic)."""
+    out = []
+    for i, N in enumerate((32, 48, 64, 96, 32, 48)):
+        rng = W.rng_for(9, i)
+        A = W.random_stable_A(rng, 2, -1.0, -0.1)
+        Q = np.diag(rng.uniform(0.2, 0.6, size=2))
+        kind = i % 3
+        if kind == 0:      # RK4 gain, cubic measurement of x1
+            meas = dict(meas_kind=W.H_CUBIC1, nz=1, hparam=np.array([1.0, 0.05, 0.0, 0.0]),
+                        **W.gaussian_noise([[0.3 ** 2]]))
+            integ = W.INT_RK4
+        elif kind == 1:    # Euler gain, linear measurement with mixture noise
+            meas = dict(meas_kind=W.H_LINEAR, nz=1, H=np.array([[1.0, 0.5]]),
+                        noise_w=np.array([0.6, 0.4]), noise_mean=np.array([[0.0], [0.8]]),
+                        noise_cov=np.array([[[0.3 ** 2]], [[0.4 ** 2]]]))
+            integ = W.INT_EULER
+        else:              # exact gain, range measurement
+            meas = dict(meas_kind=W.H_NORM, nz=1, **W.gaussian_noise([[0.3 ** 2]]))
+            integ = W.INT_EXACT
+        m = W.ModelSpec(nx=2, A=A, Q=Q, N=(N, N), t_nominal=0.05, integrator=integ, substeps=1,
+                        precision=W.FP32, **meas)
+        prior = W.gaussian_prior(np.array([1.5, -1.0]), np.diag([0.4, 0.3]))
+        out.append(W.simulate(m, prior, 0.05, 2, rng))
+    return out
+
+
+def test_batch_general_branches_lockstep(B, ctx):
+    scs = _slow_path_scenarios()
+    note("case: batch of RK4 / Euler / exact gains with cubic, range and mixture-noise "
+         "measurements, sizes 32..96, lockstep, 2 steps")
+    fs = make(B, ctx, scs)
+    try:
+        for k in range(2):
+            before = [B.pmf_get_state(f)[1:] for f in fs]
+            lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, k), want_loglik=True)
+            what = f"general step {k}"
+            _K[what] = k
+            check_against_oracle(B, fs, scs, before, lls, what)
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
 def test_batch_replays_are_deterministic(B, ctx):
     note("case: two identical batches give bitwise equal densities")
     scs = W.batched_workload(24, K=3)
