@@ -754,14 +754,20 @@ extern __shared__ __align__(16) unsigned char pmf_fsm[];
 __shared__ FState pmf_FS[GMAX];
 __shared__ double pmf_slots[32 * 8 + GMAX * 8];
 __shared__ int pmf_item;
+__shared__ GItem pmf_gi;   // the group being processed, written by thread 0 of the kernel loop
 
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) const float cgfloat;
 typedef __attribute__((address_space(1))) const unsigned long long cgu64;   // a complex pair
 
 template <int N0, int N1, int NX, int G>
-__device__ __noinline__ void process_group(const GItem& GI, const BItem* __restrict__ items, const FPlan* __restrict__ plans,
-                              const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out, int bufcplx) {
+__device__ __noinline__ void process_group(const BItem* __restrict__ items, const FPlan* __restrict__ plans,
+                                           const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out,
+                                           int bufcplx) {
+    // the group's first item and size, uniform (scalar registers; no per-thread copy)
+    struct {
+        int first, count;
+    } const GI = {__builtin_amdgcn_readfirstlane(pmf_gi.first), __builtin_amdgcn_readfirstlane(pmf_gi.G)};
     float2* bufA = reinterpret_cast<float2*>(pmf_fsm);
     float2* bufB = bufA + bufcplx;
     float2* twr = bufB + bufcplx;   // 128
@@ -774,7 +780,7 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
     constexpr int TPR = G * SEGW, RPS = FUSED_THREADS / TPR;
     constexpr int NT = FUSED_THREADS;
     const int tid = threadIdx.x;
-    const int Gact = GI.G;   // filters present (<= G)
+    const int Gact = GI.count;   // filters present (<= G)
 
     // plans into LDS, one 8-byte word per thread (one round trip for the group)
     constexpr int PW = sizeof(FPlan) / sizeof(double);
@@ -1016,7 +1022,6 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
         double u0 = u0first;
         const float* pr = Pr + tr * RS + g * RP + j;
         float* po = Po + tr * RS + g * RP + j;
-#pragma unroll 2
         for (int r = tr; r < N0; r += RPS, u0 += du0, pr += RPS * RS, po += RPS * RS) {
             const double L = Pg.fast ? qpoly(al, be, ga, u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
             const float v = *pr * __expf((float)(L - sh));
@@ -1070,7 +1075,6 @@ __device__ __noinline__ void process_group(const GItem& GI, const BItem* __restr
             double nu0 = F.amap[0] * ((double)tr - half0) + F.amap[1] * uj + F.bmap[0];
             double nu1 = F.amap[2] * ((double)tr - half0) + F.amap[3] * uj + F.bmap[1];
             const double dn0 = F.amap[0] * RPS, dn1 = F.amap[2] * RPS;
-#pragma unroll 2
             for (int r = tr; r < N0; r += RPS, nu0 += dn0, nu1 += dn1) {
                 float val = 0.f;
                 if (nu0 >= 0.0 && nu0 <= (double)(N0 - 1) && nu1 >= 0.0 && nu1 <= (double)(N1 - 1)) {
@@ -1141,15 +1145,19 @@ k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__
         const FPlan* __restrict__ plans, int* ctr, const double* __restrict__ zall, int nzmax,
         double* __restrict__ ll_out, int bufcplx) {
     for (;;) {
-        if (threadIdx.x == 0) pmf_item = atomicAdd(ctr, 1);
+        if (threadIdx.x == 0) {
+            const int next = atomicAdd(ctr, 1);
+            pmf_item = next;
+            if (next < ngroups) pmf_gi = groups[next];
+        }
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(pmf_item);
+        const int type = __builtin_amdgcn_readfirstlane(pmf_gi.type);
         __syncthreads();
         if (it >= ngroups) break;
-        const GItem GI = groups[it];
 #define PMF_GROUP(T, N0, N1, NX) \
-    case T: process_group<N0, N1, NX, group_g<N0, N1>()>(GI, items, plans, zall, nzmax, ll_out, bufcplx); break;
-        switch (GI.type) {
+    case T: process_group<N0, N1, NX, group_g<N0, N1>()>(items, plans, zall, nzmax, ll_out, bufcplx); break;
+        switch (type) {
             PMF_GROUP(GT_2D_128, 128, 128, 2)
             PMF_GROUP(GT_2D_96, 96, 96, 2)
             PMF_GROUP(GT_2D_64, 64, 64, 2)
