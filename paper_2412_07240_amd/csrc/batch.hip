@@ -1672,8 +1672,6 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
         std::string why;
         if (!batch_fusable(filters[i], &why)) return fail(PMF_E_INVALID, "filter not fusable: " + why);
         nzmax = std::max(nzmax, filters[i]->model.nz);
-        for (int j = i + 1; j < n && j < i + 2; ++j)
-            if (filters[j] == filters[i]) return fail(PMF_E_INVALID, "filter listed twice");
     }
     for (int i = 0; i < n * nzmax; ++i)
         if (!std::isfinite(z[i])) return fail(PMF_E_INVALID, "non-finite measurement");
@@ -1688,6 +1686,13 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
                 same = false;
                 break;
             }
+    if (!same) {
+        // a filter listed twice would be stepped twice in one launch, racing with itself
+        std::vector<pmf_filter*> sorted(filters, filters + n);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(PMF_E_INVALID, "filter listed twice");
+    }
     for (int i = 0; i < n; ++i) {
         e = batch_enter(filters[i]);
         if (e != hipSuccess) return hip_fail(e, "batch enter");

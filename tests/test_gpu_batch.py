@@ -264,6 +264,25 @@ def test_batch_replays_are_deterministic(B, ctx):
         assert np.array_equal(a, b)
 
 
+def test_batch_rejects_bad_calls(B, ctx):
+    note("case: batch refuses a filter listed twice (not adjacent), T <= 0 and non-finite z")
+    scs = W.batched_workload(3, K=1)
+    fs = make(B, ctx, scs)
+    try:
+        for args in (([fs[0], fs[1], fs[0]], 0.05, zmat([scs[0], scs[1], scs[0]], 0)),
+                     (fs, 0.0, zmat(scs, 0)),
+                     (fs, 0.05, np.full((3, 2), np.nan))):
+            with pytest.raises(B.PmfError) as e:
+                B.pmf_batch_step(ctx, *args)
+            assert e.value.status == B.PMF_E_INVALID
+        # the filters are untouched and still step normally
+        lls = B.pmf_batch_step(ctx, fs, 0.05, zmat(scs, 0), want_loglik=True)
+        assert np.all(np.isfinite(lls))
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
 def test_batch_rejects_unsupported_filters(B, ctx):
     note("case: batch rejects FP64 / 3-D filters before running")
     sc = W.config2(K=1, N=32)                       # FP64
