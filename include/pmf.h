@@ -209,11 +209,13 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
 /* One predict(T) + update(z) cycle for n filters in one fused launch (Fourier
  * grids, FP32, nx <= 2, N_a <= 128 per axis for nx = 2, N <= 256 for nx = 1;
  * other filters are rejected with PMF_E_INVALID before anything runs).
- * z: n * nz_max doubles, row f holds filter f's measurement (nz_max = largest nz).
+ * z: n * nz_max doubles, row f holds filter f's measurement (nz_max = largest nz);
+ * copied into pinned staging before the call returns (the caller may reuse it).
  * loglik: NULL or n doubles written by an asynchronous copy (as pmf_update).
- * The step is recorded once as a HIP graph per (filter set, T, stream) and
- * replayed; results equal n separate pmf_predict + pmf_update calls up to FP32
- * rounding of the likelihood shift.  Async. */
+ * Each filter may appear once (a repeated filter is rejected).  The step is
+ * recorded as HIP graphs per (filter set, T, stream), one per staging slot of z,
+ * and replayed; results equal n separate pmf_predict + pmf_update calls up to
+ * FP32 rounding of the likelihood shift.  Async. */
 pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
                           const double* z, double* loglik, void* stream);
 
