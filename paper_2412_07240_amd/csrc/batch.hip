@@ -218,54 +218,88 @@ __device__ __noinline__ void plan_stage_coefs(const PredictArgs& a, const double
     }
 }
 
+// One filter's plan.  Every operand is loaded before the first branch on any of
+// them (the model, the grid, the constants of the interval and the row of z), so
+// that the loads go out together: one memory round trip after the item's own.
 template <int NX>
-__device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Pout) {
-    // built in registers and stored once: loads of the constants can all be
-    // issued up front (no interleaved stores that could alias them)
-    FPlan P;
+__device__ void plan_one(const BItem& I, const double* __restrict__ zs, int nzmax, double* __restrict__ zd,
+                         FPlan& __restrict__ Pout) {
+    constexpr int n = NX;   // compile-time: the small matrix loops unroll into registers
     const PredictArgs& a = I.k->pa;
     const KModel& m = I.k->m;
-    const DevDesc* d = I.d;
-    constexpr int n = NX;   // compile-time: the small matrix loops unroll into registers
-    Grid g = d->g;
-    int l = a.lmin;
-    P.bad = 0;
-    if (a.integ == PMF_INT_EXACT) {
-        // W_y = M^-1 W M^-T on the 2 x 2 (or 1 x 1) block, in registers
-        const double m00 = g.Mi[0], m01 = g.Mi[1], m10 = g.Mi[MS], m11 = g.Mi[MS + 1];
-        const double w00 = a.W[0], w01 = a.W[1], w10 = a.W[MS], w11 = a.W[MS + 1];
-        if (n == 2) {
-            const double t00 = m00 * w00 + m01 * w10, t01 = m00 * w01 + m01 * w11;
-            const double t10 = m10 * w00 + m11 * w10, t11 = m10 * w01 + m11 * w11;
-            P.gc[0] = t00 * m00 + t01 * m01;
-            P.gc[1] = t10 * m10 + t11 * m11;
-            P.gc[2] = t00 * m10 + t01 * m11;
-        } else {
-            P.gc[0] = m00 * w00 * m00;
-            P.gc[1] = 0.0;
-            P.gc[2] = 0.0;
+    const DevDesc& d = *I.d;
+
+    // ---- loads
+    Grid g;
+    mat_zero(g.M);
+    mat_zero(g.Mi);
+    double Phi[MSQ], W[MSQ];
+    mat_zero(Phi);
+    mat_zero(W);
+    for (int i = 0; i < MS; ++i) g.c[i] = i < n ? d.g.c[i] : 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            g.M[i * MS + j] = d.g.M[i * MS + j];
+            g.Mi[i * MS + j] = d.g.Mi[i * MS + j];
+            Phi[i * MS + j] = a.Phi[i * MS + j];
+            W[i * MS + j] = a.W[i * MS + j];
         }
+    const int par = d.par;
+    const double pscale = d.pscale;
+    const int integ = a.integ, lmin = a.lmin;
+    const double T = a.T, etr = a.etr;
+    const double Wn0 = m.Wnom[0], Wn1 = m.Wnom[MS + 1], span = m.span;
+    const int interp = m.interp, meas = m.meas, ncomp = m.ncomp, nz = m.nz;
+    const double lw0 = m.lw[0];
+    // measurement rows past nz are loaded from valid addresses and weighted zero
+    double z[3], H[3][NX], nmean[3], Ri[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        z[i] = zs[i < nzmax ? i : 0];
+        nmean[i] = m.nmean[0][i];
+#pragma unroll
+        for (int k = 0; k < n; ++k) H[i][k] = m.H[i * MS + k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Ri[i * 3 + k] = m.nRi[0][i * MS + k];
+    }
+
+    // ---- the plan, built in registers
+    FPlan P;
+    int l = lmin;
+    P.bad = 0;
+    // exact integrator: W_y = M^-1 W M^-T on the current grid
+    if (n == 2) {
+        const double m00 = g.Mi[0], m01 = g.Mi[1], m10 = g.Mi[MS], m11 = g.Mi[MS + 1];
+        const double t00 = m00 * W[0] + m01 * W[MS], t01 = m00 * W[1] + m01 * W[MS + 1];
+        const double t10 = m10 * W[0] + m11 * W[MS], t11 = m10 * W[1] + m11 * W[MS + 1];
+        P.gc[0] = t00 * m00 + t01 * m01;
+        P.gc[1] = t10 * m10 + t11 * m11;
+        P.gc[2] = t00 * m10 + t01 * m11;
     } else {
-        // the stage planners take M^-1 through memory: a copy of their own
+        P.gc[0] = g.Mi[0] * W[0] * g.Mi[0];
+        P.gc[1] = 0.0;
+        P.gc[2] = 0.0;
+    }
+    if (integ != PMF_INT_EXACT) {
+        // RK4 / Euler: stage coefficients into the filter's table (out of line)
         double Mi[MSQ];
         mat_copy(Mi, g.Mi);
-        if (a.integ == PMF_INT_RK4 && a.T > 0.0) l = plan_substeps(a, Mi, n, l);
+        if (integ == PMF_INT_RK4 && T > 0.0) l = plan_substeps(a, Mi, n, l);
         if (l > FUSED_LMAX) {
             l = FUSED_LMAX;
             P.bad = 1;
         }
-        plan_stage_coefs(a, Mi, n, l, a.T / l, I.coef);
+        plan_stage_coefs(a, Mi, n, l, T / l, I.coef);
     }
-    const double h = a.T / l;
     P.l = l;
-    P.h = h;
-    P.etr = a.etr;
-    P.T = a.T;
+    P.h = T / l;
+    P.etr = etr;
+    P.T = T;
     // grid follows x' = A x
     double c2[MS], M2[MSQ];
     mat_zero(M2);
-    mat_vec(c2, a.Phi, g.c, n);
-    mat_mul(M2, a.Phi, g.M, n);
+    mat_vec(c2, Phi, g.c, n);
+    mat_mul(M2, Phi, g.M, n);
     for (int i = 0; i < n; ++i) g.c[i] = c2[i];
     mat_copy(g.M, M2);
     grid_finish(g, n);
@@ -280,77 +314,70 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ z, FPlan& Po
     P.Mi[2] = g.Mi[MS];
     P.Mi[3] = g.Mi[MS + 1];
     P.vol = g.vol;
-    P.Wnom[0] = m.Wnom[0];
-    P.Wnom[1] = m.Wnom[MS + 1];
-    P.span = m.span;
-    P.integ = a.integ;
-    P.interp = m.interp;
+    P.Wnom[0] = Wn0;
+    P.Wnom[1] = Wn1;
+    P.span = span;
+    P.integ = integ;
+    P.interp = interp;
     P.nx = n;
-    P.par = d->par;
-    P.pscale = d->pscale;
-    // linear-Gaussian measurement: log l as a quadratic in index coordinates
-    P.fast = (m.meas == PMF_H_LINEAR && m.ncomp == 1) ? 1 : 0;
-    P.q0 = 0.0;
-    P.qb[0] = P.qb[1] = 0.0;
-    P.qQ[0] = P.qQ[1] = P.qQ[2] = 0.0;
-    if (P.fast) {
-        // fixed trip counts (nz <= 3; rows past nz weighted zero): every load of the
-        // model is independent of nz and issued up front, and the arrays stay in
-        // registers
-        const int nz = m.nz;
-        double r0[3], G[6], Rir0[3], Ri[9];
+    P.par = par;
+    P.pscale = pscale;
+    // linear-Gaussian measurement: log l as a quadratic in index coordinates,
+    // r0 = z - mean - H c, G = H M (rows past nz zero)
+    P.fast = (meas == PMF_H_LINEAR && ncomp == 1) ? 1 : 0;
+    double r0[3], G[3][NX], Rir0[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i) {
+        const bool on = i < nz;
+        double hc = 0.0;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) Ri[i * 3 + k] = (i < nz && k < nz) ? m.nRi[0][i * MS + k] : 0.0;
+        for (int k = 0; k < n; ++k) hc += H[i][k] * g.c[k];
+        r0[i] = on ? z[i] - nmean[i] - hc : 0.0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const bool on = i < nz;
-            double hc = 0.0;
-#pragma unroll
-            for (int k = 0; k < n; ++k) hc += m.H[i * MS + k] * g.c[k];
-            r0[i] = on ? z[i] - m.nmean[0][i] - hc : 0.0;
-#pragma unroll
-            for (int b = 0; b < n; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < n; ++k) s += m.H[i * MS + k] * g.M[k * MS + b];
-                G[i * 2 + b] = on ? s : 0.0;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
+        for (int b = 0; b < n; ++b) {
             double s = 0.0;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) s += Ri[i * 3 + k] * r0[k];
-            Rir0[i] = s;
+            for (int k = 0; k < n; ++k) s += H[i][k] * g.M[k * MS + b];
+            G[i][b] = on ? s : 0.0;
         }
-        double rr = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) rr += r0[i] * Rir0[i];
-        P.q0 = m.lw[0] - 0.5 * rr;
-        double Qf[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int a2 = 0; a2 < n; ++a2) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) s += G[i * 2 + a2] * Rir0[i];
-            P.qb[a2] = s;
-#pragma unroll
-            for (int b = 0; b < n; ++b) {
-                double t = 0.0;
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) t += G[i * 2 + a2] * Ri[i * 3 + k] * G[k * 2 + b];
-                Qf[a2 * 2 + b] = t;
-            }
-        }
-        P.qQ[0] = Qf[0];
-        P.qQ[1] = Qf[3];
-        P.qQ[2] = Qf[1];
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += (i < nz && k < nz ? Ri[i * 3 + k] : 0.0) * r0[k];
+        Rir0[i] = s;
+    }
+    double rr = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rr += r0[i] * Rir0[i];
+    double qb[2] = {0.0, 0.0}, Qf[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a2 = 0; a2 < n; ++a2) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) s += G[i][a2] * Rir0[i];
+        qb[a2] = s;
+#pragma unroll
+        for (int b = 0; b < n; ++b) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) t += G[i][a2] * (i < nz && k < nz ? Ri[i * 3 + k] : 0.0) * G[k][b];
+            Qf[a2 * 2 + b] = t;
+        }
+    }
+    P.q0 = P.fast ? lw0 - 0.5 * rr : 0.0;
+    P.qb[0] = P.fast ? qb[0] : 0.0;
+    P.qb[1] = P.fast ? qb[1] : 0.0;
+    P.qQ[0] = P.fast ? Qf[0] : 0.0;
+    P.qQ[1] = P.fast ? Qf[3] : 0.0;
+    P.qQ[2] = P.fast ? Qf[1] : 0.0;
     Pout = P;
+    if (zd)
+        for (int q = 0; q < 3; ++q)
+            if (q < nzmax) zd[q] = z[q];
 }
 
 // One thread per filter; thread 0 also clears the work counter of the fused
@@ -362,16 +389,13 @@ __global__ void __launch_bounds__(64) k_batch_plan(const BItem* __restrict__ ite
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *ctr = 0;
     if (i >= n) return;
-    const BItem& I = items[i];
+    const BItem I = items[i];
     const double* zs = zsrc + (size_t)I.idx * nzmax;
-    double z[3] = {0.0, 0.0, 0.0};
-    for (int q = 0; q < nzmax && q < 3; ++q) z[q] = zs[q];
-    if (zdst)
-        for (int q = 0; q < nzmax && q < 3; ++q) zdst[(size_t)I.idx * nzmax + q] = z[q];
+    double* zd = zdst ? zdst + (size_t)I.idx * nzmax : nullptr;
     if (I.nx == 2)
-        plan_one<2>(I, z, plans[i]);
+        plan_one<2>(I, zs, nzmax, zd, plans[i]);
     else
-        plan_one<1>(I, z, plans[i]);
+        plan_one<1>(I, zs, nzmax, zd, plans[i]);
 }
 
 
