@@ -21,6 +21,7 @@ namespace pmf {
 
 constexpr int FUSED_THREADS = 1024;
 constexpr int FUSED_LMAX = 64;
+constexpr int PLAN_THREADS = 16;   // planning kernel workgroup
 
 constexpr int GMAX = 16;            // filters of one size packed into a workgroup
 constexpr int CPLX_BUDGET = 9400;   // complex LDS entries per buffer (2 buffers)
@@ -381,17 +382,20 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ zs, int nzma
 }
 
 // One thread per filter; thread 0 also clears the work counter of the fused
-// launch.  zsrc: the step's measurements (rows of nzmax, possibly in mapped host
-// memory); zdst (optional): device copy of them for the fused kernel.
-__global__ void __launch_bounds__(64) k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
+// launch.  zsrc: the step's measurements, one row of nzmax per item in item
+// order (possibly in mapped host memory), so that its load needs no field of the
+// item; zdst (optional): device copy of them, same order, for the fused kernel.
+// Narrow workgroups spread the filters' latency-bound round trips over every
+// compute unit.
+__global__ void __launch_bounds__(PLAN_THREADS) k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
                              const double* __restrict__ zsrc, double* __restrict__ zdst, int nzmax,
                              int* __restrict__ ctr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *ctr = 0;
     if (i >= n) return;
     const BItem I = items[i];
-    const double* zs = zsrc + (size_t)I.idx * nzmax;
-    double* zd = zdst ? zdst + (size_t)I.idx * nzmax : nullptr;
+    const double* zs = zsrc + (size_t)i * nzmax;
+    double* zd = zdst ? zdst + (size_t)i * nzmax : nullptr;
     if (I.nx == 2)
         plan_one<2>(I, zs, nzmax, zd, plans[i]);
     else
@@ -828,7 +832,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         FS[tid].pout = par ? p0 : p1;
         FS[tid].d = d;
         FS[tid].km = &k->m;
-        FS[tid].zrow = zall + (size_t)idx * nzmax;
+        FS[tid].zrow = zall + (size_t)(GI.first + gg) * nzmax;
         FS[tid].idx = idx;
     }
     for (int i = tid; i < H1; i += NT) {
@@ -1275,6 +1279,7 @@ struct BatchCache {
     int grid = 0, bufcplx = 0;
     hipGraph_t graph[2] = {nullptr, nullptr};          // one step per staging slot
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    std::vector<int> order;                            // filter index of each item
 };
 
 namespace pmf {
@@ -1457,6 +1462,8 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     std::vector<GItem> groups;
     const int maxcplx = group_items(items, sorted, groups);
     c->ngroups = (int)groups.size();
+    c->order.resize(n);
+    for (int q = 0; q < n; ++q) c->order[q] = sorted[q].idx;
     bool ok = true;
     auto A = [&](size_t bytes) {
         void* p = ctx_alloc(ctx, bytes, st);
@@ -1501,7 +1508,7 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, cap, c->d_items, c->d_plans, n,
+            hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, cap, c->d_items, c->d_plans, n,
                                c->hz_dev[i], c->d_z, nzmax, c->d_ctr);
             hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, cap, c->d_groups, c->ngroups,
                                c->d_items, c->d_plans, c->d_ctr, c->d_z, nzmax, c->d_ll, c->bufcplx);
@@ -1667,13 +1674,14 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
     const int grid = std::min(ng, it->second * db->ncu);
     std::memcpy(db->h_items, sorted.data(), sizeof(BItem) * n);
     std::memcpy(db->h_groups, groups.data(), sizeof(GItem) * ng);
-    std::memcpy(db->h_z, z, sizeof(double) * 3 * n);
+    for (int q = 0; q < n; ++q)   // rows in item order
+        std::memcpy(db->h_z + (size_t)q * 3, z + (size_t)sorted[q].idx * 3, sizeof(double) * 3);
     e = hipMemcpyAsync(db->d_items, db->h_items, sizeof(BItem) * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(db->d_groups, db->h_groups, sizeof(GItem) * ng, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(db->d_z, db->h_z, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "served batch upload");
-    hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, db->d_items, db->d_plans, n, db->d_z,
+    hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st, db->d_items, db->d_plans, n, db->d_z,
                        nullptr, 3, db->d_ctr);
     hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, db->d_groups, ng, db->d_items,
                        db->d_plans, db->d_ctr, db->d_z, 3, db->d_ll, maxcplx);
@@ -1735,7 +1743,9 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
     c->slot ^= 1;
     e = hipEventSynchronize(c->ev[slot]);
     if (e != hipSuccess) return hip_fail(e, "staging wait");
-    std::memcpy(c->h_z[slot], z, sizeof(double) * n * nzmax);
+    // rows in item order
+    for (int q = 0; q < n; ++q)
+        std::memcpy(c->h_z[slot] + (size_t)q * nzmax, z + (size_t)c->order[q] * nzmax, sizeof(double) * nzmax);
     if (ctx->profile) {
         // same kernels as the graph, launched directly with events around the fused one
         if ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {
@@ -1750,7 +1760,7 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             hipEvent_t t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
             ctx->ev_used++;
             ctx->ev_stream = st;
-            hipLaunchKernelGGL(k_batch_plan, dim3((n + 63) / 64), dim3(64), 0, st, c->d_items, c->d_plans, n,
+            hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st, c->d_items, c->d_plans, n,
                                c->hz_dev[slot], c->d_z, c->nzmax, c->d_ctr);
             e = hipEventRecord(t0, st);
             if (e == hipSuccess) {
