@@ -212,16 +212,18 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
  * z: n * nz_max doubles, row f holds filter f's measurement (nz_max = largest nz);
  * copied into pinned staging before the call returns (the caller may reuse it).
  * loglik: NULL or n doubles written by an asynchronous copy (as pmf_update).
- * Each filter may appear once (a repeated filter is rejected).  The step is
- * recorded as HIP graphs per (filter set, T, stream), one per staging slot of z,
- * and replayed; results equal n separate pmf_predict + pmf_update calls up to
- * FP32 rounding of the likelihood shift.  Async. */
+ * Each filter may appear once (a repeated filter is rejected).  The launch
+ * set-up (grouping, device tables) is cached per (filter set, T, stream); a
+ * step is then two kernel launches (per-filter planning, fused cycle) and z
+ * goes through one of several mapped staging slots, so up to four steps can be
+ * in flight before the call blocks.  Results equal n separate pmf_predict +
+ * pmf_update calls up to FP32 rounding of the likelihood shift.  Async. */
 pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
                           const double* z, double* loglik, void* stream);
 
 /* Kernel timing of batched steps: with enable != 0, every later pmf_batch_step
- * launches the step's kernels directly (instead of replaying its graph) and
- * records HIP events on its stream right before and after the fused kernel.
+ * also records HIP events on its stream right before and after the fused
+ * kernel.
  * pmf_batch_kernel_time synchronises the context's last batch stream and
  * returns the summed event time (ms) of the fused kernel and the number of
  * launches since the previous call, then clears them.  Diagnostic. */

@@ -1271,15 +1271,19 @@ struct BatchCache {
     double* d_z = nullptr;
     double* d_ll = nullptr;
     int* d_ctr = nullptr;
-    double* h_z[2] = {nullptr, nullptr};      // pinned staging of z, one per slot
-    double* hz_dev[2] = {nullptr, nullptr};   // the same memory as the device reads it
-    hipEvent_t ev[2] = {nullptr, nullptr};    // the step that read slot i has finished
-    int slot = 0;
+    // z staging: step k writes slot k % ZSLOTS of mapped pinned memory, which its
+    // planning kernel reads.  An event is recorded after every ZEVERY-th step only
+    // (an event costs several microseconds of GPU time between steps); before
+    // step k overwrites its slot it waits on the event of a step in
+    // [k - ZSLOTS, k - ZEVERY - 1], which also covers step k - ZSLOTS.
+    static constexpr int ZSLOTS = 8, ZEVERY = 4;
+    double* h_z[ZSLOTS] = {};                 // pinned staging of z
+    double* hz_dev[ZSLOTS] = {};              // the same memory as the device reads it
+    hipEvent_t ev[2] = {nullptr, nullptr};    // alternate over groups of ZEVERY steps
+    long long step = 0;
     size_t lds = 0;
     int grid = 0, bufcplx = 0;
-    hipGraph_t graph[2] = {nullptr, nullptr};          // one step per staging slot
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    std::vector<int> order;                            // filter index of each item
+    std::vector<int> order;                   // filter index of each item
 };
 
 namespace pmf {
@@ -1287,10 +1291,6 @@ namespace pmf {
 static void cache_free(pmf_ctx* ctx, BatchCache* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    for (int i = 0; i < 2; ++i) {
-        if (c->exec[i]) (void)hipGraphExecDestroy(c->exec[i]);
-        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
-    }
     ctx_free(ctx, c->d_items, nullptr);
     ctx_free(ctx, c->d_groups, nullptr);
     ctx_free(ctx, c->d_plans, nullptr);
@@ -1298,10 +1298,10 @@ static void cache_free(pmf_ctx* ctx, BatchCache* c) {
     ctx_free(ctx, c->d_z, nullptr);
     ctx_free(ctx, c->d_ll, nullptr);
     ctx_free(ctx, c->d_ctr, nullptr);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < BatchCache::ZSLOTS; ++i)
         if (c->h_z[i]) (void)hipHostFree(c->h_z[i]);
+    for (int i = 0; i < 2; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-    }
     delete c;
 }
 
@@ -1483,11 +1483,11 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     if (e == hipSuccess) e = hipMemcpy(c->d_items, sorted.data(), sizeof(BItem) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(c->d_groups, groups.data(), sizeof(GItem) * groups.size(), hipMemcpyHostToDevice);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    for (int i = 0; i < BatchCache::ZSLOTS && e == hipSuccess; ++i) {
         e = hipHostMalloc(reinterpret_cast<void**>(&c->h_z[i]), sizeof(double) * n * nzmax, hipHostMallocMapped);
         if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hz_dev[i]), c->h_z[i], 0);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
     }
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "batch setup");
     c->bufcplx = maxcplx;
     c->lds = fused_lds(maxcplx);
@@ -1501,23 +1501,6 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     e = hipGetDeviceProperties(&prop, ctx->device);
     if (e != hipSuccess) return hip_fail(e, "device properties");
     c->grid = std::min(c->ngroups, per_cu * prop.multiProcessorCount);
-    // the step as a graph, one per staging slot: plan every filter (reading its z
-    // from the slot's mapped host memory, clearing the work counter), fused kernel
-    hipStream_t cap;
-    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, cap, c->d_items, c->d_plans, n,
-                               c->hz_dev[i], c->d_z, nzmax, c->d_ctr);
-            hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, cap, c->d_groups, c->ngroups,
-                               c->d_items, c->d_plans, c->d_ctr, c->d_z, nzmax, c->d_ll, c->bufcplx);
-            e = hipStreamEndCapture(cap, &c->graph[i]);
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&c->exec[i], c->graph[i], nullptr, nullptr, 0);
-    }
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) return hip_fail(e, "graph capture");
     return PMF_OK;
 }
 
@@ -1737,17 +1720,19 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
         }
         c = ctx->batch;
     }
-    // stage z in mapped pinned memory (two slots, each reused only after the step
-    // that read it finished); the planning kernel reads it there, no separate copy
-    const int slot = c->slot;
-    c->slot ^= 1;
-    e = hipEventSynchronize(c->ev[slot]);
+    // stage z in mapped pinned memory; the planning kernel reads it there, no
+    // separate copy.  The event of the group of steps before the previous one
+    // (never recorded before step 2 ZEVERY: the first slots are fresh).
+    const long long k = c->step++;
+    const int slot = (int)(k % BatchCache::ZSLOTS);
+    const int evi = (int)((k / BatchCache::ZEVERY) & 1);
+    e = hipEventSynchronize(c->ev[evi]);
     if (e != hipSuccess) return hip_fail(e, "staging wait");
     // rows in item order
     for (int q = 0; q < n; ++q)
         std::memcpy(c->h_z[slot] + (size_t)q * nzmax, z + (size_t)c->order[q] * nzmax, sizeof(double) * nzmax);
     if (ctx->profile) {
-        // same kernels as the graph, launched directly with events around the fused one
+        // the same launches with events around the fused kernel
         if ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {
             for (int q = 0; q < 2 && e == hipSuccess; ++q) {
                 hipEvent_t ev;
@@ -1772,9 +1757,15 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             if (e == hipSuccess) e = hipEventRecord(t1, st);
         }
     } else {
-        e = hipGraphLaunch(c->exec[slot], st);
+        // plan every filter (reading its z from the slot, clearing the work
+        // counter), then the fused kernel
+        hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st,
+                           c->d_items, c->d_plans, n, c->hz_dev[slot], c->d_z, c->nzmax, c->d_ctr);
+        hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups, c->ngroups,
+                           c->d_items, c->d_plans, c->d_ctr, c->d_z, c->nzmax, c->d_ll, c->bufcplx);
+        e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipEventRecord(c->ev[slot], st);
+    if (e == hipSuccess && k % BatchCache::ZEVERY == BatchCache::ZEVERY - 1) e = hipEventRecord(c->ev[evi], st);
     if (e == hipSuccess && loglik) e = hipMemcpyAsync(loglik, c->d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return PMF_OK;

@@ -264,6 +264,36 @@ def test_batch_replays_are_deterministic(B, ctx):
         assert np.array_equal(a, b)
 
 
+def test_batch_steps_back_to_back_equal_synchronised_steps(B, ctx):
+    """More steps than the library's z staging slots, submitted back to back from
+    one host buffer that the caller overwrites between calls: bitwise equal to
+    the same steps with the host waiting for each (a slot reused too early would
+    feed a later step's z to an earlier one)."""
+    K = 20
+    note(f"case: {K} batched steps back to back vs waited for, 24 mixed-size filters")
+    scs = W.batched_workload(24, K=K)
+    outs = []
+    for wait in (True, False):
+        fs = make(B, ctx, scs)
+        fa = B.FilterArray(fs)
+        zbuf = np.zeros((len(scs), 2))
+        try:
+            for k in range(K):
+                zbuf[:] = zmat(scs, k)
+                B.pmf_batch_step(ctx, fa, scs[0].T, zbuf)
+                if wait:
+                    B.pmf_stream_sync()
+            B.pmf_stream_sync()
+            outs.append([B.pmf_get_state(f) for f in fs])
+        finally:
+            for f in fs:
+                B.pmf_destroy(f)
+    for i, (a, b) in enumerate(zip(*outs)):
+        assert np.all(np.isfinite(a[4])), f"filter {i}"
+        for q in (1, 2, 4):
+            assert np.array_equal(a[q], b[q]), f"filter {i} field {q}"
+
+
 def test_batch_rejects_bad_calls(B, ctx):
     note("case: batch refuses a filter listed twice (not adjacent), T <= 0 and non-finite z")
     scs = W.batched_workload(3, K=1)
