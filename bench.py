@@ -30,6 +30,9 @@ if ROOT not in sys.path:
 
 METRIC = "grid-point FPE updates/sec at stated L1 error vs FP64; p50/p99 update latency"
 HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs x 4 SIMDs x 16 lanes per clock (a wave64 instruction every
+# 4 clocks per SIMD; packed FP32 is not used) at 2.4 GHz
+VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 BYTES_PER_POINT = 8            # FP32 density read once + written once per cycle
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_batch_4096_traffic.json")
 
@@ -209,15 +212,24 @@ def run_batched(args):
                    "filters": nf, "points_per_step": pts, "T": T, "reductions": "f64"},
     }
     traffic = None
+    valu = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("source_hash") == source_hash() and tr.get("points_per_step") == pts:
             traffic = tr.get("bytes_per_launch")
+            valu = tr.get("valu_wave_instr_per_launch")
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                        "kernel": "pmf::k_fused", "kernel_ms": kavg_ms,
                        "algorithmic_bytes_per_launch": BYTES_PER_POINT * pts}
+    if valu:
+        # what actually bounds the fused cycle: VALU issue (SQ_INSTS_VALU of the
+        # same sources from the counter run, over the live kernel time)
+        lane = 64.0 * valu
+        out["valu_issue"] = {"lane_instr_per_point": lane / pts,
+                             "achieved": lane / (kavg_ms * 1e-3), "peak": VALU_PEAK_LANE_INSTR,
+                             "unit": "lane-instructions/s", "frac": lane / (kavg_ms * 1e-3) / VALU_PEAK_LANE_INSTR}
 
     if not args.no_extras:
         # p50/p99 latency of a step (submit -> results on the host)
