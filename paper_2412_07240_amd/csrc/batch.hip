@@ -527,8 +527,10 @@ template <int R> __device__ inline void fdft(float2* v, int sign) {
     if constexpr (R == 8) fdft8(v, sign);
 }
 
-// one Stockham pass; LF: consecutive threads take consecutive lines
-template <int R, int N, int NS, int NL, int LS, int ES, int SIGN, bool LF>
+// one Stockham pass; LF: consecutive threads take consecutive lines.  GAP > 0
+// (with LS = 1): the lines come in runs of GAP with one skipped slot after each
+// run, i.e. line l starts at l + l / GAP
+template <int R, int N, int NS, int NL, int LS, int ES, int SIGN, bool LF, int GAP = 0>
 __device__ inline void cpass(const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw) {
     constexpr int NB = N / R;
     constexpr int TOT = NL * NB;
@@ -545,8 +547,9 @@ __device__ inline void cpass(const float2* __restrict__ in, float2* __restrict__
                 line = w / NB;
                 j = w - line * NB;
             }
-            const float2* src = in + line * LS;
-            float2* dst = out + line * LS;
+            const int lo = GAP ? line + line / GAP : line * LS;
+            const float2* src = in + lo;
+            float2* dst = out + lo;
             float2 v[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) v[r] = src[(j + r * NB) * ES];
@@ -568,15 +571,16 @@ __device__ inline void cpass(const float2* __restrict__ in, float2* __restrict__
     }
 }
 
-template <int N, int NL, int LS, int ES, int SIGN, bool LF, int P = 0, int NS = 1>
+template <int N, int NL, int LS, int ES, int SIGN, bool LF, int GAP = 0, int P = 0, int NS = 1>
 __device__ inline float2* cfft(float2* in, float2* out, const float2* tw) {
+    static_assert(GAP == 0 || LS == 1, "gapped lines are unit-stride");
     if constexpr (P == num_passes(N)) {
         return in;
     } else {
         constexpr int R = radix_at(N, P);
-        cpass<R, N, NS, NL, LS, ES, SIGN, LF>(in, out, tw);
+        cpass<R, N, NS, NL, LS, ES, SIGN, LF, GAP>(in, out, tw);
         __syncthreads();
-        return cfft<N, NL, LS, ES, SIGN, LF, P + 1, NS * R>(out, in, tw);
+        return cfft<N, NL, LS, ES, SIGN, LF, GAP, P + 1, NS * R>(out, in, tw);
     }
 }
 
@@ -785,6 +789,34 @@ __shared__ int pmf_item;
 __shared__ GItem pmf_gi;   // the group being processed, written by thread 0 of the kernel loop
 
 typedef __attribute__((address_space(1))) float gfloat;
+// spectral gain of one mode over the interval: a2 = k0^2, a1 = k0 (first
+// derivative symbol), b2 = k1^2, b1 = k1; exact, or the product over the RK4 /
+// Euler substeps of their amplification factors (stage coefficients in cf)
+__device__ inline float mode_gain(const FPlan& P, const double* cf, float a2, float a1, float b2, float b1) {
+    if (P.integ == PMF_INT_EXACT)
+        return __expf(-0.5f * ((float)P.gc[0] * a2 + (float)P.gc[1] * b2) - (float)P.gc[2] * a1 * b1);
+    const float hh = (float)P.h;
+    float g2 = 1.f;
+    if (P.integ == PMF_INT_EULER) {
+        for (int q = 0; q < P.l; ++q) {
+            const float sig = (float)cf[3 * q] * a2 + (float)cf[3 * q + 1] * b2 + 2.f * (float)cf[3 * q + 2] * a1 * b1;
+            g2 = g2 / (1.f + 0.5f * hh * sig);
+        }
+    } else {
+        for (int q = 0; q < P.l; ++q) {
+            const double* c3 = cf + 6 * q;
+            const float la = -0.5f * ((float)c3[0] * a2 + (float)c3[1] * b2 + 2.f * (float)c3[2] * a1 * b1);
+            const float lb = -0.5f * ((float)c3[3] * a2 + (float)c3[4] * b2 + 2.f * (float)c3[5] * a1 * b1);
+            const float lc = -0.5f * ((float)c3[6] * a2 + (float)c3[7] * b2 + 2.f * (float)c3[8] * a1 * b1);
+            const float y2 = 1.f + 0.5f * hh * la;
+            const float y3 = 1.f + 0.5f * hh * lb * y2;
+            const float y4 = 1.f + hh * lb * y3;
+            g2 *= 1.f + hh / 6.f * (la + 2.f * lb * y2 + 2.f * lb * y3 + lc * y4);
+        }
+    }
+    return g2;
+}
+
 typedef __attribute__((address_space(1))) const float cgfloat;
 typedef __attribute__((address_space(1))) const unsigned long long cgu64;   // a complex pair
 
@@ -884,91 +916,122 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     // ---- forward: rows (r2c), columns
     float2* cur = cfft<H1, N0 * G, PITCH, 1, -1, true>(bufA, bufB, twr);
     float2* oth = (cur == bufA) ? bufB : bufA;
+    // 2-D: the DC and Nyquist entries of a row spectrum of real data are real,
+    // X_0 = Re Z_0 + Im Z_0 and X_H1 = Re Z_0 - Im Z_0; they are stored packed as
+    // X_0 + i X_H1 in entry 0, so that the column transforms run over H1 columns
+    // per filter (entry H1 is not used)
+    constexpr int MW = NX == 2 ? H1 : PITCH;   // entries written per row
 #pragma unroll 1
-    for (int e = tid; e < N0 * G * PITCH; e += NT) {
-        const int L = e / PITCH, s = e - L * PITCH;
+    for (int e = tid; e < N0 * G * MW; e += NT) {
+        const int L = e / MW, s = e - L * MW;
         const float2 Zs = cur[L * PITCH + (s == H1 ? 0 : s)];
         const float2 Zc = f2conj(cur[L * PITCH + (s == 0 ? 0 : H1 - s)]);
-        const float2 E = f2scale(f2add(Zs, Zc), 0.5f);
-        const float2 t = f2mul(twp[s], f2sub(Zs, Zc));
-        // X_s = E - i/2 W^s (Z_s - conj Z_{H1-s})
-        oth[L * PITCH + s] = f2add(E, make_float2(0.5f * t.y, -0.5f * t.x));
+        if (NX == 2 && s == 0) {
+            oth[L * PITCH] = make_float2(Zs.x + Zs.y, Zs.x - Zs.y);
+        } else {
+            const float2 E = f2scale(f2add(Zs, Zc), 0.5f);
+            const float2 t = f2mul(twp[s], f2sub(Zs, Zc));
+            // X_s = E - i/2 W^s (Z_s - conj Z_{H1-s})
+            oth[L * PITCH + s] = f2add(E, make_float2(0.5f * t.y, -0.5f * t.x));
+        }
     }
     __syncthreads();
     cur = oth;
     oth = (cur == bufA) ? bufB : bufA;
     if constexpr (NX == 2) {
-        cur = cfft<N0, SPITCH, 1, SPITCH, -1, true>(cur, oth, twc);
+        cur = cfft<N0, G * H1, 1, SPITCH, -1, true, H1>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
-    // ---- per-mode gain with 1/(N0 N1) of the unnormalised transforms; a thread
-    // owns spectral column c (filter g, frequency s1) and walks its rows
+    // ---- per-mode gain with 1/(N0 N1) of the unnormalised transforms.  2-D: the
+    // last wave takes the packed DC/Nyquist columns, the other waves the remaining
+    // columns, a thread owning one column (filter g, frequency s1) and walking its
+    // rows (no wave mixes the two kinds)
     {
         constexpr float inv = 1.0f / ((float)N0 * (float)N1);
-        constexpr int CPS = NT / SPITCH;   // rows walked in parallel per column
-        const int cth = tid % SPITCH, r0 = tid / SPITCH;
-        if (r0 < CPS) {
-            const int g = cth / PITCH, s1 = cth - g * PITCH;
-            const FPlan& P = FS[g].p;
-            const int kk1 = (s1 < H1) ? s1 : s1 - N1;
-            const float kap1 = (6.283185307179586f / N1) * kk1;
-            const float b2 = (NX == 2) ? kap1 * kap1 : 0.f;
-            const float b1 = (NX == 2) ? ((s1 == H1) ? 0.f : kap1) : 0.f;
-            const float scale = (float)P.etr * inv;
-            const float p0 = (float)P.gc[0], p1 = (float)P.gc[1], p2 = (float)P.gc[2];
-            const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
-            for (int s0 = r0; s0 < N0; s0 += CPS) {
-                float a1, a2;
-                if constexpr (NX == 2) {
-                    const int kk = (s0 < N0 / 2) ? s0 : s0 - N0;
-                    const float kap = (6.283185307179586f / N0) * kk;
-                    a2 = kap * kap;
-                    a1 = (2 * s0 == N0) ? 0.f : kap;
-                } else {
-                    a2 = kap1 * kap1;
-                    a1 = (s1 == H1) ? 0.f : kap1;
-                }
-                float g2;
-                if (P.integ == PMF_INT_EXACT) {
-                    g2 = __expf(-0.5f * (p0 * a2 + p1 * b2) - p2 * a1 * b1);
-                } else {
-                    const float hh = (float)P.h;
-                    g2 = 1.f;
-                    if (P.integ == PMF_INT_EULER) {
-                        for (int q = 0; q < P.l; ++q) {
-                            const float sig = (float)cf[3 * q] * a2 + (float)cf[3 * q + 1] * b2 +
-                                              2.f * (float)cf[3 * q + 2] * a1 * b1;
-                            g2 = g2 / (1.f + 0.5f * hh * sig);
-                        }
-                    } else {
-                        for (int q = 0; q < P.l; ++q) {
-                            const double* c3 = cf + 6 * q;
-                            const float la = -0.5f * ((float)c3[0] * a2 + (float)c3[1] * b2 + 2.f * (float)c3[2] * a1 * b1);
-                            const float lb = -0.5f * ((float)c3[3] * a2 + (float)c3[4] * b2 + 2.f * (float)c3[5] * a1 * b1);
-                            const float lc = -0.5f * ((float)c3[6] * a2 + (float)c3[7] * b2 + 2.f * (float)c3[8] * a1 * b1);
-                            const float y2 = 1.f + 0.5f * hh * la;
-                            const float y3 = 1.f + 0.5f * hh * lb * y2;
-                            const float y4 = 1.f + hh * lb * y3;
-                            g2 *= 1.f + hh / 6.f * (la + 2.f * lb * y2 + 2.f * lb * y3 + lc * y4);
-                        }
+        auto rowk = [](int s0, float& a2, float& a1) {
+            const int kk = (s0 < N0 / 2) ? s0 : s0 - N0;
+            const float kap = (6.283185307179586f / N0) * kk;
+            a2 = kap * kap;
+            a1 = (2 * s0 == N0) ? 0.f : kap;
+        };
+        if constexpr (NX == 2) {
+            constexpr int CWN = H1 - 1;       // columns 1 .. H1-1 of each filter
+            constexpr int NCOLN = G * CWN;
+            constexpr int TN = NT - 64;
+            constexpr int CPS = TN / NCOLN;   // rows walked in parallel per column
+            static_assert(CPS >= 1, "a thread per column");
+            if (tid < TN) {
+                const int cth = tid % NCOLN, r0 = tid / NCOLN;
+                if (r0 < CPS) {
+                    const int g = cth / CWN, s1 = 1 + cth - g * CWN;
+                    const FPlan& P = FS[g].p;
+                    const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
+                    const float scale = (float)P.etr * inv;
+                    const float kap1 = (6.283185307179586f / N1) * s1;
+                    float2* colp = cur + g * PITCH + s1;
+                    for (int s0 = r0; s0 < N0; s0 += CPS) {
+                        float a2, a1;
+                        rowk(s0, a2, a1);
+                        float2* x = colp + s0 * SPITCH;
+                        *x = f2scale(*x, mode_gain(P, cf, a2, a1, kap1 * kap1, kap1) * scale);
                     }
                 }
-                float2* x = cur + s0 * SPITCH + cth;
-                *x = f2scale(*x, g2 * scale);
+            } else {
+                // packed column Z = A + i B, A and B the column spectra of the real
+                // DC and Nyquist columns; their gains gd, gn are even in the row
+                // frequency (no cross term: the first-derivative symbol of both is
+                // zero), so Z'[k] = (gd + gn)/2 Z[k] + (gd - gn)/2 conj Z[N0 - k];
+                // one (filter, pair k <-> N0 - k) per lane
+                constexpr int PAIRS = N0 / 2 + 1;
+                const float kn = 3.14159265358979f;   // |kappa_1| at the Nyquist index
+                for (int e = tid - TN; e < G * PAIRS; e += 64) {
+                    const int g = e / PAIRS, s0 = e - g * PAIRS;
+                    const FPlan& P = FS[g].p;
+                    const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
+                    const float scale = (float)P.etr * inv;
+                    const int m = s0 == 0 ? 0 : N0 - s0;
+                    float a2, a1;
+                    rowk(s0, a2, a1);
+                    const float gd = mode_gain(P, cf, a2, a1, 0.f, 0.f);
+                    const float gn = mode_gain(P, cf, a2, a1, kn * kn, 0.f);
+                    const float pa = 0.5f * (gd + gn) * scale, pb = 0.5f * (gd - gn) * scale;
+                    float2* x = cur + s0 * SPITCH + g * PITCH;
+                    float2* y = cur + m * SPITCH + g * PITCH;
+                    const float2 zk = *x, zm = *y;
+                    *x = f2add(f2scale(zk, pa), f2scale(f2conj(zm), pb));
+                    if (m != s0) *y = f2add(f2scale(zm, pa), f2scale(f2conj(zk), pb));
+                }
+            }
+        } else {
+            // 1-D: a thread per spectral entry (filter g, frequency s1)
+            for (int cth = tid; cth < SPITCH; cth += NT) {
+                const int g = cth / PITCH, s1 = cth - g * PITCH;
+                const FPlan& P = FS[g].p;
+                const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
+                const int kk1 = (s1 < H1) ? s1 : s1 - N1;
+                const float kap1 = (6.283185307179586f / N1) * kk1;
+                const float a1 = (s1 == H1) ? 0.f : kap1;
+                float2* x = cur + cth;
+                *x = f2scale(*x, mode_gain(P, cf, kap1 * kap1, a1, 0.f, 0.f) * (float)P.etr * inv);
             }
         }
     }
     __syncthreads();
     // ---- inverse: columns, rows (c2r)
     if constexpr (NX == 2) {
-        cur = cfft<N0, SPITCH, 1, SPITCH, +1, true>(cur, oth, twc);
+        cur = cfft<N0, G * H1, 1, SPITCH, +1, true, H1>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
 #pragma unroll 1
     for (int e = tid; e < N0 * G * H1; e += NT) {
         const int L = e / H1, s = e - L * H1;
-        const float2 Xs = cur[L * PITCH + s];
-        const float2 Xc = f2conj(cur[L * PITCH + H1 - s]);
+        float2 Xs = cur[L * PITCH + s];
+        float2 Xc = f2conj(cur[L * PITCH + H1 - s]);
+        if (NX == 2 && s == 0) {
+            // packed entry 0: X_0 + i X_H1, both real
+            Xc = make_float2(Xs.y, 0.f);
+            Xs = make_float2(Xs.x, 0.f);
+        }
         const float2 Aa = f2add(Xs, Xc);
         const float2 Bb = f2mul(f2conj(twp[s]), f2sub(Xs, Xc));
         // Z_s = (X_s + conj X_{H1-s}) + i W^{-s} (X_s - conj X_{H1-s})
