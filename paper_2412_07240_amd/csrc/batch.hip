@@ -24,19 +24,26 @@ constexpr int FUSED_LMAX = 64;
 constexpr int PLAN_THREADS = 16;   // planning kernel workgroup
 
 constexpr int GMAX = 16;            // filters of one size packed into a workgroup
-constexpr int CPLX_BUDGET = 9400;   // complex LDS entries per buffer (2 buffers)
+// complex LDS entries per buffer (2 buffers): with the static LDS (10,160 B) and
+// the twiddle tables (3,088 B) the workgroup takes the whole 160 KiB
+constexpr int CPLX_BUDGET = 9412;
 
-// zero rows around a 2-D posterior in LDS (one above, one below, and the two
-// floats before the upper one, where the stencil of node (0, 0) reads its corner
-// tap): with the row pads they let every cubic stencil read its 4 x 4 taps
-// without bounds checks
-constexpr int guard_rows(int n0) { return n0 > 1 ? 2 : 0; }
+// Complex entries per row of a spectrum: N1/2 + 1 (2-D rows hold the real DC
+// and Nyquist entries packed into entry 0 and leave the last unused: the odd
+// stride keeps the row transforms free of LDS bank conflicts).
+constexpr int spec_pitch(int n1) { return n1 / 2 + 1; }
 
-// complex LDS entries of one buffer for a group of G filters of n0 rows of
-// `pitch` entries (the posterior's guard included)
-constexpr int group_cplx(int n0, int G, int pitch) {
-    return (n0 + guard_rows(n0)) * G * pitch + (n0 > 1 ? 1 : 0);
+// complex LDS entries of one buffer for a group of G filters: the spectra, or
+// the 2-D posterior, whichever is larger.  The posterior has super-rows of
+// n1 + 1 floats (the last a zero pad) after one zero float; with guard, a zero
+// super-row set above and below it as well (row -1 and row n0 of every filter)
+constexpr int group_cplx(int n0, int n1, int G, bool guard = false) {
+    const int spec = n0 * G * spec_pitch(n1);
+    const int post = n0 > 1 ? ((n0 + (guard ? 2 : 0)) * G * (n1 + 1) + 2) / 2 : 0;
+    return spec > post ? spec : post;
 }
+// guard rows when they fit the budget; otherwise the stencil clamps its rows
+constexpr bool group_guard(int n0, int n1, int G) { return n0 > 1 && group_cplx(n0, n1, G, true) <= CPLX_BUDGET; }
 
 struct FConst {
     KModel m;
@@ -835,7 +842,11 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     float2* twp = twc + 128;        // 130
     FState* FS = pmf_FS;
     double* slots = pmf_slots;
-    constexpr int H1 = N1 / 2, PITCH = H1 + 1, SPITCH = G * PITCH, RP = 2 * PITCH, RS = G * RP;
+    // spectra and the predicted density: super-row L = r G + g (row r of filter g)
+    // of PITCH complex = RP floats; the 2-D posterior: super-rows of RPO floats
+    constexpr int H1 = N1 / 2, PITCH = spec_pitch(N1), SPITCH = G * PITCH, RP = 2 * PITCH, RS = G * RP;
+    constexpr int RPO = NX == 2 ? N1 + 1 : RP, RSO = G * RPO;
+    constexpr bool GUARD = group_guard(N0, N1, G);
     constexpr int SEGW = pow2_ceil(N1) < 32 ? 32 : pow2_ceil(N1);
     constexpr int TPR = G * SEGW, RPS = FUSED_THREADS / TPR;
     constexpr int NT = FUSED_THREADS;
@@ -1026,11 +1037,13 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     for (int e = tid; e < N0 * G * H1; e += NT) {
         const int L = e / H1, s = e - L * H1;
         float2 Xs = cur[L * PITCH + s];
-        float2 Xc = f2conj(cur[L * PITCH + H1 - s]);
+        float2 Xc;
         if (NX == 2 && s == 0) {
             // packed entry 0: X_0 + i X_H1, both real
             Xc = make_float2(Xs.y, 0.f);
             Xs = make_float2(Xs.x, 0.f);
+        } else {
+            Xc = f2conj(cur[L * PITCH + H1 - s]);
         }
         const float2 Aa = f2add(Xs, Xc);
         const float2 Bb = f2mul(f2conj(twp[s]), f2sub(Xs, Xc));
@@ -1041,19 +1054,19 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     cur = cfft<H1, N0 * G, PITCH, 1, +1, true>(oth, cur, twr);
     oth = (cur == bufA) ? bufB : bufA;
     const float* Pr = reinterpret_cast<const float*>(cur);   // predicted: (r, g, j) at r*RS + g*RP + j
-    // posterior, same layout, starting one row and two floats into the buffer
-    // (2-D): row -1 with the two floats before it, row N0 and the two pad floats
-    // of every row are zeroed here (positions the likelihood pass does not write,
-    // so no barrier is needed)
-    constexpr int PO_OFF = NX == 2 ? RS + 2 : 0;
+    // posterior (2-D): super-rows of RPO = N1 + 1 floats after one float (and,
+    // with GUARD, after the super-row set of row -1); that float, the last float
+    // of every super-row and the guard rows -1 and N0 are zeroed here (positions
+    // the likelihood pass does not write, so no barrier is needed): a stencil tap
+    // one column left or right of a row, or one row above or below the grid,
+    // reads zero
+    constexpr int PO_OFF = NX == 2 ? (GUARD ? RSO + 1 : 1) : 0;
     float* Po = reinterpret_cast<float*>(oth) + PO_OFF;
     if constexpr (NX == 2) {
-        for (int e = tid; e < RS + 2; e += NT) Po[e - PO_OFF] = 0.f;
-        for (int e = tid; e < RS; e += NT) Po[N0 * RS + e] = 0.f;
-        for (int e = tid; e < N0 * G * 2; e += NT) {
-            const int rg = e >> 1;
-            Po[rg * RP + N1 + (e & 1)] = 0.f;
-        }
+        for (int e = tid; e < PO_OFF; e += NT) Po[e - PO_OFF] = 0.f;
+        if (GUARD)
+            for (int e = tid; e < RSO; e += NT) Po[N0 * RSO + e] = 0.f;
+        for (int e = tid; e < N0 * G; e += NT) Po[e * RPO + N1] = 0.f;
     }
 
     // ---- likelihood (FP64 Horner in u0 per thread), shift, multiply, FP64 sums
@@ -1112,8 +1125,8 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         const bool jedge = (j == 0 || j == N1 - 1);
         double u0 = u0first;
         const float* pr = Pr + tr * RS + g * RP + j;
-        float* po = Po + tr * RS + g * RP + j;
-        for (int r = tr; r < N0; r += RPS, u0 += du0, pr += RPS * RS, po += RPS * RS) {
+        float* po = Po + tr * RSO + g * RPO + j;
+        for (int r = tr; r < N0; r += RPS, u0 += du0, pr += RPS * RS, po += RPS * RSO) {
             const double L = Pg.fast ? qpoly(al, be, ga, u0) : floglik_general(mg, Pg, u0, NX == 2 ? uj : 0.0, zg);
             const float v = *pr * __expf((float)(L - sh));
             *po = v;
@@ -1125,8 +1138,8 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         }
         if (NX == 2 && !jedge) {
             // rows 0 and N0-1 are on the boundary too
-            if (tr == 0) acc[3] += (double)Po[g * RP + j];
-            if ((N0 - 1) % RPS == tr) acc[3] += (double)Po[(N0 - 1) * RS + g * RP + j];
+            if (tr == 0) acc[3] += (double)Po[g * RPO + j];
+            if ((N0 - 1) % RPS == tr) acc[3] += (double)Po[(N0 - 1) * RSO + g * RPO + j];
         }
     }
     // per-thread sums -> the seven moment sums (u1 is constant per thread in 2-D)
@@ -1159,7 +1172,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     if (act && FS[g].ok) {
         const FState& F = FS[g];
         gfloat* Pout = (gfloat*)F.pout;
-        const float* Pog = Po + g * RP;
+        const float* Pog = Po + g * RPO;
         const float inv_mass = (float)F.inv_mass;
         if constexpr (NX == 2) {
             // old index coordinates of new node (r, j), advanced by RPS rows per step
@@ -1175,12 +1188,17 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                     float w0[4], w1[4];
                     cubic_weights((float)(nu0 - i0), w0);
                     cubic_weights((float)(nu1 - i1), w1);
-                    // the 4 x 4 stencil at constant offsets from one base; taps outside
-                    // the grid read the zero guard rows and row pads
-                    const float* p = Pog + (i0 - 1) * RS + (i1 - 1);
+                    // taps outside the grid are zero: columns -1 and N1 read the zero
+                    // pad floats, rows -1 and N0 the zero guard rows (without GUARD
+                    // they get weight zero and read rows 0 and N0 - 1 instead)
+                    const float* q = Pog + i0 * RSO + (i1 - 1);
+                    const bool top = !GUARD && i0 == 0, bot = !GUARD && i0 == N0 - 2;
+                    if (top) w0[0] = 0.f;
+                    if (bot) w0[3] = 0.f;
+                    const float* rows[4] = {top ? q : q - RSO, q, q + RSO, bot ? q + RSO : q + 2 * RSO};
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
-                        const float* row = p + a * RS;
+                        const float* row = rows[a];
                         val += w0[a] * (w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3]);
                     }
                 }
@@ -1224,10 +1242,9 @@ enum {
 
 template <int N0, int N1>
 constexpr int group_g() {
-    constexpr int pitch = N1 / 2 + 1;
     constexpr int seg = pow2_ceil(N1) < 32 ? 32 : pow2_ceil(N1);
     int G = 1;
-    while (G < GMAX && group_cplx(N0, 2 * G, pitch) <= CPLX_BUDGET && (2 * G) * seg <= FUSED_THREADS) G *= 2;
+    while (G < GMAX && group_cplx(N0, N1, 2 * G) <= CPLX_BUDGET && (2 * G) * seg <= FUSED_THREADS) G *= 2;
     return G;
 }
 
@@ -1458,7 +1475,6 @@ static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sort
     int maxcplx = 0;
     for (int q = 0; q < n;) {
         const BItem& b = items[order[q]];
-        const int pitch = b.n1 / 2 + 1;
         const int type = group_type(b.nx, b.n0, b.n1);
         const int G = group_capacity(type);
         GItem gi;
@@ -1478,7 +1494,7 @@ static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sort
         }
         gi.G = cnt;
         groups.push_back(gi);
-        maxcplx = std::max(maxcplx, group_cplx(gi.n0, G, pitch));
+        maxcplx = std::max(maxcplx, group_cplx(gi.n0, gi.n1, G, group_guard(gi.n0, gi.n1, G)));
     }
     return maxcplx;
 }
