@@ -1169,17 +1169,18 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
 
     // ---- interpolation onto the new grid, straight to HBM (normalised lazily)
     double macc[1] = {0.0};
-    if (act && FS[g].ok) {
+    // rows shorter than their thread segment (N1 = 48, 96) are enumerated flat,
+    // point p = r N1 + j over all RPS x SEGW threads of the filter, so that no
+    // lane idles
+    constexpr bool FLAT = NX == 2 && N1 < SEGW;
+    if ((FLAT ? (tr < RPS && g < Gact) : act) && FS[g].ok) {
         const FState& F = FS[g];
         gfloat* Pout = (gfloat*)F.pout;
         const float* Pog = Po + g * RPO;
         const float inv_mass = (float)F.inv_mass;
         if constexpr (NX == 2) {
-            // old index coordinates of new node (r, j), advanced by RPS rows per step
-            double nu0 = F.amap[0] * ((double)tr - half0) + F.amap[1] * uj + F.bmap[0];
-            double nu1 = F.amap[2] * ((double)tr - half0) + F.amap[3] * uj + F.bmap[1];
-            const double dn0 = F.amap[0] * RPS, dn1 = F.amap[2] * RPS;
-            for (int r = tr; r < N0; r += RPS, nu0 += dn0, nu1 += dn1) {
+            // the cubic interpolant of the posterior at old index coordinates (nu0, nu1)
+            auto interp_at = [&](double nu0, double nu1) -> float {
                 float val = 0.f;
                 if (nu0 >= 0.0 && nu0 <= (double)(N0 - 1) && nu1 >= 0.0 && nu1 <= (double)(N1 - 1)) {
                     // stencil base at most N - 2: on the last node the weights are
@@ -1202,9 +1203,28 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                         val += w0[a] * (w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3]);
                     }
                 }
-                val *= inv_mass;
-                Pout[r * N1 + j] = val;
-                macc[0] += (double)val;
+                return val;
+            };
+            if constexpr (FLAT) {
+                constexpr int STEP = RPS * SEGW;
+                for (int p = tr * SEGW + j; p < N0 * N1; p += STEP) {
+                    const int r = p / N1, c = p - r * N1;
+                    const double u0 = (double)r - half0, u1 = (double)c - half1;
+                    const float val = interp_at(F.amap[0] * u0 + F.amap[1] * u1 + F.bmap[0],
+                                                F.amap[2] * u0 + F.amap[3] * u1 + F.bmap[1]) * inv_mass;
+                    Pout[p] = val;
+                    macc[0] += (double)val;
+                }
+            } else {
+                // old index coordinates of new node (r, j), advanced by RPS rows per step
+                double nu0 = F.amap[0] * ((double)tr - half0) + F.amap[1] * uj + F.bmap[0];
+                double nu1 = F.amap[2] * ((double)tr - half0) + F.amap[3] * uj + F.bmap[1];
+                const double dn0 = F.amap[0] * RPS, dn1 = F.amap[2] * RPS;
+                for (int r = tr; r < N0; r += RPS, nu0 += dn0, nu1 += dn1) {
+                    const float val = interp_at(nu0, nu1) * inv_mass;
+                    Pout[r * N1 + j] = val;
+                    macc[0] += (double)val;
+                }
             }
         } else {
             const double nu = F.amap[0] * uj + F.bmap[0];
