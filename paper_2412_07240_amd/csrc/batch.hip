@@ -173,6 +173,33 @@ __device__ inline void fdft16(float2* a, int s) {
     }
 }
 
+// 12 = 3 x 4: radix-3 transforms of the stride-4 subsequences, twiddles
+// W12^(n2 k1), radix-4 transforms across them (x[n2 + 4 n1] -> X[k1 + 3 k2])
+__device__ inline void fdft12(float2* a, int s) {
+    float2 y[4][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        float2 t[3] = {a[n2], a[n2 + 4], a[n2 + 8]};
+        fdft3(t, s);
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) y[n2][k1] = t[k1];
+    }
+    const float c = 0.86602540378443864676f;   // cos 30 degrees
+    y[1][1] = f2mul(y[1][1], make_float2(c, s * 0.5f));
+    y[1][2] = f2mul(y[1][2], make_float2(0.5f, s * c));
+    y[2][1] = f2mul(y[2][1], make_float2(0.5f, s * c));
+    y[2][2] = f2mul(y[2][2], make_float2(-0.5f, s * c));
+    y[3][1] = f2si(y[3][1], s);
+    y[3][2] = make_float2(-y[3][2].x, -y[3][2].y);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        float2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        fdft4(t, s);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 3 * k2] = t[k2];
+    }
+}
+
 
 // ---------------------------------------------------------------- segmented reductions
 // Threads map onto points as (tr, g, j): TPR = G * seg threads per "super-row",
@@ -509,6 +536,16 @@ constexpr int radix_at(int n, int i) {
     }
     if (e == 2) r[k++] = 4;
     if (e == 1) r[k++] = 2;
+    // a trailing 4 and a factor 3 merge into one radix-12 pass (96 = 8 x 12);
+    // with 8s only, a pair 8 x 8 becomes 16 x 4 first (192 = 16 x 12)
+    if (n % 3 == 0 && k >= 2 && r[k - 1] == 8 && r[k - 2] == 8) {
+        r[k - 2] = 16;
+        r[k - 1] = 4;
+    }
+    if (n % 3 == 0 && k >= 1 && r[k - 1] == 4) {
+        r[k - 1] = 12;
+        n /= 3;
+    }
     while (n % 3 == 0) {
         r[k++] = 3;
         n /= 3;
@@ -528,6 +565,7 @@ constexpr int pow2_ceil(int v) {
 
 template <int R> __device__ inline void fdft(float2* v, int sign) {
     if constexpr (R == 16) fdft16(v, sign);
+    if constexpr (R == 12) fdft12(v, sign);
     if constexpr (R == 2) fdft2(v);
     if constexpr (R == 3) fdft3(v, sign);
     if constexpr (R == 4) fdft4(v, sign);
