@@ -557,6 +557,11 @@ constexpr int num_passes(int n) {
     while (radix_at(n, k) != 0) ++k;
     return k;
 }
+constexpr int plan_product(int n) {
+    int p = 1;
+    for (int k = 0; radix_at(n, k) != 0; ++k) p *= radix_at(n, k);
+    return p;
+}
 constexpr int pow2_ceil(int v) {
     int p = 1;
     while (p < v) p <<= 1;
@@ -619,6 +624,7 @@ __device__ inline void cpass(const float2* __restrict__ in, float2* __restrict__
 template <int N, int NL, int LS, int ES, int SIGN, bool LF, int GAP = 0, int P = 0, int NS = 1>
 __device__ inline float2* cfft(float2* in, float2* out, const float2* tw) {
     static_assert(GAP == 0 || LS == 1, "gapped lines are unit-stride");
+    static_assert(plan_product(N) == N, "the radix plan multiplies out to the transform length");
     if constexpr (P == num_passes(N)) {
         return in;
     } else {
