@@ -70,11 +70,12 @@ struct GItem {
 struct FPlan {
     double c[2], M[4], Mi[4], vol;   // grid after the move (2x2 row-major)
     double gc[3];                    // exact integrator: W_y packed 00, 11, 01
-    double h, etr, T;
+    double h, etr, tnew;             // substep, e^{-tr A T}, the filter's time after the step
     double q0, qb[2], qQ[3];         // linear-Gaussian log l = q0 + qb.u - 1/2 u^T Q u
     double Wnom[2], span;
     double pscale;                   // pending scale of the stored density
-    int l, bad, fast, integ, interp, nx, par, pad;
+    int l, bad, fast, integ, interp, nx, par;
+    int status;                      // the descriptor's status word before the step
 };
 
 // per-filter working state in LDS
@@ -279,8 +280,8 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ zs, int nzma
             Phi[i * MS + j] = a.Phi[i * MS + j];
             W[i * MS + j] = a.W[i * MS + j];
         }
-    const int par = d.par;
-    const double pscale = d.pscale;
+    const int par = d.par, status0 = d.status;
+    const double pscale = d.pscale, t0 = d.t;
     const int integ = a.integ, lmin = a.lmin;
     const double T = a.T, etr = a.etr;
     const double Wn0 = m.Wnom[0], Wn1 = m.Wnom[MS + 1], span = m.span;
@@ -329,7 +330,8 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ zs, int nzma
     P.l = l;
     P.h = T / l;
     P.etr = etr;
-    P.T = T;
+    P.tnew = t0 + T;
+    P.status = status0;
     // grid follows x' = A x
     double c2[MS], M2[MSQ];
     mat_zero(M2);
@@ -777,7 +779,9 @@ __device__ void filter_design(FState& F, const double* acc, int NX, int n0, int 
     }
 }
 
-// thread 0..G-1: write back descriptor and log-likelihood of filter tid
+// thread 0..G-1: write back descriptor and log-likelihood of filter tid (stores
+// only: the time and status word come with the plan)
+template <int NX>
 __device__ void filter_commit(const FState& F, double* ll_out) {
     const FPlan& P = F.p;
     DevDesc* d = F.d;
@@ -786,20 +790,20 @@ __device__ void filter_commit(const FState& F, double* ll_out) {
     for (int q = 0; q < MS; ++q) gg.c[q] = 0.0;
     if (F.ok) {
         gg.c[0] = F.gnc[0];
-        gg.c[1] = P.nx == 2 ? F.gnc[1] : 0.0;
+        gg.c[1] = NX == 2 ? F.gnc[1] : 0.0;
         gg.M[0] = F.gnM[0];
-        if (P.nx == 2) gg.M[MS + 1] = F.gnM[3];
+        if (NX == 2) gg.M[MS + 1] = F.gnM[3];
     } else {
         gg.c[0] = P.c[0];
         gg.c[1] = P.c[1];
         gg.M[0] = P.M[0];
-        if (P.nx == 2) {
+        if (NX == 2) {
             gg.M[1] = P.M[1];
             gg.M[MS] = P.M[2];
             gg.M[MS + 1] = P.M[3];
         }
     }
-    grid_finish(gg, P.nx);
+    grid_finish(gg, NX);
     // the batched grid is at most 2 x 2: only that block of the descriptor
     // changes (the rest is zero since the filter was created)
     d->g.c[0] = gg.c[0];
@@ -813,19 +817,19 @@ __device__ void filter_commit(const FState& F, double* ll_out) {
     d->g.Mi[MS] = gg.Mi[MS];
     d->g.Mi[MS + 1] = gg.Mi[MS + 1];
     d->g.vol = gg.vol;
-    d->t += P.T;
+    d->t = P.tnew;
     d->l = P.l;
     d->h = P.h;
     d->etr = P.etr;
     d->par = 1 - P.par;
     if (F.ok) {
         d->loglik = F.loglik;
-        d->status |= F.bits;
+        d->status = P.status | F.bits;
         d->pscale = F.pscale2;
         ll_out[F.idx] = F.loglik;
     } else {
         d->loglik = NAN;
-        d->status |= PMF_E_DEGENERATE | F.bits | (P.bad ? PMF_E_INVALID : 0);
+        d->status = P.status | PMF_E_DEGENERATE | F.bits | (P.bad ? PMF_E_INVALID : 0);
         d->pscale = 1.0;
         ll_out[F.idx] = NAN;
     }
@@ -1294,7 +1298,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         gfloat* Pout = (gfloat*)FS[g].pout;
         for (int r = tr; r < N0; r += RPS) Pout[r * N1 + j] = Pr[r * RS + g * RP + j];
     }
-    if (tid < Gact) filter_commit(FS[tid], ll_out);
+    if (tid < Gact) filter_commit<NX>(FS[tid], ll_out);
     __syncthreads();
 }
 

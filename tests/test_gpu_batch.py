@@ -48,6 +48,7 @@ def check_against_oracle(B, fs, scs, before, lls, what):
         st, _ = oracle.predict(sc.model, st, sc.T)
         st, ll_o, status, _, _ = oracle.update(sc.model, st, sc.z[k_of(what)])
         _, c2, M2, t2, P2 = B.pmf_get_state(f)
+        assert abs(t2 - st.t) <= 1e-12 * max(1.0, abs(st.t)), f"{what} filter {i}: time {t2} vs {st.t}"
         np.testing.assert_allclose(M2, st.M, rtol=1e-4, atol=0, err_msg=f"{what} filter {i}")
         np.testing.assert_allclose(c2, st.c, atol=1e-4 * np.abs(st.M).max() * 100, err_msg=f"{what} filter {i}")
         err = l1_vs_oracle(sc.model, c2, M2, P2, st)
