@@ -77,7 +77,7 @@ hipError_t batch_leave(pmf_filter* f);
 bool batch_fusable(const pmf_filter* f, std::string* why);
 
 // fused steps over a changing set of filters (served batches, batch.hip): the
-// items are rebuilt on every call, no graph.  Asynchronous on st; the host
+// items are rebuilt on every call (nothing cached).  Asynchronous on st; the host
 // staging is reused by the next call, so the caller waits for st in between.
 DynBatch* dyn_create(pmf_ctx* ctx);
 void dyn_destroy(pmf_ctx* ctx, DynBatch* db);

@@ -1,4 +1,4 @@
-"""The fused batched step (one persistent launch per step, recorded as a HIP graph)
+"""The fused batched step (a planning kernel and one persistent launch per step)
 against the FP64 oracle and against the generic path.
 
 Bar (FP32 densities): L1 <= 1e-5 per filter per step vs the oracle started from
@@ -139,7 +139,7 @@ def test_batch_full_size_sampled(B, ctx):
     if big not in sample:
         sample[0] = big
     try:
-        B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, 0))          # warm: graph built
+        B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, 0))          # warm: launch set-up cached
         before = [B.pmf_get_state(fs[i])[1:] for i in sample]
         lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, 1), want_loglik=True)
         assert np.all(np.isfinite(lls))
