@@ -152,11 +152,13 @@ def test_batch_full_size_sampled(B, ctx):
             B.pmf_destroy(f)
 
 
-def _corner_state(sc, k):
+def _corner_state(sc, k, far=False):
     """A state whose next regrid reads the old grid's corner: the old grid is the
     new one (as the oracle designs it) moved back by e^{-AT} and shifted by half a
     cell along both index axes, so new node (0, 0) sits at old index (1/2, 1/2)
-    and its cubic stencil takes taps from row -1 and column -1."""
+    and its cubic stencil takes taps from row -1 and column -1 (far: shifted the
+    other way, new node (N-1, N-1) at old index (N-3/2, N-3/2), taps from row N
+    and column N)."""
     import scipy.linalg
     import scipy.stats
     m = sc.model
@@ -166,7 +168,7 @@ def _corner_state(sc, k):
         s1, _ = oracle.predict(m, st, sc.T)
         s2, *_ = oracle.update(m, s1, sc.z[k])
         M0 = Phi_inv @ s2.M
-        c0 = Phi_inv @ (s2.c - 0.5 * s2.M @ np.ones(2))
+        c0 = Phi_inv @ (s2.c + (0.5 if far else -0.5) * s2.M @ np.ones(2))
         X = oracle.nodes(m, c0, M0)
         P = sum(w * scipy.stats.multivariate_normal(mu, C).pdf(X)
                 for w, mu, C in zip(sc.prior.w, sc.prior.mean, sc.prior.cov))
@@ -175,23 +177,28 @@ def _corner_state(sc, k):
     s1, _ = oracle.predict(m, st, sc.T)
     s2, *_ = oracle.update(m, s1, sc.z[k])
     N = np.asarray(m.N)
-    x00 = s2.c + s2.M @ (-(N // 2)).astype(float)
-    nu = np.linalg.solve(s1.M, x00 - s1.c) + N // 2
-    assert np.all(nu > 0.05) and np.all(nu < 0.95), nu
+    j = (N - 1) if far else np.zeros(2, int)
+    x = s2.c + s2.M @ (j - N // 2).astype(float)
+    nu = np.linalg.solve(s1.M, x - s1.c) + N // 2
+    lo = (N - 2) if far else np.zeros(2)
+    assert np.all(nu > lo + 0.05) and np.all(nu < lo + 0.95), nu
     return st
 
 
-def test_batch_regrid_reads_corner_taps(B, ctx):
-    """Regression: the stencil of new node (0, 0) reads old row -1 and column -1,
-    which must be zero guard positions in LDS (not whatever the memory held)."""
+@pytest.mark.parametrize("far", [False, True], ids=["near", "far"])
+def test_batch_regrid_reads_corner_taps(B, ctx, far):
+    """Regression: the stencil of new node (0, 0) reads old row -1 and column -1
+    (far corner: node (N-1, N-1), old row N and column N), which must read as zero
+    (guard rows, row pads, or clamped rows of weight zero; not whatever the memory
+    held)."""
     scs = W.batched_workload(20, K=1)
-    note(f"case: 20 filters set up so that node (0, 0) regrids from the old grid's corner cell, "
-         f"sizes {sorted(set(sc.model.N[0] for sc in scs))}")
+    note(f"case: 20 filters set up so that a corner node regrids from the old grid's "
+         f"{'far' if far else 'near'} corner cell, sizes {sorted(set(sc.model.N[0] for sc in scs))}")
     fs = make(B, ctx, scs)
     try:
         before = []
         for f, sc in zip(fs, scs):
-            st = _corner_state(sc, 0)
+            st = _corner_state(sc, 0, far)
             B.pmf_set_state(f, st.c, st.M, st.t, st.P, sc.model.grid, sc.model.precision)
             before.append(B.pmf_get_state(f)[1:])
         lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, 0), want_loglik=True)
