@@ -1573,9 +1573,19 @@ static size_t fused_lds(int maxcplx) {
     return 2 * (size_t)maxcplx * sizeof(float2) + (128 + 128 + 130) * sizeof(float2);
 }
 
-static hipError_t fused_lds_attribute() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_fused), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)fused_lds(CPLX_BUDGET));
+// The buffer budget takes the whole 160 KiB of a gfx950 compute unit together with
+// the kernel's static LDS: checked here, so that a change to the static LDS fails
+// with this message rather than as a launch error.
+static pmf_status fused_lds_attribute() {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_fused));
+    if (e != hipSuccess) return hip_fail(e, "fused kernel attributes");
+    if (fa.sharedSizeBytes + fused_lds(CPLX_BUDGET) > (size_t)160 * 1024)
+        return fail(PMF_E_DEVICE, "fused kernel: static LDS plus the buffer budget exceed 160 KiB");
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_fused), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fused_lds(CPLX_BUDGET));
+    if (e != hipSuccess) return hip_fail(e, "fused kernel LDS attribute");
+    return PMF_OK;
 }
 
 static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, hipStream_t st) {
@@ -1638,8 +1648,8 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     if (e != hipSuccess) return hip_fail(e, "batch setup");
     c->bufcplx = maxcplx;
     c->lds = fused_lds(maxcplx);
-    e = fused_lds_attribute();
-    if (e != hipSuccess) return hip_fail(e, "fused kernel LDS attribute");
+    pmf_status ls = fused_lds_attribute();
+    if (ls != PMF_OK) return ls;
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, FUSED_THREADS, c->lds);
     if (e != hipSuccess) return hip_fail(e, "occupancy");
@@ -1749,9 +1759,10 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
     if (s != PMF_OK) return s;
     hipError_t e = hipSuccess;
     if (!db->attr) {
-        e = fused_lds_attribute();
+        const pmf_status ls = fused_lds_attribute();
+        if (ls != PMF_OK) return ls;
         hipDeviceProp_t prop;
-        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, ctx->device);
+        e = hipGetDeviceProperties(&prop, ctx->device);
         if (e != hipSuccess) return hip_fail(e, "fused kernel set-up");
         db->ncu = prop.multiProcessorCount;
         db->attr = true;
