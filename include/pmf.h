@@ -206,9 +206,10 @@ pmf_status pmf_get_state(pmf_filter* f, void* host_buf, size_t* bytes);
  * with the same nx, grid kind, N and precision.  Synchronous. */
 pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
 
-/* One predict(T) + update(z) cycle for n filters in one fused launch (Fourier
- * grids, FP32, nx <= 2, N_a <= 128 per axis for nx = 2, N <= 256 for nx = 1;
- * other filters are rejected with PMF_E_INVALID before anything runs).
+/* One predict(T) + update(z) cycle for n >= 1 filters in one fused launch
+ * (Fourier grids, FP32, nx <= 2, N_a <= 128 per axis for nx = 2, N <= 256 for
+ * nx = 1; other filters, n < 1 and NULL arguments are rejected with
+ * PMF_E_INVALID before anything runs).
  * z: n * nz_max doubles, row f holds filter f's measurement (nz_max = largest nz);
  * copied into pinned staging before the call returns (the caller may reuse it).
  * loglik: NULL or n doubles written by an asynchronous copy (as pmf_update).

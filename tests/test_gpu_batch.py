@@ -85,9 +85,10 @@ def test_batch_lockstep_mixed_sizes(B, ctx):
             B.pmf_destroy(f)
 
 
-def test_batch_matches_generic_fp32_path(B, ctx):
-    scs = W.batched_workload(12, K=5)
-    note("case: batch vs separate predict+update calls, 12 filters, 5 steps")
+@pytest.mark.parametrize("nf", [12, 1])
+def test_batch_matches_generic_fp32_path(B, ctx, nf):
+    scs = W.batched_workload(nf, K=5)
+    note(f"case: batch vs separate predict+update calls, {nf} filter(s), 5 steps")
     fa = make(B, ctx, scs)
     fb = make(B, ctx, scs)
     try:
@@ -313,6 +314,11 @@ def test_batch_rejects_bad_calls(B, ctx):
             with pytest.raises(B.PmfError) as e:
                 B.pmf_batch_step(ctx, *args)
             assert e.value.status == B.PMF_E_INVALID
+        # an empty batch (through the C call: the binding needs a z row per filter)
+        zz = np.zeros(2)
+        st = B.lib().pmf_batch_step(ctx, (B.C.c_void_p * 1)(), 0, 0.05,
+                                    zz.ctypes.data_as(B.C.POINTER(B.C.c_double)), None, None)
+        assert st == B.PMF_E_INVALID
         # the filters are untouched and still step normally
         lls = B.pmf_batch_step(ctx, fs, 0.05, zmat(scs, 0), want_loglik=True)
         assert np.all(np.isfinite(lls))
