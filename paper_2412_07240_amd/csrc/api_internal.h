@@ -15,6 +15,7 @@ struct pmf_ctx {
     bool has_alloc = false;
     pmf_allocator alloc{};
     BatchCache* batch = nullptr;
+    long long batch_leaves = 0;                 // filters that left batched steps so far
     bool profile = false;                       // record events around batched launches
     std::vector<hipEvent_t> ev_pool;             // start/stop pairs, reused
     int ev_used = 0;

@@ -1432,6 +1432,7 @@ struct BatchCache {
     size_t lds = 0;
     int grid = 0, bufcplx = 0;
     std::vector<int> order;                   // filter index of each item
+    long long leaves_seen = -1;               // pmf_ctx::batch_leaves when all filters last entered
 };
 
 namespace pmf {
@@ -1482,6 +1483,7 @@ hipError_t batch_leave(pmf_filter* f) {
     if (e != hipSuccess) return e;
     f->cur = par;
     f->in_batch = false;
+    ++f->ctx->batch_leaves;
     return hipSuccess;
 }
 
@@ -1839,56 +1841,68 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
     using namespace pmf;
     if (!ctx || n < 1 || !filters || !z) return fail(PMF_E_INVALID, "NULL argument or n < 1");
     if (!std::isfinite(T) || !(T > 0.0)) return fail(PMF_E_INVALID, "T must be finite and > 0");
-    int nzmax = 1;
-    for (int i = 0; i < n; ++i) {
-        if (!filters[i] || filters[i]->ctx != ctx) return fail(PMF_E_INVALID, "filter of another context");
-        std::string why;
-        if (!batch_fusable(filters[i], &why)) return fail(PMF_E_INVALID, "filter not fusable: " + why);
-        nzmax = std::max(nzmax, filters[i]->model.nz);
-    }
-    for (int i = 0; i < n * nzmax; ++i)
-        if (!std::isfinite(z[i])) return fail(PMF_E_INVALID, "non-finite measurement");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const hipStream_t st = static_cast<hipStream_t>(stream);
     BatchCache* c = ctx->batch;
-    bool same = c && c->n == n && c->T == T && c->stream == st;
-    if (same)
-        for (int i = 0; i < n; ++i)
-            if (c->filters[i] != filters[i]) {
-                same = false;
-                break;
-            }
-    if (!same) {
-        // a filter listed twice would be stepped twice in one launch, racing with itself
-        std::vector<pmf_filter*> sorted(filters, filters + n);
-        std::sort(sorted.begin(), sorted.end());
-        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-            return fail(PMF_E_INVALID, "filter listed twice");
-    }
-    for (int i = 0; i < n; ++i) {
-        e = batch_enter(filters[i]);
-        if (e != hipSuccess) return hip_fail(e, "batch enter");
-    }
-    if (!same) {
-        pmf_status s = build_cache(ctx, filters, n, T, st);
-        if (s != PMF_OK) {
-            batch_cache_release(ctx);
-            return s;
+    const bool same = c && c->n == n && c->T == T && c->stream == st &&
+                      std::equal(filters, filters + n, c->filters.begin());
+    if (!same || c->leaves_seen != ctx->batch_leaves) {
+        // a new filter set, or a filter of it took other calls since the last step:
+        // validate, (re-)enter the batched layout, build the launch set-up.  An
+        // unchanged set skips all of this (its filters were checked when it was built)
+        int nzmax = 1;
+        for (int i = 0; i < n; ++i) {
+            if (!filters[i] || filters[i]->ctx != ctx) return fail(PMF_E_INVALID, "filter of another context");
+            std::string why;
+            if (!batch_fusable(filters[i], &why)) return fail(PMF_E_INVALID, "filter not fusable: " + why);
+            nzmax = std::max(nzmax, filters[i]->model.nz);
         }
-        c = ctx->batch;
+        for (int i = 0; i < n * nzmax; ++i)
+            if (!std::isfinite(z[i])) return fail(PMF_E_INVALID, "non-finite measurement");
+        if (!same) {
+            // a filter listed twice would be stepped twice in one launch, racing with itself
+            std::vector<pmf_filter*> sorted(filters, filters + n);
+            std::sort(sorted.begin(), sorted.end());
+            if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+                return fail(PMF_E_INVALID, "filter listed twice");
+        }
+        for (int i = 0; i < n; ++i) {
+            e = batch_enter(filters[i]);
+            if (e != hipSuccess) return hip_fail(e, "batch enter");
+        }
+        if (!same) {
+            pmf_status s = build_cache(ctx, filters, n, T, st);
+            if (s != PMF_OK) {
+                batch_cache_release(ctx);
+                return s;
+            }
+            c = ctx->batch;
+        }
+        c->leaves_seen = ctx->batch_leaves;
     }
-    // stage z in mapped pinned memory; the planning kernel reads it there, no
-    // separate copy.  The event of the group of steps before the previous one
-    // (never recorded before step 2 ZEVERY: the first slots are fresh).
-    const long long k = c->step++;
+    const int nzmax = c->nzmax;
+    // stage z in mapped pinned memory, rows in item order, checking it on the way;
+    // the planning kernel reads it there, no separate copy.  First the event of
+    // the group of steps before the previous one (never recorded before step
+    // 2 ZEVERY: the first slots are fresh).
+    const long long k = c->step;
     const int slot = (int)(k % BatchCache::ZSLOTS);
     const int evi = (int)((k / BatchCache::ZEVERY) & 1);
     e = hipEventSynchronize(c->ev[evi]);
     if (e != hipSuccess) return hip_fail(e, "staging wait");
-    // rows in item order
-    for (int q = 0; q < n; ++q)
-        std::memcpy(c->h_z[slot] + (size_t)q * nzmax, z + (size_t)c->order[q] * nzmax, sizeof(double) * nzmax);
+    bool finite = true;
+    double* dst = c->h_z[slot];
+    for (int q = 0; q < n; ++q) {
+        const double* src = z + (size_t)c->order[q] * nzmax;
+        for (int j = 0; j < nzmax; ++j) {
+            const double v = src[j];
+            finite = finite && std::isfinite(v);
+            dst[(size_t)q * nzmax + j] = v;
+        }
+    }
+    if (!finite) return fail(PMF_E_INVALID, "non-finite measurement");
+    c->step = k + 1;
     if (ctx->profile) {
         // the same launches with events around the fused kernel
         if ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {

@@ -322,6 +322,13 @@ def test_batch_rejects_bad_calls(B, ctx):
         # the filters are untouched and still step normally
         lls = B.pmf_batch_step(ctx, fs, 0.05, zmat(scs, 0), want_loglik=True)
         assert np.all(np.isfinite(lls))
+        # the same set again (the cached path) with a non-finite z: refused, and the
+        # next step runs normally
+        with pytest.raises(B.PmfError) as e:
+            B.pmf_batch_step(ctx, fs, 0.05, np.full((3, 2), np.inf))
+        assert e.value.status == B.PMF_E_INVALID
+        lls = B.pmf_batch_step(ctx, fs, 0.05, zmat(scs, 0), want_loglik=True)
+        assert np.all(np.isfinite(lls))
     finally:
         for f in fs:
             B.pmf_destroy(f)
