@@ -370,6 +370,30 @@ def _lagrange_weights(t: np.ndarray, pts: np.ndarray) -> np.ndarray:
     return out
 
 
+def lagrange_stencil(model, a: int, ua: np.ndarray):
+    """The four taps of the cubic Lagrange stencil along axis a at old
+    computational coordinates ua: two nodes on either side of ua, shifted inwards
+    at the ends of the node set.  Returns (density index of each tap, clipped to
+    the grid; abscissa of each tap; whether the tap is a grid node, a tap beyond
+    or on the grid's end being a zero value; whether ua lies in the grid).
+    Fourier: the nodes are the indices 0..N-1 and the taps -1 and N are zero.
+    Chebyshev: the nodes are the N + 2 Chebyshev-Gauss-Lobatto points, whose two
+    end points +-1 carry the zero boundary values."""
+    n = model.N[a]
+    if model.grid == FOURIER:
+        inside = (ua >= 0.0) & (ua <= n - 1)
+        i0 = np.floor(np.clip(ua, 0.0, n - 1)).astype(int)
+        idx = i0[:, None] + np.arange(-1, 3)[None, :]
+        return np.clip(idx, 0, n - 1), idx.astype(float), (idx >= 0) & (idx <= n - 1), inside
+    inside = np.abs(ua) <= 1.0
+    v = cheb.cgl_nodes(n)                                    # n + 2 nodes
+    nn = n + 1
+    k0 = np.clip(np.searchsorted(v, ua, side="right") - 1, 0, nn - 1)
+    ks = np.clip(k0 - 1, 0, nn - 3)
+    kidx = ks[:, None] + np.arange(4)[None, :]
+    return np.clip(kidx - 1, 0, n - 1), v[kidx], (kidx >= 1) & (kidx <= n), inside
+
+
 def _separable(M: np.ndarray) -> bool:
     return bool(np.all(M[~np.eye(M.shape[0], dtype=bool)] == 0.0))
 
@@ -407,28 +431,11 @@ def interpolate(model, state: State, c_new: np.ndarray, M_new: np.ndarray) -> np
     inside = np.ones(npts, bool)
     taps_idx, taps_w = [], []
     for a in range(nx):
-        n = model.N[a]
         ua = flatU[:, a]
-        if model.grid == FOURIER:
-            inside &= (ua >= 0.0) & (ua <= n - 1)
-            i0 = np.floor(np.clip(ua, 0.0, n - 1)).astype(int)
-            idx = i0[:, None] + np.arange(-1, 3)[None, :]          # index stencil
-            pts = idx.astype(float)
-            w = _lagrange_weights(ua, pts)
-            valid = (idx >= 0) & (idx <= n - 1)
-            arr_idx = np.clip(idx, 0, n - 1)
-        else:
-            inside &= np.abs(ua) <= 1.0
-            v = cheb.cgl_nodes(n)                                    # n + 2 nodes
-            nn = n + 1
-            k0 = np.clip(np.searchsorted(v, ua, side="right") - 1, 0, nn - 1)
-            ks = np.clip(k0 - 1, 0, nn - 3)
-            kidx = ks[:, None] + np.arange(4)[None, :]
-            w = _lagrange_weights(ua, v[kidx])
-            valid = (kidx >= 1) & (kidx <= n)                       # ends are zero
-            arr_idx = np.clip(kidx - 1, 0, n - 1)
+        arr_idx, pts, valid, ins = lagrange_stencil(model, a, ua)
+        inside &= ins
         taps_idx.append(arr_idx)
-        taps_w.append(np.where(valid, w, 0.0))
+        taps_w.append(np.where(valid, _lagrange_weights(ua, pts), 0.0))
     out = np.zeros(npts)
     for combo in np.ndindex(*([4] * nx)):
         wt = np.ones(npts)

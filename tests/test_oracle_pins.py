@@ -3,8 +3,8 @@
 None of these compares the oracle with itself: each checks a library routine,
 a closed form (Kalman-Bucy prediction, Kalman update, heat kernel, W(T) for a
 scalar and a nilpotent A), an exactness property (band-limited trigonometric
-data, polynomials), an invariant (mass conservation) or the paper's own 1-D/
-diagonal algorithm written out separately.
+data, polynomials), an invariant (mass conservation) or the per-mode
+implicit diffusion step of Sec. V.A for single Fourier modes.
 """
 import math
 
@@ -198,39 +198,50 @@ def test_mass_is_conserved_on_the_moving_grid(integ):
     assert abs(mass1 - mass0) < 1e-13 * mass0
 
 
-def _paper_algorithm_1d_or_diag(P, deltas, A_diag, D_diag, T, l):
-    """The paper's Algorithm (Sec. V.B) for diagonal A and Q, written out from its
-    steps: FFT per dimension; c'' from fftshift(-N/2 : N/2-1) and the current grid
-    size L; Psi = product of psi over l Euler substeps with the grid size of each
-    substep; multiply; inverse FFT; normalise."""
-    shape = P.shape
-    S = np.fft.fftn(P)
-    Psi = np.ones(shape)
-    L = np.array([n * d for n, d in zip(shape, deltas)])
-    dt = T / l
-    for n in range(l):
-        denom = np.ones(shape)
-        for a, N in enumerate(shape):
-            c2 = -(2 * np.pi / L[a] * np.fft.fftshift(np.arange(-N // 2, N // 2))) ** 2
-            sh = [1] * len(shape)
-            sh[a] = N
-            denom = denom - 0.5 * c2.reshape(sh) * D_diag[a] * dt
-        Psi = Psi / denom
-        L = L * np.exp(np.asarray(A_diag) * dt)             # grid moves with x' = A x
-    out = np.fft.ifftn(S * Psi).real
-    return out / out.sum()
+def _euler_mode_gain(kappa2, deltas, A_diag, D_diag, T, l, factors=None):
+    """Implicit diffusion step of Sec. V.A for one Fourier mode of an axis-aligned
+    grid with diagonal A and D: the step at t_n divides the mode by
+    1 + h/2 sum_a D_aa kappa_a^2 / delta_a(t_n)^2, where the grid step moves as
+    delta_a(t) = delta_a e^{A_aa t} (x' = A x); l factors at t_n = n h."""
+    h = T / l
+    g = 1.0
+    for n in range(l if factors is None else factors):
+        sig = sum(D_diag[a] * kappa2[a] / (deltas[a] * math.exp(A_diag[a] * n * h)) ** 2
+                  for a in range(len(deltas)))
+        g /= 1.0 + 0.5 * h * sig
+    return g
 
 
-def test_oracle_euler_reduces_to_papers_algorithm():
+def _euler_case(l=7, factors=None):
     A = np.diag([-0.4, -0.9])
     D = np.diag([0.3, 0.6])
-    m = _gauss_model(2, A, D, (32, 48), W.INT_EULER, substeps=7, T=0.4, span=6.0)
-    rng = np.random.default_rng(11)
-    st = oracle.create(m, W.PriorSpec(np.array([0.5, 0.5]), rng.standard_normal((2, 2)),
-                                      np.array([np.eye(2) * 0.4, np.diag([0.6, 0.2])])))
-    st1, _ = oracle.predict(m, st, 0.4)
-    want = _paper_algorithm_1d_or_diag(st.P, np.diag(st.M), np.diag(A), np.diag(D), 0.4, 7)
-    np.testing.assert_allclose(st1.P / st1.P.sum(), want, atol=1e-15, rtol=1e-11)
+    N = (32, 48)
+    m = _gauss_model(2, A, D, N, W.INT_EULER, substeps=l, T=0.4, span=6.0)
+    st = oracle.create(m, W.gaussian_prior([0.5, -0.5], np.diag([0.4, 0.3])))
+    j0, j1 = np.meshgrid(np.arange(N[0]), np.arange(N[1]), indexing="ij")
+    k0, k1 = 2 * np.pi * 3 / N[0], 2 * np.pi * 5 / N[1]
+    # the mean, one oblique mode and the Nyquist mode of axis 0 (symbol pi^2 kept)
+    st.P = 1.0 + 0.3 * np.cos(k0 * j0 + 0.4) * np.cos(k1 * j1) + 0.1 * np.cos(np.pi * j0)
+    st1, used = oracle.predict(m, st, 0.4)
+    deltas = np.diag(st.M)
+    g1 = _euler_mode_gain((k0 ** 2, k1 ** 2), deltas, np.diag(A), np.diag(D), 0.4, l, factors)
+    gn = _euler_mode_gain((np.pi ** 2, 0.0), deltas, np.diag(A), np.diag(D), 0.4, l, factors)
+    want = math.exp(-np.trace(A) * 0.4) * (
+        1.0 + 0.3 * g1 * np.cos(k0 * j0 + 0.4) * np.cos(k1 * j1) + 0.1 * gn * np.cos(np.pi * j0))
+    return st1.P, want, used
+
+
+def test_oracle_euler_is_the_per_mode_implicit_step():
+    got, want, used = _euler_case()
+    assert used == 7
+    np.testing.assert_allclose(got, want, atol=1e-13, rtol=1e-12)
+
+
+def test_euler_pin_tells_the_product_endpoints_apart():
+    """The pin separates the reading of l factors at t_0..t_{l-1} from one with
+    l + 1 factors (the product endpoints are ambiguous in the paper)."""
+    got, want_more, _ = _euler_case(factors=8)
+    assert np.max(np.abs(got - want_more)) > 1e-4
 
 
 # ---------------------------------------------------- measurement update (Sec. I.A)
