@@ -222,6 +222,21 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
 pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
                           const double* z, double* loglik, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): pmf_batch_step without
+ * any allocation.  Same arguments, filters and results as pmf_batch_step, at most
+ * 4096 filters (more -> PMF_E_INVALID before anything runs).  The per-step
+ * records (items, groups, plans, staged z, log-likelihoods, work counter; under
+ * 2 MiB) live in a file-scope device array that each GPU holds until the process
+ * ends; the per-filter constants live in the filter (allocated by pmf_create).
+ * No hipMalloc/hipFree or other allocating call is made.  Synchronous: returns
+ * once the step has completed on `stream` and loglik (NULL ok, n doubles, any
+ * host memory) is written.  Every call on one GPU uses that GPU's one array:
+ * calls from threads of one process are serialised by a lock; calls that
+ * overlap on one GPU by other means race.  Nothing is cached between calls. */
+pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
+                                  const double* z, double* loglik, void* stream);
+
 /* Kernel timing of batched steps: with enable != 0, every later pmf_batch_step
  * also records HIP events on its stream right before and after the fused
  * kernel.

@@ -385,6 +385,13 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
         f->D2 = A((size_t)3 * 256 * 256 * f->es);
         for (int i = 0; i < 5; ++i) f->rk[i] = A(f->ntot * f->es);
     }
+    {
+        std::string why;
+        if (batch_fusable(f, &why)) {
+            f->dconst = A(fused_const_bytes());
+            f->dconst_T = -1.0;
+        }
+    }
     if (!okalloc) {
         pmf_destroy(f);
         return fail(PMF_E_NOMEM, "device allocation failed");

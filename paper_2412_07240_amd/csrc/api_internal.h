@@ -76,6 +76,9 @@ void batch_cache_release(pmf_ctx* ctx);
 void batch_forget_filter(pmf_ctx* ctx, pmf_filter* f);
 hipError_t batch_leave(pmf_filter* f);
 bool batch_fusable(const pmf_filter* f, std::string* why);
+// bytes of a filter's fused-step constants (its record f->dconst; allocated at
+// create for every filter the fused kernel accepts)
+size_t fused_const_bytes();
 
 // fused steps over a changing set of filters (served batches, batch.hip): the
 // items are rebuilt on every call (nothing cached).  Asynchronous on st; the host

@@ -11,6 +11,7 @@
 // HBM traffic per filter: the density read once and written once.
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -1528,21 +1529,20 @@ static int pow2_at_least(int v) {
 }
 
 // Same-size filters in groups of at most the group type's capacity, largest
-// grids first (the persistent workgroups take the longest work first).
-// Returns the largest complex LDS need of a group.
-static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sorted, std::vector<GItem>& groups) {
-    const int n = (int)items.size();
-    std::vector<int> order(n);
+// grids first (the persistent workgroups take the longest work first).  Array
+// form without allocation: order (n ints) is working space, sorted receives the
+// items in group order, groups at most n records (*ngroups of them).  Ties keep
+// the input order.  Returns the largest complex LDS need of a group.
+static int group_items_arr(const BItem* items, int n, int* order, BItem* sorted, GItem* groups, int* ngroups) {
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    std::sort(order, order + n, [&](int a, int b) {
         const long pa = (long)items[a].n0 * items[a].n1, pb = (long)items[b].n0 * items[b].n1;
         if (pa != pb) return pa > pb;
         if (items[a].n1 != items[b].n1) return items[a].n1 > items[b].n1;
-        return items[a].nx > items[b].nx;
+        if (items[a].nx != items[b].nx) return items[a].nx > items[b].nx;
+        return a < b;
     });
-    sorted.assign(n, BItem{});
-    groups.clear();
-    int maxcplx = 0;
+    int ng = 0, maxcplx = 0;
     for (int q = 0; q < n;) {
         const BItem& b = items[order[q]];
         const int type = group_type(b.nx, b.n0, b.n1);
@@ -1563,9 +1563,21 @@ static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sort
             ++cnt;
         }
         gi.G = cnt;
-        groups.push_back(gi);
+        groups[ng++] = gi;
         maxcplx = std::max(maxcplx, group_cplx(gi.n0, gi.n1, G, group_guard(gi.n0, gi.n1, G)));
     }
+    *ngroups = ng;
+    return maxcplx;
+}
+
+static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sorted, std::vector<GItem>& groups) {
+    const int n = (int)items.size();
+    std::vector<int> order(n);
+    sorted.assign(n, BItem{});
+    groups.assign(n, GItem{});
+    int ng = 0;
+    const int maxcplx = group_items_arr(items.data(), n, order.data(), sorted.data(), groups.data(), &ng);
+    groups.resize(ng);
     return maxcplx;
 }
 
@@ -1710,6 +1722,21 @@ static void dyn_free_buffers(pmf_ctx* ctx, DynBatch* db) {
 
 DynBatch* dyn_create(pmf_ctx*) { return new DynBatch(); }
 
+size_t fused_const_bytes() { return sizeof(FConst); }
+
+// the filter's fused-step constants for interval T in its device record
+// f->dconst (uploaded only when T changed)
+static pmf_status upload_consts(pmf_filter* f, double T) {
+    if (f->dconst_T == T) return PMF_OK;
+    FConst k;
+    k.m = f->km;
+    k.pa = predict_args(f, T);
+    const hipError_t e = hipMemcpy(f->dconst, &k, sizeof(FConst), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "fused constants upload");
+    f->dconst_T = T;
+    return PMF_OK;
+}
+
 void dyn_destroy(pmf_ctx* ctx, DynBatch* db) {
     if (!db) return;
     (void)hipDeviceSynchronize();
@@ -1782,14 +1809,8 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
             f->bytes += sizeof(FConst);
             f->dconst_T = -1.0;
         }
-        if (f->dconst_T != T) {
-            FConst k;
-            k.m = f->km;
-            k.pa = predict_args(f, T);
-            e = hipMemcpy(f->dconst, &k, sizeof(FConst), hipMemcpyHostToDevice);
-            if (e != hipSuccess) return hip_fail(e, "fused constants upload");
-            f->dconst_T = T;
-        }
+        s = upload_consts(f, T);
+        if (s != PMF_OK) return s;
         BItem& b = items[i];
         b.P[0] = static_cast<float*>(f->buf[0]);
         b.P[1] = static_cast<float*>(f->buf[1]);
@@ -1966,5 +1987,152 @@ extern "C" pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int*
     *total_ms = tot;
     *launches = ctx->ev_used;
     ctx->ev_used = 0;
+    return PMF_OK;
+}
+
+// ==================================================================== step without allocation
+// pmf_batch_step_noalloc: the same planning and fused kernels, with their
+// per-step records (items, groups, plans, z, log-likelihoods, work counter) in a
+// file-scope device array instead of library allocations.
+
+namespace pmf {
+
+constexpr int NOALLOC_MAX = 4096;   // filters per call
+constexpr size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+// byte offsets of the parts inside the array (each 256-byte aligned)
+constexpr size_t NA_CTR = 0;
+constexpr size_t NA_ITEMS = 256;
+constexpr size_t NA_GROUPS = NA_ITEMS + al256(sizeof(BItem) * NOALLOC_MAX);
+constexpr size_t NA_PLANS = NA_GROUPS + al256(sizeof(GItem) * NOALLOC_MAX);
+constexpr size_t NA_Z = NA_PLANS + al256(sizeof(FPlan) * NOALLOC_MAX);
+constexpr size_t NA_LL = NA_Z + al256(sizeof(double) * 3 * NOALLOC_MAX);
+constexpr size_t NA_BYTES = NA_LL + al256(sizeof(double) * NOALLOC_MAX);
+static_assert(NA_BYTES <= (size_t)2 << 20, "the no-allocation scratch stays under 2 MiB");
+
+}  // namespace pmf
+
+// Every GPU the library runs on holds its own copy until the process ends.  In
+// host code this name is only a stand-in for the symbol: the device address comes
+// from hipGetSymbolAddress, once per device (na_device below).
+static __device__ __align__(256) unsigned char scratch[pmf::NA_BYTES];
+
+namespace pmf {
+
+constexpr int NA_MAXDEV = 64;
+static std::mutex na_mu;                      // one call at a time (host staging, scratch)
+static unsigned char* na_ptr[NA_MAXDEV] = {};   // device address of scratch, per device
+static int na_ncu[NA_MAXDEV] = {};
+// host staging, reused by every call (calls are serialised by na_mu)
+static BItem na_items[NOALLOC_MAX], na_sorted[NOALLOC_MAX];
+static GItem na_groups[NOALLOC_MAX];
+static int na_order[NOALLOC_MAX];
+static pmf_filter* na_seen[NOALLOC_MAX];
+static double na_z[3 * NOALLOC_MAX], na_ll[NOALLOC_MAX];
+
+// the scratch address, compute-unit count and LDS attribute of device dev
+// (the device is current); set up on its first call
+static pmf_status na_device(int dev, unsigned char** ptr, int* ncu) {
+    if (dev < 0 || dev >= NA_MAXDEV) return fail(PMF_E_INVALID, "device index beyond 64");
+    if (!na_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
+        const pmf_status ls = fused_lds_attribute();
+        if (ls != PMF_OK) return ls;
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "device properties");
+        na_ncu[dev] = prop.multiProcessorCount;
+        na_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *ptr = na_ptr[dev];
+    *ncu = na_ncu[dev];
+    return PMF_OK;
+}
+
+}  // namespace pmf
+
+extern "C" pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
+                                             const double* z, double* loglik, void* stream) {
+    using namespace pmf;
+    if (!ctx || n < 1 || !filters || !z) return fail(PMF_E_INVALID, "NULL argument or n < 1");
+    if (n > NOALLOC_MAX) return fail(PMF_E_INVALID, "more than 4096 filters (the scratch array's limit)");
+    if (!std::isfinite(T) || !(T > 0.0)) return fail(PMF_E_INVALID, "T must be finite and > 0");
+    std::lock_guard<std::mutex> lk(na_mu);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    unsigned char* base = nullptr;
+    int ncu = 0;
+    pmf_status s = na_device(ctx->device, &base, &ncu);
+    if (s != PMF_OK) return s;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+
+    // checks first: nothing runs unless every filter and every z is acceptable
+    int nzmax = 1;
+    for (int i = 0; i < n; ++i) {
+        pmf_filter* f = filters[i];
+        if (!f || f->ctx != ctx) return fail(PMF_E_INVALID, "filter of another context");
+        std::string why;
+        if (!batch_fusable(f, &why)) return fail(PMF_E_INVALID, "filter not fusable: " + why);
+        if (!f->dconst) return fail(PMF_E_INVALID, "filter has no fused-step constants");
+        nzmax = std::max(nzmax, f->model.nz);
+        na_seen[i] = f;
+    }
+    for (int i = 0; i < n * nzmax; ++i)
+        if (!std::isfinite(z[i])) return fail(PMF_E_INVALID, "non-finite measurement");
+    std::sort(na_seen, na_seen + n);
+    if (std::adjacent_find(na_seen, na_seen + n) != na_seen + n) return fail(PMF_E_INVALID, "filter listed twice");
+
+    for (int i = 0; i < n; ++i) {
+        pmf_filter* f = filters[i];
+        e = batch_enter(f);
+        if (e != hipSuccess) return hip_fail(e, "batch enter");
+        s = upload_consts(f, T);
+        if (s != PMF_OK) return s;
+        BItem& b = na_items[i];
+        b.P[0] = static_cast<float*>(f->buf[0]);
+        b.P[1] = static_cast<float*>(f->buf[1]);
+        b.d = f->desc;
+        b.k = static_cast<const FConst*>(f->dconst);
+        b.coef = f->coef;
+        b.idx = i;
+        b.nx = f->model.nx;
+        b.n0 = f->model.nx == 2 ? f->model.N[0] : 1;
+        b.n1 = f->model.nx == 2 ? f->model.N[1] : f->model.N[0];
+    }
+    int ng = 0;
+    const int maxcplx = group_items_arr(na_items, n, na_order, na_sorted, na_groups, &ng);
+    // z rows in item order, stride 3 (the kernels' layout)
+    for (int q = 0; q < n; ++q)
+        for (int j = 0; j < 3; ++j)
+            na_z[(size_t)q * 3 + j] = j < nzmax ? z[(size_t)na_sorted[q].idx * nzmax + j] : 0.0;
+    const size_t lds = fused_lds(maxcplx);
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, FUSED_THREADS, lds);
+    if (e != hipSuccess) return hip_fail(e, "occupancy");
+    if (per_cu < 1) return fail(PMF_E_INVALID, "fused kernel does not fit on a compute unit");
+    const int grid = std::min(ng, per_cu * ncu);
+
+    BItem* d_items = reinterpret_cast<BItem*>(base + NA_ITEMS);
+    GItem* d_groups = reinterpret_cast<GItem*>(base + NA_GROUPS);
+    FPlan* d_plans = reinterpret_cast<FPlan*>(base + NA_PLANS);
+    double* d_z = reinterpret_cast<double*>(base + NA_Z);
+    double* d_ll = reinterpret_cast<double*>(base + NA_LL);
+    int* d_ctr = reinterpret_cast<int*>(base + NA_CTR);
+    e = hipMemcpyAsync(d_items, na_sorted, sizeof(BItem) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_groups, na_groups, sizeof(GItem) * ng, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_z, na_z, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "no-allocation step upload");
+    // the planning kernel clears the work counter (thread 0) before the fused kernel runs
+    hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st,
+                       d_items, d_plans, n, d_z, nullptr, 3, d_ctr);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, d_groups, ng, d_items, d_plans, d_ctr,
+                       d_z, 3, d_ll, maxcplx);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(na_ll, d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "no-allocation step");
+    if (loglik)
+        for (int i = 0; i < n; ++i) loglik[i] = na_ll[i];
     return PMF_OK;
 }

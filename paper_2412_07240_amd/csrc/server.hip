@@ -278,8 +278,8 @@ extern "C" pmf_status pmf_server_add_track(pmf_server* s, const pmf_model* model
     if (r != PMF_OK) return r;
     std::string why;
     const bool fusable = batch_fusable(f, &why);
-    // room for the fused-step constants a batched track adds on first use
-    const size_t bytes = f->bytes + (fusable ? 2048 : 0);
+    // (a fusable filter's fused-step constants are allocated at create)
+    const size_t bytes = f->bytes;
     std::lock_guard<std::mutex> lk(s->mu);
     int live = 0, slot = -1;
     for (int i = 0; i < (int)s->tracks.size(); ++i) {
