@@ -1,14 +1,17 @@
 """The fused batched step (a planning kernel and one persistent launch per step)
 against the FP64 oracle and against the generic path.
 
-Bar (FP32 densities): L1 <= 1e-5 per filter per step vs the oracle started from
-the same state, grids equal to 1e-5 relative, log-likelihood to 1e-4."""
+Bar (FP32 densities): L1 <= 1e-5 and every point within 1e-5 of the peak, per
+filter per step, vs the oracle started from the same state; designed grids
+within the bars derived in gpu_common (step 1e-5 relative, centre 1e-4 cells);
+log-likelihood to 1e-4 relative."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
-from gpu_common import l1, l1_vs_oracle, note
+from gpu_common import (EPS32, check_density, fp32_free_tol, fp32_update_tol, oracle_one_step, l1, l1_vs_oracle, note, oracle_trajectories,
+                        update_amplification)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,20 +43,21 @@ def zmat(scs, k):
 
 
 def check_against_oracle(B, fs, scs, before, lls, what):
-    """before[i] = (c, M, t, P) of filter i ahead of the step."""
-    worst = 0.0
+    """before[i] = (c, M, t, P) of filter i ahead of the step.  Returns the worst
+    (L1, pointwise error, grid M deviation, grid c deviation in cells)."""
+    worst = [0.0, 0.0, 0.0, 0.0]
     for i, (f, sc) in enumerate(zip(fs, scs)):
         c, M, t, P = before[i]
         st = oracle.State(np.array(c), np.array(M), t, np.asarray(P, float))
         st, _ = oracle.predict(sc.model, st, sc.T)
+        amp = update_amplification(sc.model, st, sc.z[k_of(what)])
         st, ll_o, status, _, _ = oracle.update(sc.model, st, sc.z[k_of(what)])
         _, c2, M2, t2, P2 = B.pmf_get_state(f)
         assert abs(t2 - st.t) <= 1e-12 * max(1.0, abs(st.t)), f"{what} filter {i}: time {t2} vs {st.t}"
-        np.testing.assert_allclose(M2, st.M, rtol=1e-4, atol=0, err_msg=f"{what} filter {i}")
-        np.testing.assert_allclose(c2, st.c, atol=1e-4 * np.abs(st.M).max() * 100, err_msg=f"{what} filter {i}")
-        err = l1_vs_oracle(sc.model, c2, M2, P2, st)
-        worst = max(worst, err)
-        assert err <= 1e-5, f"{what} filter {i} N={sc.model.N}: L1 {err:.3e}"
+        e1, em, dM, dc = check_density(sc.model, c2, M2, P2, st, fp32_update_tol(amp),
+                                       what=f"{what} filter {i} N={sc.model.N} A {amp:.0f}", designed=True)
+        for q, v in enumerate((e1, em, dM, dc)):
+            worst[q] = max(worst[q], v)
         if np.isnan(ll_o):
             assert np.isnan(lls[i]), (what, i, lls[i])     # both reject; predicted state kept
         else:
@@ -79,8 +83,79 @@ def test_batch_lockstep_mixed_sizes(B, ctx):
             what = f"lockstep step {k}"
             _K[what] = k
             worst = check_against_oracle(B, fs, scs, before, lls, what)
-            note(f"  step {k}: worst L1 {worst:.2e}")
+            note(f"  step {k}: worst L1 {worst[0]:.2e}  pointwise {worst[1]:.2e}  "
+                 f"grid dM {worst[2]:.1e}  dc {worst[3]:.1e} cells")
     finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
+@pytest.mark.timeout(900)
+def test_batch_50_steps_free_running_and_per_step(B, ctx):
+    """40 mixed-size filters carried through 50 batched steps with no
+    resynchronisation.  Two checks after every step:
+      * per step: the GPU's step against the oracle's step from the same
+        pre-step state (each step's own error), bar fp32_update_tol of that
+        update's amplification;
+      * free-running: the GPU's state against the oracle's own 50-step run from
+        the same prior.  FP32 rounding moves the GPU's trajectory away from the
+        oracle's mostly at outlier measurements (an update magnifies absolute
+        errors of the predictive by up to its amplification A) and the filter
+        carries such a difference for many steps, so the bar is the stability
+        bound max(accumulation bar, 2 A_k (e_{k-1} + 2 eps32)), e_{k-1} the
+        difference measured after the previous step (the predict does not grow
+        an L1 difference; the update at most magnifies it by its amplification,
+        twice for the normalisation).
+    The models are linear-Gaussian, so the oracle's own L1 against the exact
+    Kalman posterior is printed beside the free-running difference."""
+    import multiprocessing
+    K, n = 50, 40
+    scs = W.batched_workload(n, K=K)
+    note(f"case: batch of {n} mixed-size 2-D filters, {K} steps: per-step and free-running vs the oracle")
+    trajs = oracle_trajectories(scs, K, exact=True)
+    note("  oracle runs done")
+    fs = make(B, ctx, scs)
+    fa = B.FilterArray(fs)
+    worst_step = [0.0, 0.0, 0.0, 0.0]
+    worst_free = [0.0, 0.0, 0.0, 0.0]
+    amp_sum = np.zeros(n)
+    e_prev = np.zeros(n)
+    pool = multiprocessing.get_context("spawn").Pool(8)
+    try:
+        for k in range(K):
+            before = [B.pmf_get_state(f)[1:] for f in fs]
+            lls = B.pmf_batch_step(ctx, fa, scs[0].T, zmat(scs, k), want_loglik=True)
+            one = pool.map(oracle_one_step, [(sc, k, *before[i]) for i, sc in enumerate(scs)])
+            ws, wf = [0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0]
+            e_kf_max = 0.0
+            for i, (f, sc) in enumerate(zip(fs, scs)):
+                _, c2, M2, t2, P2 = B.pmf_get_state(f)
+                c1, M1, t1, P1, ll1, amp1 = one[i]
+                r = check_density(sc.model, c2, M2, P2, oracle.State(c1, M1, t1, P1), fp32_update_tol(amp1),
+                                  what=f"step {k} filter {i} N={sc.model.N} A {amp1:.0f}", designed=True)
+                ws = [max(a, b) for a, b in zip(ws, r)]
+                if not np.isnan(ll1):
+                    assert abs(lls[i] - ll1) <= 1e-4 * max(1.0, abs(ll1)), (k, i, lls[i], ll1)
+                c_o, M_o, t_o, P_o, ll_o, amp, e_kf = trajs[i][k]
+                amp_sum[i] += amp
+                bar = max(fp32_free_tol(amp_sum[i]), 2.0 * amp * (e_prev[i] + 2.0 * EPS32))
+                rf = check_density(sc.model, c2, M2, P2, oracle.State(c_o, M_o, t_o, P_o), bar,
+                                   what=f"free step {k} filter {i} N={sc.model.N} A {amp:.0f} prev {e_prev[i]:.1e}",
+                                   designed=True)
+                e_prev[i] = rf[0]
+                wf = [max(a, b) for a, b in zip(wf, rf)]
+                e_kf_max = max(e_kf_max, e_kf)
+            worst_step = [max(a, b) for a, b in zip(worst_step, ws)]
+            worst_free = [max(a, b) for a, b in zip(worst_free, wf)]
+            note(f"  step {k}: per-step L1 {ws[0]:.2e} pointwise {ws[1]:.2e} dM {ws[2]:.1e} dc {ws[3]:.1e}; "
+                 f"free-running L1 {wf[0]:.2e} pointwise {wf[1]:.2e} dM {wf[2]:.1e} dc {wf[3]:.1e}; "
+                 f"oracle vs exact posterior up to {e_kf_max:.1e}")
+        note(f"  over {K} steps: per-step worst L1 {worst_step[0]:.2e} pointwise {worst_step[1]:.2e} "
+             f"dM {worst_step[2]:.1e} dc {worst_step[3]:.1e}; free-running worst L1 {worst_free[0]:.2e} "
+             f"pointwise {worst_free[1]:.2e} dM {worst_free[2]:.1e} dc {worst_free[3]:.1e}")
+    finally:
+        pool.close()
+        pool.join()
         for f in fs:
             B.pmf_destroy(f)
 
@@ -146,8 +221,9 @@ def test_batch_full_size_sampled(B, ctx):
         assert np.all(np.isfinite(lls))
         what = "full step 1"
         _K[what] = 1
-        check_against_oracle(B, [fs[i] for i in sample], [scs[i] for i in sample], before,
-                             [lls[i] for i in sample], what)
+        worst = check_against_oracle(B, [fs[i] for i in sample], [scs[i] for i in sample], before,
+                                     [lls[i] for i in sample], what)
+        note(f"  worst L1 {worst[0]:.2e}  pointwise {worst[1]:.2e}  grid dM {worst[2]:.1e}  dc {worst[3]:.1e} cells")
     finally:
         for f in fs:
             B.pmf_destroy(f)

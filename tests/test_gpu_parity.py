@@ -1,10 +1,13 @@
 """HIP path vs the FP64 oracle, element by element, through the C ABI.
 
 Bar: L1 = sum_j q_j |P_gpu - P_oracle| <= 1e-10 for FP64 densities and <= 1e-5 for
-FP32 densities (q_j the node's integration weight), grids equal to rounding,
-log-likelihoods to 1e-9 (FP64) / 1e-4 (FP32), substep counts equal.
-FP32 runs are checked in lockstep: before each cycle the GPU is given the
-oracle's state, so each cycle's own error is measured.
+FP32 densities (q_j the node's integration weight), and every point within the
+same fraction of the oracle's peak; grids equal to rounding (designed FP32 grids:
+the bars derived in gpu_common), log-likelihoods to 1e-9 (FP64) / 1e-4 (FP32),
+substep counts equal (FP32 free-running: within one).
+FP32 runs are checked in lockstep (before each cycle the GPU is given the
+oracle's state, so each cycle's own error is measured) and free-running (both
+sides carry their own state through every cycle).
 """
 import numpy as np
 import pytest
@@ -87,6 +90,18 @@ def test_gaussian_mixture_noise_1d(B, ctx):
     # tails of the predictive amplifies rounding noise and is not a parity case
     sc.z = sc.z * 0 + np.array([[0.3], [20.1], [-0.5], [19.6], [0.0], [20.4]])
     run_free(B, ctx, sc, 6, 1e-10, what="gm-noise")
+
+
+def test_cfg1_1d_fp32_free_running_100_cycles(B, ctx):
+    note("case: config1 1-D N=64 FP32 RK4, free-running 100 cycles (no resynchronisation)")
+    run_free(B, ctx, W.config1(K=100, precision=W.FP32), 100, 1e-5, ll_tol=1e-4, what="cfg1-fp32-free",
+             report=True)
+
+
+def test_cfg2_2d_fp32_free_running_50_cycles(B, ctx):
+    note("case: config2 2-D N=128 FP32 RK4 cubic measurement, free-running 50 cycles")
+    run_free(B, ctx, W.config2(K=50, N=128, precision=W.FP32), 50, 1e-5, ll_tol=1e-4, what="cfg2-128-fp32-free",
+             report=True)
 
 
 def test_fp32_1d_lockstep(B, ctx):
