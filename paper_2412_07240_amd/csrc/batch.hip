@@ -88,7 +88,7 @@ struct FState {
     const KModel* km;       // once per group (no pointer chase later)
     const double* zrow;
     int idx;
-    double s, inv_mass, loglik;
+    double s, loglik;
     double amap[4], bmap[2];
     double gnc[2], gnM[4], gnvol;
     double pscale2;
@@ -723,7 +723,6 @@ __device__ void filter_design(FState& F, const double* acc, int NX, int n0, int 
     F.ok = !P.bad && isfinite(F.s) && isfinite(mass) && mass > 0.0;
     F.bits = 0;
     if (!F.ok) return;
-    F.inv_mass = 1.0 / mass;
     F.loglik = F.s + log(mass);
     const double iS0 = 1.0 / S0;
     const double ub0 = acc[1] * iS0, ub1 = acc[2] * iS0;
@@ -843,23 +842,42 @@ __shared__ FState pmf_FS[GMAX];
 __shared__ double pmf_slots[32 * 8 + GMAX * 8];
 __shared__ int pmf_item;
 __shared__ GItem pmf_gi;   // the group being processed, written by thread 0 of the kernel loop
+__shared__ int pmf_twtype; // group type whose twiddle tables the LDS holds (-1: none)
 
 typedef __attribute__((address_space(1))) float gfloat;
+// The interval's gain constants of one filter, read once per thread from its
+// plan in LDS (the gain loops then keep them in registers).  Exact integrator:
+// e0 = -gc0/2, e1 = -gc1/2, e2 = -gc2, so that the gain is exp(e0 a2 + e1 b2 +
+// e2 a1 b1); RK4 / Euler: substep count and length.
+struct GainC {
+    int integ, l;
+    float h, e0, e1, e2;
+};
+__device__ inline GainC gain_consts(const FPlan& P) {
+    GainC c;
+    c.integ = P.integ;
+    c.l = P.l;
+    c.h = (float)P.h;
+    c.e0 = -0.5f * (float)P.gc[0];
+    c.e1 = -0.5f * (float)P.gc[1];
+    c.e2 = -(float)P.gc[2];
+    return c;
+}
+
 // spectral gain of one mode over the interval: a2 = k0^2, a1 = k0 (first
 // derivative symbol), b2 = k1^2, b1 = k1; exact, or the product over the RK4 /
 // Euler substeps of their amplification factors (stage coefficients in cf)
-__device__ inline float mode_gain(const FPlan& P, const double* cf, float a2, float a1, float b2, float b1) {
-    if (P.integ == PMF_INT_EXACT)
-        return __expf(-0.5f * ((float)P.gc[0] * a2 + (float)P.gc[1] * b2) - (float)P.gc[2] * a1 * b1);
-    const float hh = (float)P.h;
+__device__ inline float mode_gain(const GainC& c, const double* cf, float a2, float a1, float b2, float b1) {
+    if (c.integ == PMF_INT_EXACT) return __expf(c.e0 * a2 + c.e1 * b2 + c.e2 * a1 * b1);
+    const float hh = c.h;
     float g2 = 1.f;
-    if (P.integ == PMF_INT_EULER) {
-        for (int q = 0; q < P.l; ++q) {
+    if (c.integ == PMF_INT_EULER) {
+        for (int q = 0; q < c.l; ++q) {
             const float sig = (float)cf[3 * q] * a2 + (float)cf[3 * q + 1] * b2 + 2.f * (float)cf[3 * q + 2] * a1 * b1;
             g2 = g2 / (1.f + 0.5f * hh * sig);
         }
     } else {
-        for (int q = 0; q < P.l; ++q) {
+        for (int q = 0; q < c.l; ++q) {
             const double* c3 = cf + 6 * q;
             const float la = -0.5f * ((float)c3[0] * a2 + (float)c3[1] * b2 + 2.f * (float)c3[2] * a1 * b1);
             const float lb = -0.5f * ((float)c3[3] * a2 + (float)c3[4] * b2 + 2.f * (float)c3[5] * a1 * b1);
@@ -876,7 +894,7 @@ __device__ inline float mode_gain(const FPlan& P, const double* cf, float a2, fl
 typedef __attribute__((address_space(1))) const float cgfloat;
 typedef __attribute__((address_space(1))) const unsigned long long cgu64;   // a complex pair
 
-template <int N0, int N1, int NX, int G>
+template <int N0, int N1, int NX, int G, int TYPE>
 __device__ __noinline__ void process_group(const BItem* __restrict__ items, const FPlan* __restrict__ plans,
                                            const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out,
                                            int bufcplx) {
@@ -927,23 +945,28 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         FS[tid].zrow = zall + (size_t)(GI.first + gg) * nzmax;
         FS[tid].idx = idx;
     }
-    for (int i = tid; i < H1; i += NT) {
-        float sn, cs;
-        sincospif(-2.0f * i / H1, &sn, &cs);
-        twr[i] = make_float2(cs, sn);
-    }
-    if (NX == 2)
-        for (int i = tid; i < N0; i += NT) {
+    // twiddle tables of this group type, unless the previous group of this
+    // workgroup left them (the tables sit after both buffers, at a fixed place)
+    if (__builtin_amdgcn_readfirstlane(pmf_twtype) != TYPE) {
+        for (int i = tid; i < H1; i += NT) {
             float sn, cs;
-            sincospif(-2.0f * i / N0, &sn, &cs);
-            twc[i] = make_float2(cs, sn);
+            sincospif(-2.0f * i / H1, &sn, &cs);
+            twr[i] = make_float2(cs, sn);
         }
-    for (int i = tid; i <= H1; i += NT) {
-        float sn, cs;
-        sincospif(-2.0f * i / N1, &sn, &cs);
-        twp[i] = make_float2(cs, sn);
+        if (NX == 2)
+            for (int i = tid; i < N0; i += NT) {
+                float sn, cs;
+                sincospif(-2.0f * i / N0, &sn, &cs);
+                twc[i] = make_float2(cs, sn);
+            }
+        for (int i = tid; i <= H1; i += NT) {
+            float sn, cs;
+            sincospif(-2.0f * i / N1, &sn, &cs);
+            twp[i] = make_float2(cs, sn);
+        }
     }
     __syncthreads();
+    if (tid == 0) pmf_twtype = TYPE;
 
     // ---- load: super-row L = r*G + g holds row r of filter g as complex pairs.
     // Every load of the thread is issued before the first wait: the addresses are
@@ -976,23 +999,33 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     // ---- forward: rows (r2c), columns
     float2* cur = cfft<H1, N0 * G, PITCH, 1, -1, true>(bufA, bufB, twr);
     float2* oth = (cur == bufA) ? bufB : bufA;
-    // 2-D: the DC and Nyquist entries of a row spectrum of real data are real,
-    // X_0 = Re Z_0 + Im Z_0 and X_H1 = Re Z_0 - Im Z_0; they are stored packed as
-    // X_0 + i X_H1 in entry 0, so that the column transforms run over H1 columns
-    // per filter (entry H1 is not used)
-    constexpr int MW = NX == 2 ? H1 : PITCH;   // entries written per row
+    // Split of the N1/2-point transforms Z of the rows into the half spectra X of
+    // the real rows: with E = (Z_s + conj Z_{H1-s}) / 2, O = (Z_s - conj Z_{H1-s}) / 2
+    // and t = W^s O (W = e^{-2 pi i / N1}), X_s = E - i t and X_{H1-s} = conj E - i conj t,
+    // so one thread makes both entries of a pair (s, H1 - s) from the same two loads.
+    // The DC and Nyquist entries are real, X_0 = Re Z_0 + Im Z_0 and X_H1 = Re Z_0 - Im Z_0;
+    // in 2-D they are stored packed as X_0 + i X_H1 in entry 0, so that the column
+    // transforms run over H1 columns per filter (entry H1 is not used)
+    constexpr int HP = H1 / 2 + 1;             // pairs (s, H1 - s), s = 0 .. H1/2, per row
 #pragma unroll 1
-    for (int e = tid; e < N0 * G * MW; e += NT) {
-        const int L = e / MW, s = e - L * MW;
-        const float2 Zs = cur[L * PITCH + (s == H1 ? 0 : s)];
-        const float2 Zc = f2conj(cur[L * PITCH + (s == 0 ? 0 : H1 - s)]);
-        if (NX == 2 && s == 0) {
-            oth[L * PITCH] = make_float2(Zs.x + Zs.y, Zs.x - Zs.y);
+    for (int e = tid; e < N0 * G * HP; e += NT) {
+        const int L = e / HP, s = e - L * HP;
+        const float2* zr = cur + L * PITCH;
+        float2* xr = oth + L * PITCH;
+        if (s == 0) {
+            const float2 Z0 = zr[0];
+            if constexpr (NX == 2) {
+                xr[0] = make_float2(Z0.x + Z0.y, Z0.x - Z0.y);
+            } else {
+                xr[0] = make_float2(Z0.x + Z0.y, 0.f);
+                xr[H1] = make_float2(Z0.x - Z0.y, 0.f);
+            }
         } else {
+            const float2 Zs = zr[s], Zc = f2conj(zr[H1 - s]);
             const float2 E = f2scale(f2add(Zs, Zc), 0.5f);
-            const float2 t = f2mul(twp[s], f2sub(Zs, Zc));
-            // X_s = E - i/2 W^s (Z_s - conj Z_{H1-s})
-            oth[L * PITCH + s] = f2add(E, make_float2(0.5f * t.y, -0.5f * t.x));
+            const float2 t = f2mul(twp[s], f2scale(f2sub(Zs, Zc), 0.5f));
+            xr[s] = make_float2(E.x + t.y, E.y - t.x);
+            if (2 * s != H1) xr[H1 - s] = make_float2(E.x - t.y, -E.y - t.x);
         }
     }
     __syncthreads();
@@ -1024,16 +1057,27 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                 const int cth = tid % NCOLN, r0 = tid / NCOLN;
                 if (r0 < CPS) {
                     const int g = cth / CWN, s1 = 1 + cth - g * CWN;
-                    const FPlan& P = FS[g].p;
-                    const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
-                    const float scale = (float)P.etr * inv;
+                    const GainC gc = gain_consts(FS[g].p);
+                    const float scale = (float)FS[g].p.etr * inv;
                     const float kap1 = (6.283185307179586f / N1) * s1;
                     float2* colp = cur + g * PITCH + s1;
-                    for (int s0 = r0; s0 < N0; s0 += CPS) {
-                        float a2, a1;
-                        rowk(s0, a2, a1);
-                        float2* x = colp + s0 * SPITCH;
-                        *x = f2scale(*x, mode_gain(P, cf, a2, a1, kap1 * kap1, kap1) * scale);
+                    if (gc.integ == PMF_INT_EXACT) {
+                        // exp(e0 a2 + e2 kap1 a1 + e1 kap1^2): the column's part once
+                        const float cb = gc.e1 * (kap1 * kap1), cx = gc.e2 * kap1;
+                        for (int s0 = r0; s0 < N0; s0 += CPS) {
+                            float a2, a1;
+                            rowk(s0, a2, a1);
+                            float2* x = colp + s0 * SPITCH;
+                            *x = f2scale(*x, __expf(fmaf(gc.e0, a2, fmaf(cx, a1, cb))) * scale);
+                        }
+                    } else {
+                        const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
+                        for (int s0 = r0; s0 < N0; s0 += CPS) {
+                            float a2, a1;
+                            rowk(s0, a2, a1);
+                            float2* x = colp + s0 * SPITCH;
+                            *x = f2scale(*x, mode_gain(gc, cf, a2, a1, kap1 * kap1, kap1) * scale);
+                        }
                     }
                 }
             } else {
@@ -1046,14 +1090,14 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                 const float kn = 3.14159265358979f;   // |kappa_1| at the Nyquist index
                 for (int e = tid - TN; e < G * PAIRS; e += 64) {
                     const int g = e / PAIRS, s0 = e - g * PAIRS;
-                    const FPlan& P = FS[g].p;
+                    const GainC gc = gain_consts(FS[g].p);
                     const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
-                    const float scale = (float)P.etr * inv;
+                    const float scale = (float)FS[g].p.etr * inv;
                     const int m = s0 == 0 ? 0 : N0 - s0;
                     float a2, a1;
                     rowk(s0, a2, a1);
-                    const float gd = mode_gain(P, cf, a2, a1, 0.f, 0.f);
-                    const float gn = mode_gain(P, cf, a2, a1, kn * kn, 0.f);
+                    const float gd = mode_gain(gc, cf, a2, a1, 0.f, 0.f);
+                    const float gn = mode_gain(gc, cf, a2, a1, kn * kn, 0.f);
                     const float pa = 0.5f * (gd + gn) * scale, pb = 0.5f * (gd - gn) * scale;
                     float2* x = cur + s0 * SPITCH + g * PITCH;
                     float2* y = cur + m * SPITCH + g * PITCH;
@@ -1066,13 +1110,13 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
             // 1-D: a thread per spectral entry (filter g, frequency s1)
             for (int cth = tid; cth < SPITCH; cth += NT) {
                 const int g = cth / PITCH, s1 = cth - g * PITCH;
-                const FPlan& P = FS[g].p;
+                const GainC gc = gain_consts(FS[g].p);
                 const double* cf = items[GI.first + (g < Gact ? g : 0)].coef;
                 const int kk1 = (s1 < H1) ? s1 : s1 - N1;
                 const float kap1 = (6.283185307179586f / N1) * kk1;
                 const float a1 = (s1 == H1) ? 0.f : kap1;
                 float2* x = cur + cth;
-                *x = f2scale(*x, mode_gain(P, cf, kap1 * kap1, a1, 0.f, 0.f) * (float)P.etr * inv);
+                *x = f2scale(*x, mode_gain(gc, cf, kap1 * kap1, a1, 0.f, 0.f) * (float)FS[g].p.etr * inv);
             }
         }
     }
@@ -1082,22 +1126,31 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         cur = cfft<N0, G * H1, 1, SPITCH, +1, true, H1>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
+    // Merge of the half spectra X into the N1/2-point inverse inputs Z, per pair
+    // (s, H1 - s): with A = X_s + conj X_{H1-s}, B = X_s - conj X_{H1-s} and
+    // u = conj(W^s) B, Z_s = A + i u and Z_{H1-s} = conj A + i conj u.  Entry 0 (2-D:
+    // the packed X_0 + i X_H1, both real) gives Z_0 = (X_0 + X_H1) + i (X_0 - X_H1).
 #pragma unroll 1
-    for (int e = tid; e < N0 * G * H1; e += NT) {
-        const int L = e / H1, s = e - L * H1;
-        float2 Xs = cur[L * PITCH + s];
-        float2 Xc;
-        if (NX == 2 && s == 0) {
-            // packed entry 0: X_0 + i X_H1, both real
-            Xc = make_float2(Xs.y, 0.f);
-            Xs = make_float2(Xs.x, 0.f);
+    for (int e = tid; e < N0 * G * HP; e += NT) {
+        const int L = e / HP, s = e - L * HP;
+        const float2* xr = cur + L * PITCH;
+        float2* zr = oth + L * PITCH;
+        if (s == 0) {
+            const float2 X0 = xr[0];
+            if constexpr (NX == 2) {
+                zr[0] = make_float2(X0.x + X0.y, X0.x - X0.y);
+            } else {
+                const float2 XH = f2conj(xr[H1]);
+                const float2 A = f2add(X0, XH), Bv = f2sub(X0, XH);
+                zr[0] = make_float2(A.x - Bv.y, A.y + Bv.x);
+            }
         } else {
-            Xc = f2conj(cur[L * PITCH + H1 - s]);
+            const float2 Xs = xr[s], Xc = f2conj(xr[H1 - s]);
+            const float2 A = f2add(Xs, Xc);
+            const float2 u = f2mul(f2conj(twp[s]), f2sub(Xs, Xc));
+            zr[s] = make_float2(A.x - u.y, A.y + u.x);
+            if (2 * s != H1) zr[H1 - s] = make_float2(A.x + u.y, u.x - A.y);
         }
-        const float2 Aa = f2add(Xs, Xc);
-        const float2 Bb = f2mul(f2conj(twp[s]), f2sub(Xs, Xc));
-        // Z_s = (X_s + conj X_{H1-s}) + i W^{-s} (X_s - conj X_{H1-s})
-        oth[L * PITCH + s] = make_float2(Aa.x - Bb.y, Aa.y + Bb.x);
     }
     __syncthreads();
     cur = cfft<H1, N0 * G, PITCH, 1, +1, true>(oth, cur, twr);
@@ -1216,7 +1269,9 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     if (tid < Gact) filter_design(FS[tid], red, NX, N0, N1);
     __syncthreads();
 
-    // ---- interpolation onto the new grid, straight to HBM (normalised lazily)
+    // ---- interpolation of the unnormalised posterior onto the new grid, straight to
+    // HBM: the stored values are normalised lazily, by the pending scale 1/(vol' sum)
+    // of the new grid's sum, which absorbs the posterior's own normaliser too
     double macc[1] = {0.0};
     // rows shorter than their thread segment (N1 = 48, 96) are enumerated flat,
     // point p = r N1 + j over all RPS x SEGW threads of the filter, so that no
@@ -1226,7 +1281,6 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         const FState& F = FS[g];
         gfloat* Pout = (gfloat*)F.pout;
         const float* Pog = Po + g * RPO;
-        const float inv_mass = (float)F.inv_mass;
         if constexpr (NX == 2) {
             // the cubic interpolant of the posterior at old index coordinates (nu0, nu1)
             auto interp_at = [&](double nu0, double nu1) -> float {
@@ -1260,7 +1314,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                     const int r = p / N1, c = p - r * N1;
                     const double u0 = (double)r - half0, u1 = (double)c - half1;
                     const float val = interp_at(F.amap[0] * u0 + F.amap[1] * u1 + F.bmap[0],
-                                                F.amap[2] * u0 + F.amap[3] * u1 + F.bmap[1]) * inv_mass;
+                                                F.amap[2] * u0 + F.amap[3] * u1 + F.bmap[1]);
                     Pout[p] = val;
                     macc[0] += (double)val;
                 }
@@ -1270,7 +1324,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                 double nu1 = F.amap[2] * ((double)tr - half0) + F.amap[3] * uj + F.bmap[1];
                 const double dn0 = F.amap[0] * RPS, dn1 = F.amap[2] * RPS;
                 for (int r = tr; r < N0; r += RPS, nu0 += dn0, nu1 += dn1) {
-                    const float val = interp_at(nu0, nu1) * inv_mass;
+                    const float val = interp_at(nu0, nu1);
                     Pout[r * N1 + j] = val;
                     macc[0] += (double)val;
                 }
@@ -1279,7 +1333,6 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
             const double nu = F.amap[0] * uj + F.bmap[0];
             float val = 0.f;
             if (nu >= 0.0 && nu <= (double)(N1 - 1)) val = trig_interp_1d(Pog, N1, nu);
-            val *= inv_mass;
             Pout[j] = val;
             macc[0] += (double)val;
         }
@@ -1321,6 +1374,13 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__ items,
         const FPlan* __restrict__ plans, int* ctr, const double* __restrict__ zall, int nzmax,
         double* __restrict__ ll_out, int bufcplx) {
+    // no twiddle tables in LDS yet.  The barrier keeps this block apart from the
+    // loop's claim below: without it the compiler merged the two thread-0 blocks
+    // into a rotated loop in which wave 0 passed the loop's first barrier before
+    // lane 0 had made the first claim (the workgroup then read an unwritten
+    // group record)
+    if (threadIdx.x == 0) pmf_twtype = -1;
+    __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) {
             const int next = atomicAdd(ctr, 1);
@@ -1333,7 +1393,7 @@ k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__
         __syncthreads();
         if (it >= ngroups) break;
 #define PMF_GROUP(T, N0, N1, NX) \
-    case T: process_group<N0, N1, NX, group_g<N0, N1>()>(items, plans, zall, nzmax, ll_out, bufcplx); break;
+    case T: process_group<N0, N1, NX, group_g<N0, N1>(), T>(items, plans, zall, nzmax, ll_out, bufcplx); break;
         switch (type) {
             PMF_GROUP(GT_2D_128, 128, 128, 2)
             PMF_GROUP(GT_2D_96, 96, 96, 2)
