@@ -30,6 +30,19 @@ if ROOT not in sys.path:
 
 METRIC = "grid-point FPE updates/sec at stated L1 error vs FP64; p50/p99 update latency"
 HBM_PEAK_GBS = 8000.0
+HBM_TARGET_FRAC = 0.60
+# FP32 vector arithmetic without packed instructions (the build disables them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) per clock at 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def fused_flops_per_point(n: int) -> float:
+    """Algorithmic FP32 flops of one fused cycle per grid point of an n x n filter:
+    real 2-D FFT forward + inverse 5 log2(n^2) (the standard 2.5 m log2 m per real
+    transform of m points), spectral gain 4, likelihood 6, moment sums 5, cubic
+    Lagrange regrid 62 (2 coordinates, 2 x 10 for the weights, 16 + 4 FMAs),
+    renormalising sum 1."""
+    return 10.0 * math.log2(n) + 78.0
 # VALU issue: 256 CUs x 4 SIMDs x 16 lanes per clock (a wave64 instruction every
 # 4 clocks per SIMD; packed FP32 is not used) at 2.4 GHz
 VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
@@ -219,10 +232,19 @@ def run_batched(args):
         if tr.get("source_hash") == source_hash() and tr.get("points_per_step") == pts:
             traffic = tr.get("bytes_per_launch")
             valu = tr.get("valu_wave_instr_per_launch")
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+    # The fused cycle is bound by VALU issue (the HBM roofline is priced beside it):
+    # algorithmic FP32 flops per launch over the live kernel time, against the
+    # non-packed FP32 vector peak
+    flops = float(sum(sc.model.N[0] * sc.model.N[1] * fused_flops_per_point(sc.model.N[0]) for sc in scs))
+    tflops = flops / (kavg_ms * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": tflops / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
                        "kernel": "pmf::k_fused", "kernel_ms": kavg_ms,
-                       "algorithmic_bytes_per_launch": BYTES_PER_POINT * pts}
+                       "algorithmic_flops_per_launch": flops,
+                       "why": "VALU issue limits the fused cycle (hbm frac well below its valu_issue frac)"}
+    out["hbm"] = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                  "target_frac": HBM_TARGET_FRAC, "gap_to_target": HBM_TARGET_FRAC / (achieved / HBM_PEAK_GBS),
+                  "algorithmic_bytes_per_launch": BYTES_PER_POINT * pts, "traffic": traffic}
     if valu:
         # what actually bounds the fused cycle: VALU issue (SQ_INSTS_VALU of the
         # same sources from the counter run, over the live kernel time)
@@ -231,6 +253,7 @@ def run_batched(args):
                              "achieved": lane / (kavg_ms * 1e-3), "peak": VALU_PEAK_LANE_INSTR,
                              "unit": "lane-instructions/s", "frac": lane / (kavg_ms * 1e-3) / VALU_PEAK_LANE_INSTR}
 
+    sampled = None
     if not args.no_extras:
         # p50/p99 latency of a step (submit -> results on the host)
         lat = []
@@ -242,26 +265,14 @@ def run_batched(args):
             k += 1
         out["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "what": "one batched step, submit to log-likelihoods on the host"}
-        # L1 of sampled filters vs the FP64 oracle from the same pre-step state
-        import oracle
+        # one step of 8 sampled filters, kept for the oracle check of the CPU leg
         rng = np.random.default_rng(7)
         sample = sorted(rng.choice(nf, size=8, replace=False).tolist())
         before = [B.pmf_get_state(fs[i])[1:] for i in sample]
         lls = B.pmf_batch_step(ctx, fa, T, Z[k], want_loglik=True)
-        worst = 0.0
-        for j, i in enumerate(sample):
-            c, M, t, P = before[j]
-            st = oracle.State(np.array(c), np.array(M), t, np.asarray(P, float))
-            st, _ = oracle.predict(scs[i].model, st, T)
-            st, ll_o, status, _, _ = oracle.update(scs[i].model, st, Z[k, i])
-            _, c2, M2, _, P2 = B.pmf_get_state(fs[i])
-            mapped = oracle.interpolate(scs[i].model, oracle.State(c2, M2, st.t, np.asarray(P2, float)),
-                                        st.c, st.M)
-            q = oracle.quadrature_weights(scs[i].model, st.M)
-            worst = max(worst, float(np.sum(q * np.abs(mapped - st.P))))
+        after = [B.pmf_get_state(fs[i])[1:] for i in sample]
+        sampled = (sample, before, after, Z[k].copy())
         k += 1
-        out["l1_vs_fp64_oracle"] = {"max": worst, "filters": len(sample), "tolerance": 1e-5}
-        log(f"bench: sampled L1 vs oracle {worst:.2e}")
         # plain single-filter FP64 GPU path on a sample of the same filters
         sub = scs[:64]
         ff = [B.pmf_create(ctx, sc.model.with_(precision=W.FP64), sc.prior) for sc in sub]
@@ -285,6 +296,9 @@ def run_batched(args):
                                  "speedup_of_value": value / plain}
         for f in ff:
             B.pmf_destroy(f)
+        out["equal_accuracy"] = equal_accuracy(B, ctx, scs, W, np)
+        log(f"bench: L1 vs the exact Kalman posterior: batched FP32 {out['equal_accuracy']['batched_fp32']['l1_max']:.2e}, "
+            f"plain FP64 {out['equal_accuracy']['plain_fp64']['l1_max']:.2e}")
 
     if args.copy_probe:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -298,11 +312,160 @@ def run_batched(args):
     B.pmf_ctx_destroy(ctx)
 
     if not args.no_cpu:
+        # the CPU leg: the oracle (checker and baseline) and the CPU-FFT reference
+        if sampled is not None:
+            out["l1_vs_fp64_oracle"] = sampled_oracle_l1(scs, T, *sampled)
+            log(f"bench: sampled L1 vs oracle {out['l1_vs_fp64_oracle']['max']:.2e}")
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, nf)
+        log(f"bench: CPU-FFT reference (~{args.cpu_seconds:.0f} s)")
+        out["cpu_fft_reference"] = cpu_fft_baseline(args.cpu_seconds, nf)
+        out["cpu_fft_reference"]["gpu_over_cpu"] = value / out["cpu_fft_reference"]["value"]
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def kalman_posteriors(sc, K):
+    """Exact Kalman filter of a linear-Gaussian scenario: posterior (mean, cov)
+    after each of K cycles (discretisation e^{AT}, e^{AT} W(T) e^{A^T T}; W by
+    Van Loan's block exponential)."""
+    import numpy as np
+    import scipy.linalg
+    m = sc.model
+    A = np.asarray(m.A, float)[:2, :2]
+    D = np.asarray(m.D, float)[:2, :2]
+    C = np.zeros((4, 4))
+    C[:2, :2], C[:2, 2:], C[2:, 2:] = A, D, -A.T
+    E = scipy.linalg.expm(C * sc.T)
+    Phi = E[:2, :2]
+    Qd = E[:2, 2:] @ Phi.T                       # e^{AT} W(T) e^{A^T T}
+    H = np.asarray(m.H, float)[:m.nz, :2]
+    R = np.asarray(m.noise_cov, float)[0][:m.nz, :m.nz]
+    mu = np.asarray(sc.prior.mean, float)[0][:2]
+    P = np.asarray(sc.prior.cov, float)[0][:2, :2]
+    out = []
+    for k in range(K):
+        mu, P = Phi @ mu, Phi @ P @ Phi.T + Qd
+        G = P @ H.T @ np.linalg.inv(H @ P @ H.T + R)
+        mu = mu + G @ (np.asarray(sc.z[k], float)[:m.nz] - H @ mu)
+        P = (np.eye(2) - G @ H) @ P
+        out.append((mu.copy(), 0.5 * (P + P.T)))
+    return out
+
+
+def kalman_l1(sc, c, M, P, mean, cov):
+    """L1 of a grid density against N(mean, cov) on the same nodes (normalised
+    with the grid's cell volume)."""
+    import numpy as np
+    N0, N1 = sc.model.N[0], sc.model.N[1]
+    U0, U1 = np.meshgrid(np.arange(N0) - N0 // 2, np.arange(N1) - N1 // 2, indexing="ij")
+    X = np.stack([c[0] + M[0, 0] * U0 + M[0, 1] * U1, c[1] + M[1, 0] * U0 + M[1, 1] * U1], axis=-1)
+    r = X - mean
+    Ci = np.linalg.inv(cov)
+    g = np.exp(-0.5 * np.einsum("...i,ij,...j->...", r, Ci, r))
+    vol = abs(np.linalg.det(M))
+    g /= vol * g.sum()
+    return float(vol * np.abs(np.asarray(P, float).reshape(N0, N1) - g).sum())
+
+
+def equal_accuracy(B, ctx, scs, W, np, nfil=8, K=10):
+    """Both GPU paths, batched FP32 and plain single-filter FP64, over the same K
+    cycles of the same nfil filters (one of each grid size at least), each
+    measured against the exact Kalman posterior of the linear-Gaussian model."""
+    pick, seen = [], set()
+    for i, sc in enumerate(scs):
+        if sc.model.N[0] not in seen or len(pick) < nfil:
+            pick.append(i)
+            seen.add(sc.model.N[0])
+        if len(pick) >= nfil and len(seen) >= 5:
+            break
+    sub = [scs[i] for i in pick]
+    fb = [B.pmf_create(ctx, sc.model, sc.prior) for sc in sub]
+    fp = [B.pmf_create(ctx, sc.model.with_(precision=W.FP64), sc.prior) for sc in sub]
+    kfs = [kalman_posteriors(sc, K) for sc in sub]
+    eb, ep, dpp = [], [], []
+    try:
+        for k in range(K):
+            B.pmf_batch_step(ctx, fb, sub[0].T, np.array([sc.z[k] for sc in sub]))
+            for f, sc in zip(fp, sub):
+                B.pmf_predict(f, sc.T)
+                B.pmf_update(f, sc.z[k])
+            for j, sc in enumerate(sub):
+                _, c1, M1, _, P1 = B.pmf_get_state(fb[j])
+                _, c2, M2, _, P2 = B.pmf_get_state(fp[j])
+                eb.append(kalman_l1(sc, c1, M1, P1, *kfs[j][k]))
+                ep.append(kalman_l1(sc, c2, M2, P2, *kfs[j][k]))
+                dpp.append(abs(eb[-1] - ep[-1]))
+    finally:
+        for f in fb + fp:
+            B.pmf_destroy(f)
+    return {"what": f"{len(sub)} filters (N in {sorted(seen)}), {K} cycles each, L1 of the grid density "
+                    "against the exact Kalman posterior on its own grid (linear-Gaussian models)",
+            "batched_fp32": {"l1_max": max(eb), "l1_mean": float(np.mean(eb))},
+            "plain_fp64": {"l1_max": max(ep), "l1_mean": float(np.mean(ep))},
+            "largest_difference_of_the_two": max(dpp)}
+
+
+def sampled_oracle_l1(scs, T, sample, before, after, z):
+    """L1 and pointwise error of the sampled filters' batched step against the
+    FP64 oracle's step from the same pre-step state (CPU leg)."""
+    import numpy as np
+    import oracle
+    worst, worst_pt = 0.0, 0.0
+    for j, i in enumerate(sample):
+        c, M, t, P = before[j]
+        st = oracle.State(np.array(c), np.array(M), t, np.asarray(P, float))
+        st, _ = oracle.predict(scs[i].model, st, T)
+        st, ll_o, status, _, _ = oracle.update(scs[i].model, st, z[i])
+        c2, M2, _, P2 = after[j]
+        mapped = oracle.interpolate(scs[i].model, oracle.State(c2, M2, st.t, np.asarray(P2, float)), st.c, st.M)
+        q = oracle.quadrature_weights(scs[i].model, st.M)
+        worst = max(worst, float(np.sum(q * np.abs(mapped - st.P))))
+        worst_pt = max(worst_pt, float(np.abs(mapped - st.P).max() / np.abs(st.P).max()))
+    return {"max": worst, "pointwise_max": worst_pt, "filters": len(sample), "tolerance": 1e-5}
+
+
+def _cpu_fft_worker(args):
+    idxs, budget = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        import oracle
+        import workloads as W
+        from oracle import cpu_fft
+        pts, busy = 0, 0.0
+        t_end = time.perf_counter() + budget
+        for i in idxs:
+            if time.perf_counter() > t_end:
+                break
+            sc = W.batched_filter(i, K=4)
+            f = cpu_fft.Filter(sc.model, sc.T)
+            st = oracle.create(sc.model, sc.prior)
+            t0 = time.perf_counter()
+            for k in range(4):
+                st = f.predict(st)
+                st, _ = f.update(st, sc.z[k])
+            busy += time.perf_counter() - t0
+            pts += 4 * sc.model.N[0] * sc.model.N[1]
+        return pts, busy
+
+
+def cpu_fft_baseline(seconds: float, nfilters: int):
+    """The CPU-FFT reference (scipy.fft real transforms, FP64) on the host cores:
+    one single-threaded process per core over the batched workload's filters."""
+    import multiprocessing as mp
+    cores = min(os.cpu_count() or 1, 16)
+    per = [list(range(w, nfilters, cores)) for w in range(cores)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_cpu_fft_worker, [(p, seconds) for p in per])
+    wall = time.perf_counter() - t0
+    pts = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    return {"value": pts / busy if busy > 0 else None, "unit": "grid-point updates/s", "cores": cores,
+            "kind": "scipy.fft CPU reference (FP64, not the oracle)",
+            "sample": f"4 predict+update cycles per filter of the batched workload's filters, {cores} processes x "
+                      f"1 thread, ~{seconds:.0f} s each; {pts} points in {busy:.1f} s busy ({wall:.1f} s wall)"}
 
 
 # ------------------------------------------------------------------ 3-D Chebyshev
@@ -401,6 +564,7 @@ def run_cheb3d(args):
                      "us_per_substep": 1e3 * sum(pred_ms) / lsum,
                      "algorithmic_flops_per_predict": flops / args.steps},
     }
+    pair = None
     if not args.no_extras:
         # one predict against the FP64 GPU path (parity-tested against the oracle)
         f64 = B.pmf_create(ctx, sc.model.with_(precision=W.FP64), sc.prior)
@@ -410,14 +574,18 @@ def run_cheb3d(args):
         B.pmf_predict(f64, sc.T)
         _, _, M1, _, P1 = B.pmf_get_state(f)
         _, _, M2, _, P2 = B.pmf_get_state(f64)
+        pair = (M2, P1, P2)
+        B.pmf_destroy(f64)
+    B.pmf_destroy(f)
+    B.pmf_ctx_destroy(ctx)
+    if not args.no_cpu and pair is not None:
+        # CPU leg: the Clenshaw-Curtis quadrature of the oracle for the L1 of the two GPU paths
         import oracle
+        M2, P1, P2 = pair
         q = oracle.quadrature_weights(sc.model, np.asarray(M2))
         out["l1_vs_fp64"] = {"value": float(np.sum(q * np.abs(np.asarray(P1, float) - np.asarray(P2, float)))),
                              "what": "one predict, FP32 MFMA path vs the FP64 GPU path from the same state",
                              "tolerance": 1e-5}
-        B.pmf_destroy(f64)
-    B.pmf_destroy(f)
-    B.pmf_ctx_destroy(ctx)
     if not args.no_cpu:
         log("bench cheb3d: CPU oracle baseline")
         out["cpu_baseline"] = cheb_cpu_baseline(N, 0.2)
@@ -538,9 +706,9 @@ def run_single(args):
     (the host needs the result before the next measurement), as a tracker would."""
     import numpy as np
     import workloads as W
-    import oracle
     from paper_2412_07240_amd import binding as B
 
+    checks = []
     cases = [("1-D N=64 FP64, RK4 (>= 10 substeps), T = 0.1", W.config1(K=200)),
              ("2-D 128^2 FP64, RK4, cubic measurement, T = 0.05", W.config2(K=200, precision=W.FP64)),
              ("2-D 128^2 FP32, RK4, cubic measurement, T = 0.05", W.config2(K=200, precision=W.FP32))]
@@ -570,26 +738,31 @@ def run_single(args):
             tu.append(c - b)
             k += 1
         el = time.perf_counter() - t0
-        # the last cycle against the oracle from the same pre-cycle state
+        # the last cycle, kept for the oracle check of the CPU leg
         _, c0, M0, t_, P0 = B.pmf_get_state(f)
-        st = oracle.State(np.array(c0), np.array(M0), t_, np.asarray(P0, float))
         B.pmf_predict(f, sc.T)
         B.pmf_update(f, sc.z[k])
-        st, _ = oracle.predict(m, st, sc.T)
-        st, _, _, _, _ = oracle.update(m, st, sc.z[k])
         _, c1, M1, _, P1 = B.pmf_get_state(f)
-        mapped = oracle.interpolate(m, oracle.State(np.array(c1), np.array(M1), st.t, np.asarray(P1, float)),
-                                    st.c, st.M)
-        l1 = float(np.sum(oracle.quadrature_weights(m, st.M) * np.abs(mapped - st.P)))
         B.pmf_destroy(f)
         res.append({"case": name, "points": pts, "cycles": n_cyc, "points_per_s": pts * n_cyc / el,
                     "predict_p50_ms": 1e3 * float(np.percentile(tp, 50)),
                     "predict_p99_ms": 1e3 * float(np.percentile(tp, 99)),
                     "update_p50_ms": 1e3 * float(np.percentile(tu, 50)),
-                    "update_p99_ms": 1e3 * float(np.percentile(tu, 99)),
-                    "l1_vs_fp64_oracle_one_cycle": l1})
+                    "update_p99_ms": 1e3 * float(np.percentile(tu, 99))})
+        checks.append((sc, k, (c0, M0, t_, P0), (c1, M1, P1)))
         log(f"bench single: {json.dumps(res[-1])}")
     B.pmf_ctx_destroy(ctx)
+    if not args.no_cpu:
+        # CPU leg: the last cycle of each case against the oracle from the same pre-cycle state
+        import oracle
+        for r, (sc, k, (c0, M0, t_, P0), (c1, M1, P1)) in zip(res, checks):
+            m = sc.model
+            st = oracle.State(np.array(c0), np.array(M0), t_, np.asarray(P0, float))
+            st, _ = oracle.predict(m, st, sc.T)
+            st, _, _, _, _ = oracle.update(m, st, sc.z[k])
+            mapped = oracle.interpolate(m, oracle.State(np.array(c1), np.array(M1), st.t, np.asarray(P1, float)),
+                                        st.c, st.M)
+            r["l1_vs_fp64_oracle_one_cycle"] = float(np.sum(oracle.quadrature_weights(m, st.M) * np.abs(mapped - st.P)))
     out = {
         "metric": METRIC, "value": res[1]["points_per_s"], "unit": "grid-point updates/s", "n_gpus": 1,
         "steps": n_cyc, "warmup": args.warmup,
