@@ -777,7 +777,10 @@ def run_single(args):
 
 # ------------------------------------------------------------------ convergence study
 
-CONV_N = (16, 20, 24, 30, 32, 40, 48, 50, 60, 64, 80, 96, 100, 120, 128, 150, 160, 180, 200, 240, 250)
+# N even with 2 (N + 1) also of the form 2^a 3^b 5^c 7^d 11^e 13^f 17^g (the fast sine
+# transform of the finite differences is an FFT of that length; the spectral
+# updates use N-point FFTs)
+CONV_N = (16, 20, 24, 26, 32, 34, 44, 48, 50, 54, 64, 80, 84, 90, 98, 104, 120, 168, 220, 224, 242)
 
 
 def _gm_density(x, w, mu, var):
@@ -825,13 +828,21 @@ def run_convergence(args):
                     B.pmf_predict(f, T)
                     l = B.pmf_last_substeps(f)
                     _, c, M, _, P = B.pmf_get_state(f)
+                    # time per predict of the same filter (the host waits for each)
+                    reps = []
+                    for _ in range(5):
+                        t0 = time.perf_counter()
+                        B.pmf_predict(f, T)
+                        B.pmf_stream_sync()
+                        reps.append(time.perf_counter() - t0)
                     B.pmf_destroy(f)
                     x = c[0] + M[0][0] * (np.arange(N) - N // 2)
                     ex = _gm_density(x, w, mu, var + T)
                     err = np.asarray(P, float) - ex
                     rows.append({"density": dname, "span": span, "N": N, "method": mname, "substeps": l,
                                  "max_rel_err": float(np.max(np.abs(err)) / np.max(ex)),
-                                 "l1_err": float(abs(M[0][0]) * np.sum(np.abs(err)))})
+                                 "l1_err": float(abs(M[0][0]) * np.sum(np.abs(err))),
+                                 "us_per_predict": 1e6 * float(np.median(reps))})
     B.pmf_ctx_destroy(ctx)
     # slope of log(error) against log(N) for the finite differences (second order: -2)
     slopes = {}
@@ -843,7 +854,13 @@ def run_convergence(args):
                 sl = np.polyfit(np.log([r["N"] for r in sel]), np.log([r["max_rel_err"] for r in sel]), 1)[0]
                 slopes[f"{dname}_span{span:g}_{meth}"] = float(sl)
     at = {f"{r['density']}_span{r['span']:g}_{r['method']}_N{r['N']}": r["max_rel_err"]
-          for r in rows if r["N"] in (80, 200)}
+          for r in rows if r["N"] in (80, 224)}
+    # time per predict, FDM (fast sine transform) against the spectral exact update
+    tcmp = {}
+    for N in CONV_N:
+        sel = {r["method"]: r["us_per_predict"] for r in rows if r["N"] == N and r["density"] == "gaussian"
+               and r["span"] == 8.0}
+        tcmp[str(N)] = {"fdm_dst_us": sel["fdm_dst"], "sd_exact_us": sel["sd_exact"], "sd_sine_us": sel["sd_sine"]}
     out = {"metric": "max relative error of one time update vs the heat kernel", "value": None,
            "unit": "relative error", "n_gpus": 1, "steps": len(rows), "warmup": 0, "ms_per_step": None,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -851,7 +868,7 @@ def run_convergence(args):
            "config": {"workload": "1-D, A = 0, D = 1, T = 0.05; Gaussian N(0, 0.3) and mixture "
                                   "0.3 N(-1.2, 0.15) + 0.4 N(0.3, 0.1) + 0.3 N(1.5, 0.2); spans 5 and 8 sigma",
                       "N": list(CONV_N)},
-           "fdm_slope_N100_up": slopes, "at_N80_N200": at, "rows": rows,
+           "fdm_slope_N100_up": slopes, "at_N80_N224": at, "us_per_predict": tcmp, "rows": rows,
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 

@@ -80,8 +80,10 @@ typedef struct {
     double A[16];               /* row-major nx x nx drift matrix */
     double Q[16];               /* row-major nx x nx noise gain; D = Q Q^T */
     int grid;                   /* PMF_GRID_FOURIER or PMF_GRID_CHEBYSHEV */
-    int N[4];                   /* points per axis.  Fourier: even, 2^a 3^b 5^c 17^d,
-                                   4..256.  Chebyshev: 4..256 */
+    int N[4];                   /* points per axis.  Fourier: even, 2^a 3^b 5^c 7^d
+                                   11^e 13^f 17^g, 4..256 (the fdm and sine
+                                   integrators also need 2 (N + 1) of that form).
+                                   Chebyshev: 4..256 */
     double span_sigmas;         /* grid half-width in standard deviations (e.g. 8) */
     double t_nominal;           /* interval used by the grid design, > 0 */
     int integrator;             /* PMF_INT_EXACT | _RK4 | _EULER | _FDM | _SINE
@@ -157,8 +159,9 @@ void pmf_destroy(pmf_filter* f);
  *   fdm:    the finite-difference baseline of Sec. III.B: l explicit steps of
  *           eq. FDM (step matrices of eq. fdiff per axis, the trace term inside),
  *           the nodes taken as interior nodes with zeros beyond both ends,
- *           computed by the sine-transform route of eq. FST: DST-I along every
- *           axis, the product over n of the step eigenvalues
+ *           computed by the sine-transform route of eq. FST: a fast DST-I (an
+ *           FFT of the odd extension, length 2 (N_a + 1)) along every axis, the
+ *           product over n of the step eigenvalues
  *           1 - h tr(A) + h sum_a D_y,aa(t_n) (cos(j_a pi / (N_a + 1)) - 1),
  *           DST-I back.  Needs diagonal A and D (Fourier grid; the designed
  *           grids are axis-aligned, so D_y stays diagonal);

@@ -171,7 +171,9 @@ static pmf_status validate_model(const pmf_model* m) {
         const int n = m->N[a];
         if (n < 4 || n > 256) return fail(PMF_E_INVALID, "N per axis must be 4..256");
         if (m->grid == PMF_GRID_FOURIER && (n % 2 != 0 || make_plan(n).np < 0))
-            return fail(PMF_E_INVALID, "Fourier N must be even and of the form 2^a 3^b 5^c 17^d");
+            return fail(PMF_E_INVALID, "Fourier N must be even and of the form 2^a 3^b 5^c 7^d 11^e 13^f 17^g");
+        if ((m->integrator == PMF_INT_FDM || m->integrator == PMF_INT_SINE) && make_plan(2 * (n + 1)).np < 0)
+            return fail(PMF_E_INVALID, "the sine transform needs 2 (N + 1) of the form 2^a 3^b 5^c 7^d 11^e 13^f 17^g");
         ntot *= n;
     }
     if (ntot > (1L << 24)) return fail(PMF_E_INVALID, "grid larger than 2^24 points");
@@ -378,8 +380,6 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     f->W = static_cast<double*>(A((size_t)model->nx * f->km.wstride * sizeof(double)));
     f->tab = static_cast<double*>(A((size_t)MS * TAB_STRIDE * sizeof(double)));
     f->desc = static_cast<DevDesc*>(A(sizeof(DevDesc)));
-    if (model->integrator == PMF_INT_FDM || model->integrator == PMF_INT_SINE)
-        f->D1 = A((size_t)MS * 256 * 256 * f->es);   // DST-I matrices
     if (model->grid == PMF_GRID_CHEBYSHEV) {
         f->D1 = A((size_t)3 * 256 * 256 * f->es);
         f->D2 = A((size_t)3 * 256 * 256 * f->es);
@@ -405,26 +405,6 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     if (e != hipSuccess) {
         pmf_destroy(f);
         return hip_fail(e, "upload tables");
-    }
-    if (model->integrator == PMF_INT_FDM || model->integrator == PMF_INT_SINE) {
-        std::vector<double> sall((size_t)MS * 256 * 256, 0.0);
-        for (int a = 0; a < model->nx; ++a) {
-            const int n = model->N[a];
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j)
-                    sall[(size_t)a * 256 * 256 + (size_t)i * n + j] =
-                        std::sin((double)(i + 1) * (j + 1) * M_PI / (double)(n + 1));
-        }
-        if (f->es == sizeof(double)) {
-            e = hipMemcpy(f->D1, sall.data(), sall.size() * 8, hipMemcpyHostToDevice);
-        } else {
-            std::vector<float> s32(sall.begin(), sall.end());
-            e = hipMemcpy(f->D1, s32.data(), s32.size() * 4, hipMemcpyHostToDevice);
-        }
-        if (e != hipSuccess) {
-            pmf_destroy(f);
-            return hip_fail(e, "upload sine-transform matrices");
-        }
     }
     if (model->grid == PMF_GRID_CHEBYSHEV) {
         std::vector<double> d1all((size_t)3 * 256 * 256, 0.0), d2all((size_t)3 * 256 * 256, 0.0);
@@ -535,13 +515,11 @@ pmf_status pmf_predict(pmf_filter* f, double T, void* stream) {
         void* t1 = f->buf[(f->cur + 1) % 4];
         void* t2 = f->buf[(f->cur + 2) % 4];
         if (f->es == sizeof(double))
-            e = launch_predict_fdm<double>(f->km, f->desc, f->coef, static_cast<const double*>(f->D1),
-                                           static_cast<double*>(f->buf[f->cur]), static_cast<double*>(t1),
-                                           static_cast<double*>(t2), trA, sine, st);
+            e = launch_predict_fdm<double>(f->km, f->desc, f->coef, static_cast<double*>(f->buf[f->cur]),
+                                           static_cast<double*>(t1), static_cast<double*>(t2), trA, sine, st);
         else
-            e = launch_predict_fdm<float>(f->km, f->desc, f->coef, static_cast<const float*>(f->D1),
-                                          static_cast<float*>(f->buf[f->cur]), static_cast<float*>(t1),
-                                          static_cast<float*>(t2), trA, sine, st);
+            e = launch_predict_fdm<float>(f->km, f->desc, f->coef, static_cast<float*>(f->buf[f->cur]),
+                                          static_cast<float*>(t1), static_cast<float*>(t2), trA, sine, st);
         if (e != hipSuccess) return hip_fail(e, "predict (finite differences)");
         return PMF_OK;
     }

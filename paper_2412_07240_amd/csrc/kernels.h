@@ -48,10 +48,11 @@ template <typename T>
 hipError_t launch_scale_etr(T* q, int ntot, const DevDesc* d, hipStream_t st);
 
 // finite-difference baseline by the sine-transform route, or (sine != 0) the
-// sine-series variant of the spectral update (S: DST-I matrices per axis, 256 x
-// 256 stride); t1, t2: two scratch densities; result in X
+// sine-series variant of the spectral update, with the fast sine transform (DST-I
+// through an FFT of length 2 (N_a + 1) per axis); t1, t2: two scratch densities;
+// result in X
 template <typename T>
-hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, const T* S, T* X, T* t1, T* t2,
+hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, T* X, T* t1, T* t2,
                               double trA, int sine, hipStream_t st);
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int ntot, hipStream_t st);

@@ -98,8 +98,8 @@ template <typename C, typename T> __device__ inline void dft5(C* a, int s) {
     a[3] = csub(m2, r2);
 }
 
-// R-point DFT by the definition (odd prime R without a factored butterfly, here
-// 17 for N = 34): the R roots of unity once, then X_k = sum_r a_r w^{(r k) mod R}
+// R-point DFT by the definition (odd prime R without a factored butterfly: 7, 11,
+// 13, 17): the R roots of unity once, then X_k = sum_r a_r w^{(r k) mod R}
 template <typename C, typename T, int R> __device__ inline void dft_direct(C* a, int s) {
     C w[R];
 #pragma unroll
@@ -151,11 +151,43 @@ __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* ou
         if (R == 4) dft4<C, T>(v, sign);
         if (R == 8) dft8<C, T>(v, sign);
         if (R == 5) dft5<C, T>(v, sign);
+        if (R == 7) dft_direct<C, T, 7>(v, sign);
+        if (R == 11) dft_direct<C, T, 11>(v, sign);
+        if (R == 13) dft_direct<C, T, 13>(v, sign);
         if (R == 17) dft_direct<C, T, 17>(v, sign);
         const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
     }
+}
+
+// All passes of an n-point transform of ntl lines held in LDS (A, ping-ponging
+// with B); returns the buffer holding the result.  Every thread must call it.
+template <typename T>
+__device__ typename V2<T>::t* fft_passes(typename V2<T>::t* A, typename V2<T>::t* B, int n, int ntl, int pitch,
+                                         int sign, const FftPlan& plan) {
+    using C = typename V2<T>::t;
+    int Ns = 1;
+    C* in = A;
+    C* out = B;
+    for (int p = 0; p < plan.np; ++p) {
+        const int R = plan.r[p];
+        if (R == 8) stockham_pass<T, 8>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 4) stockham_pass<T, 4>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 3) stockham_pass<T, 3>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 5) stockham_pass<T, 5>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 7) stockham_pass<T, 7>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 11) stockham_pass<T, 11>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 13) stockham_pass<T, 13>(in, out, n, Ns, ntl, pitch, sign);
+        else if (R == 17) stockham_pass<T, 17>(in, out, n, Ns, ntl, pitch, sign);
+        else stockham_pass<T, 2>(in, out, n, Ns, ntl, pitch, sign);
+        __syncthreads();
+        C* tmp = in;
+        in = out;
+        out = tmp;
+        Ns *= R;
+    }
+    return in;
 }
 
 // ------------------------------------------------------------------ FFT along one axis
@@ -194,23 +226,7 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
         A[t * pitch + k] = v;
     }
     __syncthreads();
-    int Ns = 1;
-    C* in = A;
-    C* out = B;
-    for (int p = 0; p < plan.np; ++p) {
-        const int R = plan.r[p];
-        if (R == 8) stockham_pass<T, 8>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 4) stockham_pass<T, 4>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 3) stockham_pass<T, 3>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 5) stockham_pass<T, 5>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 17) stockham_pass<T, 17>(in, out, n, Ns, ntl, pitch, sign);
-        else stockham_pass<T, 2>(in, out, n, Ns, ntl, pitch, sign);
-        __syncthreads();
-        C* tmp = in;
-        in = out;
-        out = tmp;
-        Ns *= R;
-    }
+    const C* in = fft_passes<T>(A, B, n, ntl, pitch, sign, plan);
     for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
         int t, k;
         size_t addr;
@@ -227,6 +243,59 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
         const C v = in[t * pitch + k];
         if (rdst) rdst[addr] = v.x;
         else X[addr] = v;
+    }
+}
+
+// ------------------------------------------------------------------ DST-I along one axis
+// The fast sine transform of eq. FST in O(N log N): X_k = sum_{j=1..N} x_j sin(pi j k /
+// (N + 1)), k = 1..N, from the DFT of the odd extension of each line to length
+// L = 2 (N + 1) (y_0 = y_{N+1} = 0, y_j = x_j, y_{L-j} = -x_j): DFT(y)_k = -2i X_k.
+// Lines as in k_fft_axis (element j of line (o, i) at o*N*s + i + j*s); each
+// block transforms TL lines in LDS with the same Stockham passes.
+template <typename T>
+__global__ void k_dst1_axis(const T* src, T* dst, int n, int s, int nlines, FftPlan plan, int TL) {
+    using C = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char smem_dst[];
+    const int L = 2 * (n + 1), pitch = L + 1;
+    C* A = reinterpret_cast<C*>(smem_dst);
+    C* B = A + TL * pitch;
+    const int L0 = blockIdx.x * TL;
+    const int ntl = min(TL, nlines - L0);
+    for (int e = threadIdx.x; e < ntl * L; e += blockDim.x) {
+        int t, k;
+        if (s == 1) {
+            t = e / L;
+            k = e - t * L;
+        } else {
+            t = e % ntl;
+            k = e / ntl;
+        }
+        // position k of the extension: x_k for 1 <= k <= n, -x_{L-k} for n+2 <= k < L, else 0
+        const int j = (k >= 1 && k <= n) ? k : (k >= n + 2 ? L - k : 0);
+        T v = (T)0;
+        if (j) {
+            const int Ln = L0 + t;
+            const T x = src[(size_t)(Ln / s) * n * s + (Ln % s) + (size_t)(j - 1) * s];
+            v = (k <= n) ? x : -x;
+        }
+        C c;
+        c.x = v;
+        c.y = (T)0;
+        A[t * pitch + k] = c;
+    }
+    __syncthreads();
+    const C* Y = fft_passes<T>(A, B, L, ntl, pitch, -1, plan);
+    for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
+        int t, k;
+        if (s == 1) {
+            t = e / n;
+            k = e - t * n;
+        } else {
+            t = e % ntl;
+            k = e / ntl;
+        }
+        const int Ln = L0 + t;
+        dst[(size_t)(Ln / s) * n * s + (Ln % s) + (size_t)k * s] = (T)(-0.5) * Y[t * pitch + k + 1].y;
     }
 }
 
@@ -1226,29 +1295,46 @@ __global__ void k_fdm_gain(T* X, KModel m, const DevDesc* d, const double* coef,
 }
 
 template <typename T>
-hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, const T* S, T* X, T* t1, T* t2,
+hipError_t launch_dst1_axis(const KModel& m, int a, const T* src, T* dst, hipStream_t st) {
+    const int n = m.N[a];
+    const int L = 2 * (n + 1);
+    int s = 1;
+    for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
+    const int nlines = m.ntot / n;
+    // lines per block: about 2048 extended points, both LDS buffers within 64 KiB
+    const int cap = (int)(65536 / (2 * (size_t)(L + 1) * sizeof(typename V2<T>::t)));
+    int TL = 2048 / L;
+    if (TL > cap) TL = cap;
+    if (TL < 1) TL = 1;
+    if (TL > nlines) TL = nlines;
+    const size_t lds = 2 * (size_t)TL * (L + 1) * sizeof(typename V2<T>::t);
+    const FftPlan plan = make_plan(L);
+    hipLaunchKernelGGL(k_dst1_axis<T>, dim3(cdiv(nlines, TL)), dim3(256), lds, st, src, dst, n, s, nlines, plan, TL);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* coef, T* X, T* t1, T* t2,
                               double trA, int sine, hipStream_t st) {
     const int g = cdiv(m.ntot, 256);
-    int strides[MS];
-    for (int a = 0; a < m.nx; ++a) {
-        int s = 1;
-        for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
-        strides[a] = s;
-    }
-    T* cur = X;
-    for (int a = 0; a < m.nx; ++a) {
+    hipError_t e = hipSuccess;
+    // forward sine transform along every axis: X -> t1 -> t2 -> ...
+    const T* cur = X;
+    for (int a = 0; a < m.nx && e == hipSuccess; ++a) {
         T* dst = (cur == t1) ? t2 : t1;
-        hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, S + (size_t)a * 256 * 256, cur, dst, m.N[a],
-                           strides[a], m.ntot, coef, -1, 1.0, 0);
+        e = launch_dst1_axis<T>(m, a, cur, dst, st);
         cur = dst;
     }
-    hipLaunchKernelGGL(k_fdm_gain<T>, dim3(g), dim3(256), 0, st, cur, m, d, coef, trA, sine);
-    for (int a = 0; a < m.nx; ++a) {
+    if (e != hipSuccess) return e;
+    T* spec = const_cast<T*>(cur);
+    hipLaunchKernelGGL(k_fdm_gain<T>, dim3(g), dim3(256), 0, st, spec, m, d, coef, trA, sine);
+    // back along every axis (the DST-I is its own inverse up to the factors the gain carries), ending in X
+    for (int a = 0; a < m.nx && e == hipSuccess; ++a) {
         T* dst = (a == m.nx - 1) ? X : ((cur == t1) ? t2 : t1);
-        hipLaunchKernelGGL(k_axis_mm<T>, dim3(g), dim3(256), 0, st, S + (size_t)a * 256 * 256, cur, dst, m.N[a],
-                           strides[a], m.ntot, coef, -1, 1.0, 0);
+        e = launch_dst1_axis<T>(m, a, cur, dst, st);
         cur = dst;
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -1265,7 +1351,7 @@ hipError_t launch_predict_fdm(const KModel& m, const DevDesc* d, const double* c
                                            T*, T*, T*, hipStream_t);                                         \
     template hipError_t launch_rk4_stage<T>(T*, T*, const T*, T*, int, const DevDesc*, int, hipStream_t);   \
     template hipError_t launch_scale_etr<T>(T*, int, const DevDesc*, hipStream_t);                           \
-    template hipError_t launch_predict_fdm<T>(const KModel&, const DevDesc*, const double*, const T*, T*, T*, T*, \
+    template hipError_t launch_predict_fdm<T>(const KModel&, const DevDesc*, const double*, T*, T*, T*,      \
                                               double, int, hipStream_t);                                       \
     template hipError_t launch_copy<T>(T*, const T*, int, hipStream_t);
 

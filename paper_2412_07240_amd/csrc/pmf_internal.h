@@ -307,6 +307,9 @@ PMF_HD FftPlan make_plan(int n) {
     while (n % 2 == 0) { p.r[p.np++] = 2; n /= 2; }
     while (n % 3 == 0) { p.r[p.np++] = 3; n /= 3; }
     while (n % 5 == 0 && p.np < 9) { p.r[p.np++] = 5; n /= 5; }
+    while (n % 7 == 0 && p.np < 9) { p.r[p.np++] = 7; n /= 7; }
+    while (n % 11 == 0 && p.np < 9) { p.r[p.np++] = 11; n /= 11; }
+    while (n % 13 == 0 && p.np < 9) { p.r[p.np++] = 13; n /= 13; }
     while (n % 17 == 0 && p.np < 9) { p.r[p.np++] = 17; n /= 17; }
     if (n != 1) p.np = -1;
     return p;

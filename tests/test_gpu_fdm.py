@@ -1,8 +1,9 @@
-"""Finite-difference baseline (sine-transform route of eq. FST), the sine-series
-variant of the spectral update, and the radix-5 FFT sizes they are compared at
-(N = 80, 200 in the convergence study), HIP path vs the FP64 oracle through the
-C ABI.  Same bars as the other parity tests: L1 <=
-1e-10 (FP64), <= 1e-5 per cycle in lockstep (FP32)."""
+"""Finite-difference baseline (sine-transform route of eq. FST, with the fast sine
+transform: an FFT of the odd extension of length 2 (N + 1) per axis), the
+sine-series variant of the spectral update, and the FFT radices their sizes need
+(5, 7, 11, 13, 17), HIP path vs the FP64 oracle (dense sine matrices, dense DFT)
+through the C ABI.  Same bars as the other parity tests: L1 <= 1e-10 (FP64),
+<= 1e-5 per cycle in lockstep (FP32)."""
 import numpy as np
 import pytest
 
@@ -46,8 +47,40 @@ def test_fdm_1d_n80(B, ctx):
 
 
 def test_fdm_2d(B, ctx):
-    note("case: finite differences 2-D N=(48,40) FP64, 3 cycles")
-    run_free(B, ctx, _diag_scenario(2, (48, 40), 3), 3, 1e-10, what="fdm2d")
+    note("case: finite differences 2-D N=(48,50) FP64, 3 cycles (extensions 98 = 2 7^2, 102 = 2 3 17)")
+    run_free(B, ctx, _diag_scenario(2, (48, 50), 3), 3, 1e-10, what="fdm2d")
+
+
+@pytest.mark.parametrize("N", [90, 120, 224])
+def test_fdm_1d_fast_sine_transform_sizes(B, ctx, N):
+    # odd extensions of length 182 = 2 7 13, 242 = 2 11^2, 450 = 2 3^2 5^2
+    note(f"case: config1 recipe, finite differences, N={N} (sine transform by an FFT of length {2 * (N + 1)}), FP64")
+    sc = W.config1(K=3, N=N)
+    sc.model = sc.model.with_(integrator=W.INT_FDM)
+    run_free(B, ctx, sc, 3, 1e-10, what=f"fdm1d-{N}")
+
+
+def test_sine_1d_n168(B, ctx):
+    note("case: config1 recipe, sine-series update, N=168 (FFT of length 338 = 2 13^2), FP64")
+    sc = W.config1(K=3, N=168)
+    sc.model = sc.model.with_(integrator=W.INT_SINE)
+    run_free(B, ctx, sc, 3, 1e-10, what="sine1d-168")
+
+
+@pytest.mark.parametrize("N", [22, 26, 98])
+def test_radix_7_11_13_exact_1d(B, ctx, N):
+    note(f"case: config1 recipe, exact integrator, N={N} (radix-7/11/13 FFT passes), FP64")
+    sc = W.config1(K=3, N=N)
+    sc.model = sc.model.with_(integrator=W.INT_EXACT)
+    run_free(B, ctx, sc, 3, 1e-10, what=f"radix-{N}")
+
+
+def test_fdm_refuses_sizes_without_a_fast_sine_transform(B, ctx):
+    # 2 (40 + 1) = 82 = 2 41: no radix plan for the odd extension
+    sc = W.config1(K=1, N=40)
+    with pytest.raises(B.PmfError) as e:
+        B.pmf_create(ctx, sc.model.with_(integrator=W.INT_FDM), sc.prior)
+    assert e.value.status == B.PMF_E_INVALID
 
 
 def test_fdm_3d(B, ctx):
