@@ -251,16 +251,23 @@ pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int* launches);
 
 /* ------------------------------------------------------------------ serving
  * Many independent tracks (one filter each) fed by an asynchronous stream of
- * requests.  A native worker thread takes rounds: in each round every idle track
- * contributes the head of its FIFO; a track whose head is predict(T) followed by
- * update(z) and that pmf_batch_step accepts (Fourier, FP32, nx <= 2, the sizes
- * listed there) runs that pair as one fused cycle, batched with the other tracks
- * of the round that have the same T; every other op runs alone through
- * pmf_predict / pmf_update on one of a few HIP streams.  Ops of one track run in
- * submission order; results equal the direct calls on the same filter.  The
- * server owns its tracks' filters.  A server's functions may be called from any
- * thread; the filters of its tracks must not be used directly while ops of theirs
- * are queued or running. */
+ * requests, served by continuous batching: a native worker thread puts the next
+ * op of every idle track with queued ops on the device as soon as the track is
+ * free, without waiting for the work already running (finished work is found by
+ * event queries).  A track whose FIFO starts with predict(T) followed by update(z)
+ * and that pmf_batch_step accepts (Fourier, FP32, nx <= 2, the sizes listed
+ * there) runs that pair as one fused cycle, batched with the other such tracks
+ * taken in the same pass that have the same T (up to 4 fused batches on the
+ * device at once); every other op runs alone through pmf_predict / pmf_update on
+ * one of 4 HIP streams, concurrently with the fused batches.  One op (or fused
+ * pair) of a track is on the device at a time, so a track's ops run in submission
+ * order; results equal the direct calls on the same filter (fused pairs: bit for
+ * bit equal to pmf_batch_step of the filter alone).  Admission: a track that
+ * does not fit the server's device-memory budget waits (its ops are queued)
+ * until pmf_server_remove_track frees memory; waiting tracks are admitted in the
+ * order they were added.  The server owns its tracks' filters.  A server's
+ * functions may be called from any thread; the filters of its tracks must not be
+ * used directly while ops of theirs are queued or running. */
 typedef struct pmf_server pmf_server;
 
 typedef enum { PMF_OP_PREDICT = 0, PMF_OP_UPDATE = 1 } pmf_op;
@@ -276,9 +283,13 @@ typedef struct {
 } pmf_completion;
 
 typedef struct {
-    size_t budget_bytes, used_bytes;   /* device bytes of the tracks' filters */
-    int tracks;
-    long long submitted, completed, rounds, fused_ops, single_ops;
+    size_t budget_bytes, used_bytes;   /* device bytes of the admitted tracks' filters */
+    int tracks;                        /* admitted tracks */
+    int waiting_tracks;                /* tracks waiting for memory */
+    long long submitted, completed;
+    long long rounds;                  /* worker passes that put work on the device */
+    long long fused_ops, single_ops;
+    long long admitted_late;           /* tracks admitted after waiting */
 } pmf_server_stats;
 
 /* Server on ctx with a device-memory budget for its tracks (admission control)
@@ -288,11 +299,17 @@ pmf_status pmf_server_create(pmf_ctx* ctx, size_t budget_bytes, int max_tracks, 
 /* Blocks until every submitted op has completed, then frees the tracks. */
 void pmf_server_destroy(pmf_server* s);
 
-/* New track: creates its filter (as pmf_create).  PMF_E_NOMEM, with nothing
- * kept, when its device bytes would exceed the budget or max_tracks are live. */
+/* New track (the model is validated as pmf_create does).  If its device bytes
+ * fit the budget and no earlier track is waiting, its filter is created now;
+ * otherwise the track waits for memory: *track is set and ops may be submitted
+ * to it, and it is created (and its ops run) once removals free enough memory.
+ * PMF_E_NOMEM, with nothing kept, when max_tracks tracks are live or its device
+ * bytes exceed the whole budget.  A waiting track whose creation then fails has
+ * its queued ops completed with that error. */
 pmf_status pmf_server_add_track(pmf_server* s, const pmf_model* model, const pmf_prior* prior, int* track);
 
-/* Removes an idle track (PMF_E_BUSY while it has queued or running ops). */
+/* Removes an idle (or waiting) track (PMF_E_BUSY while it has queued or running
+ * ops), then admits waiting tracks that now fit. */
 pmf_status pmf_server_remove_track(pmf_server* s, int track);
 
 /* Queue one op: PMF_OP_PREDICT over T (z unused) or PMF_OP_UPDATE with z[0..nz)
@@ -306,13 +323,14 @@ pmf_status pmf_server_submit_cycle(pmf_server* s, int track, double T, const dou
 /* Move up to cap completions (oldest first) into out; *n = how many. */
 pmf_status pmf_server_poll(pmf_server* s, pmf_completion* out, int cap, int* n);
 
-/* Block until every op submitted so far has completed. */
+/* Block until every op submitted so far has completed (ops of tracks still
+ * waiting for memory excepted). */
 pmf_status pmf_server_drain(pmf_server* s);
 
 pmf_status pmf_server_stats_get(pmf_server* s, pmf_server_stats* out);
 
 /* The filter of an idle track, for pmf_get_state / pmf_moments (NULL if the
- * track does not exist). */
+ * track does not exist or waits for memory). */
 pmf_filter* pmf_server_filter(pmf_server* s, int track);
 
 /* Device pointer of the density (for zero-copy inspection in tests); valid until

@@ -58,8 +58,9 @@ class pmf_completion(C.Structure):
 
 class pmf_server_stats(C.Structure):
     _fields_ = [("budget_bytes", C.c_size_t), ("used_bytes", C.c_size_t), ("tracks", C.c_int),
-                ("submitted", C.c_longlong), ("completed", C.c_longlong), ("rounds", C.c_longlong),
-                ("fused_ops", C.c_longlong), ("single_ops", C.c_longlong)]
+                ("waiting_tracks", C.c_int), ("submitted", C.c_longlong), ("completed", C.c_longlong),
+                ("rounds", C.c_longlong), ("fused_ops", C.c_longlong), ("single_ops", C.c_longlong),
+                ("admitted_late", C.c_longlong)]
 
 
 class PmfError(RuntimeError):

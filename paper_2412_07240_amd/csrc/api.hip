@@ -220,6 +220,8 @@ static pmf_status validate_model(const pmf_model* m) {
     return PMF_OK;
 }
 
+pmf_status check_model(const pmf_model* m) { return validate_model(m); }
+
 static pmf_status validate_prior(const pmf_prior* p, int nx) {
     if (!p) return fail(PMF_E_INVALID, "prior is NULL");
     if (p->ncomp < 1 || p->ncomp > MAXMIX) return fail(PMF_E_INVALID, "prior ncomp must be 1..4");
@@ -306,6 +308,28 @@ static void fill_tables(const pmf_model& m, std::vector<double>& tab) {
     }
 }
 
+
+// Device bytes pmf_create allocates for a (validated) model, in the same order and
+// sizes; the server admits tracks by it before creating them.
+size_t filter_device_bytes(const pmf_model& model) {
+    KModel km{};
+    double Wn[MSQ];
+    build_kmodel(model, km, Wn);
+    const size_t es = model.precision == PMF_FP64 ? sizeof(double) : sizeof(float);
+    const size_t ntot = (size_t)km.ntot;
+    int chunk = 1024, nb = (km.ntot + chunk - 1) / chunk;
+    if (nb > MAX_RED_BLOCKS) nb = MAX_RED_BLOCKS;
+    size_t b = 4 * ntot * es;
+    if (model.grid == PMF_GRID_FOURIER) b += ntot * es * 2;
+    b += (size_t)nb * NPART * sizeof(double) + (size_t)nb * sizeof(double);
+    b += (size_t)(2 * LMAX + 1) * PACK * sizeof(double);
+    b += (size_t)model.nx * km.wstride * sizeof(double);
+    b += (size_t)MS * TAB_STRIDE * sizeof(double);
+    b += sizeof(DevDesc);
+    if (model.grid == PMF_GRID_CHEBYSHEV) b += 2 * (size_t)3 * 256 * 256 * es + 5 * ntot * es;
+    return b;
+}
+
 }  // namespace pmf
 
 using namespace pmf;
@@ -341,6 +365,7 @@ void pmf_ctx_destroy(pmf_ctx* ctx) {
     for (hipEvent_t ev : ctx->ev_pool) (void)hipEventDestroy(ev);
     delete ctx;
 }
+
 
 pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* prior, pmf_filter** out) {
     if (!ctx || !out) return fail(PMF_E_INVALID, "ctx/out is NULL");
@@ -395,6 +420,10 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     if (!okalloc) {
         pmf_destroy(f);
         return fail(PMF_E_NOMEM, "device allocation failed");
+    }
+    if (f->bytes != filter_device_bytes(*model) + (f->dconst ? fused_const_bytes() : 0)) {
+        pmf_destroy(f);
+        return fail(PMF_E_DEVICE, "device footprint differs from filter_device_bytes (library error)");
     }
     f->cur = 0;
 

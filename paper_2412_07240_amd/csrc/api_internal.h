@@ -76,6 +76,12 @@ void batch_cache_release(pmf_ctx* ctx);
 void batch_forget_filter(pmf_ctx* ctx, pmf_filter* f);
 hipError_t batch_leave(pmf_filter* f);
 bool batch_fusable(const pmf_filter* f, std::string* why);
+bool model_fusable(const pmf_model& m, std::string* why);
+// device bytes pmf_create allocates for a validated model (without the fused-step
+// constants, which fusable filters add: fused_const_bytes)
+size_t filter_device_bytes(const pmf_model& model);
+// validation of a model as pmf_create does it (PMF_OK or the error it returns)
+pmf_status check_model(const pmf_model* model);
 // bytes of a filter's fused-step constants (its record f->dconst; allocated at
 // create for every filter the fused kernel accepts)
 size_t fused_const_bytes();

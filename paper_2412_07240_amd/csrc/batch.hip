@@ -1561,8 +1561,9 @@ static hipError_t batch_enter(pmf_filter* f) {
     return hipSuccess;
 }
 
-bool batch_fusable(const pmf_filter* f, std::string* why) {
-    const pmf_model& m = f->model;
+bool batch_fusable(const pmf_filter* f, std::string* why) { return model_fusable(f->model, why); }
+
+bool model_fusable(const pmf_model& m, std::string* why) {
     if (m.grid != PMF_GRID_FOURIER) return *why = "Chebyshev grid", false;
     if (m.precision != PMF_FP32) return *why = "FP64 density", false;
     if (m.integrator == PMF_INT_FDM || m.integrator == PMF_INT_SINE)
@@ -1741,16 +1742,18 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
 
 struct DynBatch {
     int cap = 0;                     // filters the buffers hold
-    pmf::BItem* d_items = nullptr;
-    pmf::GItem* d_groups = nullptr;
-    pmf::FPlan* d_plans = nullptr;
-    double* d_z = nullptr;
-    double* d_ll = nullptr;
+    pmf::FPlan* d_plans = nullptr;   // device
     int* d_ctr = nullptr;
-    pmf::BItem* h_items = nullptr;   // pinned staging
+    // mapped pinned host memory, read (items, groups, z) and written (log-likelihoods)
+    // by the kernels in place: a served batch is two launches, no copies
+    pmf::BItem* h_items = nullptr;
     pmf::GItem* h_groups = nullptr;
     double* h_z = nullptr;
     double* h_ll = nullptr;
+    pmf::BItem* m_items = nullptr;   // the same memory as the device addresses it
+    pmf::GItem* m_groups = nullptr;
+    double* m_z = nullptr;
+    double* m_ll = nullptr;
     bool attr = false;
     int ncu = 0;
     std::map<size_t, int> per_cu;    // resident fused workgroups per CU, by LDS size
@@ -1759,24 +1762,17 @@ struct DynBatch {
 namespace pmf {
 
 static void dyn_free_buffers(pmf_ctx* ctx, DynBatch* db) {
-    ctx_free(ctx, db->d_items, nullptr);
-    ctx_free(ctx, db->d_groups, nullptr);
     ctx_free(ctx, db->d_plans, nullptr);
-    ctx_free(ctx, db->d_z, nullptr);
-    ctx_free(ctx, db->d_ll, nullptr);
     ctx_free(ctx, db->d_ctr, nullptr);
     if (db->h_items) (void)hipHostFree(db->h_items);
     if (db->h_groups) (void)hipHostFree(db->h_groups);
     if (db->h_z) (void)hipHostFree(db->h_z);
     if (db->h_ll) (void)hipHostFree(db->h_ll);
-    db->d_items = nullptr;
-    db->d_groups = nullptr;
     db->d_plans = nullptr;
-    db->d_z = db->d_ll = nullptr;
     db->d_ctr = nullptr;
-    db->h_items = nullptr;
-    db->h_groups = nullptr;
-    db->h_z = db->h_ll = nullptr;
+    db->h_items = db->m_items = nullptr;
+    db->h_groups = db->m_groups = nullptr;
+    db->h_z = db->h_ll = db->m_z = db->m_ll = nullptr;
     db->cap = 0;
 }
 
@@ -1818,20 +1814,18 @@ static pmf_status dyn_reserve(pmf_ctx* ctx, DynBatch* db, int n) {
         if (!p) ok = false;
         return p;
     };
-    db->d_items = static_cast<BItem*>(A(sizeof(BItem) * cap));
-    db->d_groups = static_cast<GItem*>(A(sizeof(GItem) * cap));
     db->d_plans = static_cast<FPlan*>(A(sizeof(FPlan) * cap));
-    db->d_z = static_cast<double*>(A(sizeof(double) * 3 * cap));
-    db->d_ll = static_cast<double*>(A(sizeof(double) * cap));
     db->d_ctr = static_cast<int*>(A(sizeof(int)));
     hipError_t e = hipSuccess;
-    if (ok) e = hipHostMalloc(reinterpret_cast<void**>(&db->h_items), sizeof(BItem) * cap, hipHostMallocDefault);
-    if (ok && e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&db->h_groups), sizeof(GItem) * cap, hipHostMallocDefault);
-    if (ok && e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&db->h_z), sizeof(double) * 3 * cap, hipHostMallocDefault);
-    if (ok && e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&db->h_ll), sizeof(double) * cap, hipHostMallocDefault);
+    auto H = [&](void** h, void** m, size_t bytes) {
+        if (e != hipSuccess) return;
+        e = hipHostMalloc(h, bytes, hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(m, *h, 0);
+    };
+    H(reinterpret_cast<void**>(&db->h_items), reinterpret_cast<void**>(&db->m_items), sizeof(BItem) * cap);
+    H(reinterpret_cast<void**>(&db->h_groups), reinterpret_cast<void**>(&db->m_groups), sizeof(GItem) * cap);
+    H(reinterpret_cast<void**>(&db->h_z), reinterpret_cast<void**>(&db->m_z), sizeof(double) * 3 * cap);
+    H(reinterpret_cast<void**>(&db->h_ll), reinterpret_cast<void**>(&db->m_ll), sizeof(double) * cap);
     if (!ok || e != hipSuccess) {
         dyn_free_buffers(ctx, db);
         return fail(PMF_E_NOMEM, "served batch allocation failed");
@@ -1896,21 +1890,18 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
         it = db->per_cu.emplace(lds, pc).first;
     }
     const int grid = std::min(ng, it->second * db->ncu);
+    // the staging set is written in place (the caller reuses a set only after the
+    // launch that read it has completed); the kernels read it, and write the
+    // log-likelihoods, through its mapped device addresses
     std::memcpy(db->h_items, sorted.data(), sizeof(BItem) * n);
     std::memcpy(db->h_groups, groups.data(), sizeof(GItem) * ng);
     for (int q = 0; q < n; ++q)   // rows in item order
         std::memcpy(db->h_z + (size_t)q * 3, z + (size_t)sorted[q].idx * 3, sizeof(double) * 3);
-    e = hipMemcpyAsync(db->d_items, db->h_items, sizeof(BItem) * n, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(db->d_groups, db->h_groups, sizeof(GItem) * ng, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(db->d_z, db->h_z, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "served batch upload");
-    hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st, db->d_items, db->d_plans, n, db->d_z,
-                       nullptr, 3, db->d_ctr);
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, db->d_groups, ng, db->d_items,
-                       db->d_plans, db->d_ctr, db->d_z, 3, db->d_ll, maxcplx);
+    hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st,
+                       db->m_items, db->d_plans, n, db->m_z, nullptr, 3, db->d_ctr);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, db->m_groups, ng, db->m_items,
+                       db->d_plans, db->d_ctr, db->m_z, 3, db->m_ll, maxcplx);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(db->h_ll, db->d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "served batch launch");
     return PMF_OK;
 }
