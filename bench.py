@@ -127,6 +127,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip latency / L1 / plain-path legs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: keep the default fused schedules instead of timing the variants per size")
+    ap.add_argument("--sched-cache", type=str, default=None,
+                    help="batched: JSON schedule cache (read when its device/runtime/build key matches)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain device copy of known size (counter scaling)")
     ap.add_argument("--workload", choices=("batched", "cheb3d", "serve", "single", "convergence", "ct4d"),
@@ -179,6 +183,16 @@ def run_batched(args):
     for i, sc in enumerate(scs):
         Z[:, i, :] = sc.z
     ctx = B.pmf_ctx_create(0)
+    sched_report = None
+    if not args.no_autotune:
+        # per-size schedule of the fused kernel, timed on synthetic filters of each
+        # size (about the count of that size in this batch), before the timed region
+        log("bench: autotuning the fused kernel's schedules for this batch's mix of sizes")
+        mix = {N: sum(1 for sc in scs if sc.model.N[0] == N) for N in W.BATCH_SIZES}
+        sched_report = B.pmf_autotune(ctx, mix, 10, args.sched_cache)
+        for line in sched_report.strip().splitlines():
+            log("  " + line)
+    schedules = {f"{N}x{N}": B.pmf_get_schedule(ctx, 2, N) for N in W.BATCH_SIZES}
     log("bench: creating filters")
     fs = [B.pmf_create(ctx, sc.model, sc.prior) for sc in scs]
     fa = B.FilterArray(fs)
@@ -222,7 +236,11 @@ def run_batched(args):
         "config": {"workload": f"batched: {nf} independent 2-D filters, N x N with N uniform in "
                                "{32,48,64,96,128}, exact integrator, linear-Gaussian update, "
                                "planning kernel + one fused persistent launch per step",
-                   "filters": nf, "points_per_step": pts, "T": T, "reductions": "f64"},
+                   "filters": nf, "points_per_step": pts, "T": T, "reductions": "f64",
+                   "schedules": schedules,
+                   "autotune": None if args.no_autotune else
+                   "pmf_autotune on a synthetic batch with this batch's mix of sizes: coordinate descent "
+                   "over sizes, 10 timed steps x 3 rounds per variant, kept if >= 1 % faster"},
     }
     traffic = None
     valu = None

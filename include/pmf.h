@@ -135,8 +135,11 @@ typedef struct {
 typedef struct pmf_ctx pmf_ctx;
 typedef struct pmf_filter pmf_filter;
 
-/* Context bound to one HIP device.  `a` may be NULL (hipMalloc/hipFree).
- * The allocator struct is copied. */
+/* Context bound to one HIP device.  `a` may be NULL (hipMalloc/hipFree); else
+ * every device allocation of the context's filters and batches goes through
+ * a->alloc / a->free (e.g. a framework's caching allocator), which may be called
+ * from the calling thread or from a server's threads.  The allocator struct is
+ * copied. */
 pmf_status pmf_ctx_create(int device, const pmf_allocator* a, pmf_ctx** out);
 void pmf_ctx_destroy(pmf_ctx* ctx);
 
@@ -190,7 +193,11 @@ pmf_status pmf_predict(pmf_filter* f, double T, void* stream);
  * unchanged and sets PMF_E_DEGENERATE in its status word. */
 pmf_status pmf_update(pmf_filter* f, const double* z, double* loglik, void* stream);
 
-/* Mean (nx) and covariance (row-major nx x nx) of the current density, FP64.
+/* Mean (nx) and covariance (row-major nx x nx) of the current density, FP64: the
+ * first two moments of the point-mass density (the moment relations of Sec. II.A;
+ * the estimates whose errors Sec. VI reports as RMSE and ASTD), as node sums with
+ * the grid's integration weights (point masses on a Fourier grid, Clenshaw-Curtis
+ * weights on a Chebyshev grid).
  * Synchronises `stream`.  Returns the status word collected since the last
  * synchronising call (PMF_E_DEGENERATE and/or PMF_W_BOUNDARY bits) and clears it. */
 pmf_status pmf_moments(pmf_filter* f, double* mean, double* cov, void* stream);
@@ -248,6 +255,46 @@ pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* filters, int 
  * launches since the previous call, then clears them.  Diagnostic. */
 pmf_status pmf_batch_profile(pmf_ctx* ctx, int enable);
 pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int* launches);
+
+/* Schedule autotuning of the fused batched step.  The fused kernel carries
+ * compile-time schedule variants per 2-D grid size N x N (N in 32, 48, 64, 96,
+ * 128): 0 the default; bit 0 (1) half the filters per workgroup (offered where
+ * more than one fits); bit 1 (2) the radix passes of the column transforms in
+ * reverse order (offered where that changes the radix plan).  All variants
+ * compute the same cycle and differ in rounding only (the radix order; the rows
+ * each thread sums in the FP64 reductions, which follow the filters per
+ * workgroup).  1-D sizes have the default only.  A context starts with variant
+ * 0 everywhere.
+ *
+ * pmf_autotune: tunes the variants for a mix of 2-D sizes.  counts[0..4] (NULL:
+ * 1024 each) are the numbers of filters of size 32, 48, 64, 96 and 128 per axis
+ * in the batches the caller will step (0..65536 each, at least one filter in
+ * all).  The tuner creates that many synthetic fusable filters (a sheared
+ * stable drift, a linear measurement of both components, exact integrator,
+ * FP32) and times `steps` (1..1000) batched steps of the whole mix with HIP
+ * events around the fused kernel, after two untimed steps.  Starting from the
+ * defaults it takes the sizes present, largest first, and for each times every
+ * offered variant on the mix (three rounds, each variant's fastest mean kept),
+ * keeping the fastest if it beats the default by at least 1 % (one pass of
+ * coordinate descent).  The choice stays in the context: later pmf_batch_step,
+ * pmf_batch_step_noalloc and server batches of the context use it.
+ * cache_path: NULL, or a JSON file.  If it exists and its "key" matches this
+ * device (architecture, compute units), HIP runtime version, library build and
+ * mix, its "schedules" are taken and nothing is timed; else the mix is timed
+ * and the file is written (replaced).  report: NULL, or a buffer of report_len
+ * bytes for a text summary (one line per size).  Synchronous; creates and
+ * destroys its synthetic filters, drops the context's cached batch set-up and
+ * clears the pmf_batch_profile timings; on failure the context's schedules are
+ * left as they were.  Not to be called while other threads use the context. */
+pmf_status pmf_autotune(pmf_ctx* ctx, const int* counts, int steps, const char* cache_path, char* report,
+                        size_t report_len);
+
+/* Schedule variant used for nx-D grids of N points per axis (nx = 1 or 2, a size
+ * pmf_batch_step accepts; else PMF_E_INVALID).  pmf_set_schedule accepts only a
+ * variant offered for that size (see pmf_autotune) and drops the context's
+ * cached batch set-up when the variant changes. */
+pmf_status pmf_get_schedule(pmf_ctx* ctx, int nx, int N, int* variant);
+pmf_status pmf_set_schedule(pmf_ctx* ctx, int nx, int N, int variant);
 
 /* ------------------------------------------------------------------ serving
  * Many independent tracks (one filter each) fed by an asynchronous stream of

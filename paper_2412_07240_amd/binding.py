@@ -79,10 +79,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2412_07240_amd.build` (hipcc, gfx950)")
+        # torch's wheel carries its own HIP runtime under the system runtime's
+        # soname.  Loaded first, it is the one copy libpmf.so binds to; loaded
+        # after libpmf.so, it would be a second runtime in the process, and the
+        # second of two runtimes to initialise finds no GPU.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
         sig = {
-            "pmf_ctx_create": (ip, [ip, vp, C.POINTER(vp)]),
+            "pmf_ctx_create": (ip, [ip, C.POINTER(pmf_allocator), C.POINTER(vp)]),
             "pmf_ctx_destroy": (None, [vp]),
             "pmf_create": (ip, [vp, C.POINTER(pmf_model), C.POINTER(pmf_prior), C.POINTER(vp)]),
             "pmf_destroy": (None, [vp]),
@@ -99,6 +104,9 @@ def lib():
             "pmf_stream_sync": (ip, [vp]),
             "pmf_batch_profile": (ip, [vp, ip]),
             "pmf_batch_kernel_time": (ip, [vp, dp, C.POINTER(C.c_int)]),
+            "pmf_autotune": (ip, [vp, C.POINTER(C.c_int), ip, C.c_char_p, C.c_char_p, C.c_size_t]),
+            "pmf_get_schedule": (ip, [vp, ip, ip, C.POINTER(C.c_int)]),
+            "pmf_set_schedule": (ip, [vp, ip, ip, ip]),
             "pmf_last_error": (C.c_char_p, []),
             "pmf_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
             "pmf_server_destroy": (None, [vp]),
@@ -122,7 +130,7 @@ def lib():
 EXPORTED = ("pmf_ctx_create", "pmf_ctx_destroy", "pmf_create", "pmf_destroy", "pmf_predict",
             "pmf_update", "pmf_moments", "pmf_sync_status", "pmf_last_substeps", "pmf_get_state",
             "pmf_set_state", "pmf_batch_step", "pmf_batch_step_noalloc", "pmf_density_ptr", "pmf_stream_sync", "pmf_batch_profile",
-            "pmf_batch_kernel_time", "pmf_last_error", "pmf_server_create", "pmf_server_destroy",
+            "pmf_batch_kernel_time", "pmf_autotune", "pmf_get_schedule", "pmf_set_schedule", "pmf_last_error", "pmf_server_create", "pmf_server_destroy",
             "pmf_server_add_track", "pmf_server_remove_track", "pmf_server_submit", "pmf_server_submit_cycle", "pmf_server_poll",
             "pmf_server_drain", "pmf_server_stats_get", "pmf_server_filter")
 
@@ -207,14 +215,61 @@ def make_prior(spec, nx: int) -> pmf_prior:
     return p
 
 
-def pmf_ctx_create(device: int = 0):
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class pmf_allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+_ctx_allocators = {}   # context -> (allocator struct, callbacks): kept alive with the context
+
+
+def torch_allocator(device: int = 0, counter: dict | None = None):
+    """A pmf_allocator whose calls go to PyTorch's caching allocator on `device`
+    (torch.cuda.caching_allocator_alloc / caching_allocator_delete).  counter, if
+    given, counts the calls ("alloc", "free", "bytes")."""
+    import torch
+
+    def _alloc(nbytes, user, stream):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), device=device)
+        except RuntimeError:
+            return None
+        if counter is not None:
+            counter["alloc"] = counter.get("alloc", 0) + 1
+            counter["bytes"] = counter.get("bytes", 0) + int(nbytes)
+        return p
+
+    def _free(ptr, user, stream):
+        if ptr:
+            torch.cuda.caching_allocator_delete(int(ptr))
+            if counter is not None:
+                counter["free"] = counter.get("free", 0) + 1
+
+    fa, ff = _ALLOC_FN(_alloc), _FREE_FN(_free)
+    return pmf_allocator(fa, ff, None), (fa, ff)
+
+
+def pmf_ctx_create(device: int = 0, allocator=None):
+    """allocator: None (hipMalloc / hipFree), "torch" (PyTorch's caching allocator)
+    or a (pmf_allocator, callbacks) pair as torch_allocator returns."""
     out = C.c_void_p()
-    _check(lib().pmf_ctx_create(device, None, C.byref(out)))
+    if allocator is None:
+        _check(lib().pmf_ctx_create(device, None, C.byref(out)))
+        return out
+    if allocator == "torch":
+        allocator = torch_allocator(device)
+    a, keep = allocator
+    _check(lib().pmf_ctx_create(device, C.byref(a), C.byref(out)))
+    _ctx_allocators[out.value] = (a, keep)
     return out
 
 
 def pmf_ctx_destroy(ctx) -> None:
     lib().pmf_ctx_destroy(ctx)
+    _ctx_allocators.pop(getattr(ctx, "value", ctx), None)
 
 
 def pmf_create(ctx, model, prior):
@@ -362,6 +417,33 @@ def pmf_batch_kernel_time(ctx):
     n = C.c_int(0)
     _check(lib().pmf_batch_kernel_time(ctx, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+TUNE_SIZES = (32, 48, 64, 96, 128)
+
+
+def pmf_autotune(ctx, counts=None, steps: int = 10, cache_path=None) -> str:
+    """Tune the fused kernel's schedule variants for a mix of 2-D sizes: counts
+    maps N (32, 48, 64, 96, 128) to the number of N x N filters in the caller's
+    batches (None: 1024 each); or read the schedules from the JSON cache at
+    cache_path.  Returns the library's text report."""
+    arr = None
+    if counts is not None:
+        arr = (C.c_int * 5)(*[int(counts.get(N, 0)) for N in TUNE_SIZES])
+    buf = C.create_string_buffer(4096)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().pmf_autotune(ctx, arr, int(steps), path, buf, len(buf)))
+    return buf.value.decode()
+
+
+def pmf_get_schedule(ctx, nx: int, N: int) -> int:
+    v = C.c_int(0)
+    _check(lib().pmf_get_schedule(ctx, int(nx), int(N), C.byref(v)))
+    return v.value
+
+
+def pmf_set_schedule(ctx, nx: int, N: int, variant: int) -> None:
+    _check(lib().pmf_set_schedule(ctx, int(nx), int(N), int(variant)))
 
 
 # ------------------------------------------------------------------ serving

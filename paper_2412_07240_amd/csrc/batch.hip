@@ -10,6 +10,8 @@
 //   store.
 // HBM traffic per filter: the density read once and written once.
 #include <algorithm>
+#include <cstdio>
+#include <string>
 #include <map>
 #include <mutex>
 #include <cstdint>
@@ -555,6 +557,21 @@ constexpr int radix_at(int n, int i) {
     }
     return i < k ? r[i] : 0;
 }
+// The radix plan of schedule variant alt: 0 the plan above, 1 the same radices in
+// reverse order (the Stockham passes take any order)
+constexpr int radix_at_v(int n, int i, int alt) {
+    if (alt == 0) return radix_at(n, i);
+    int k = 0;
+    while (radix_at(n, k) != 0) ++k;
+    return i < k ? radix_at(n, k - 1 - i) : 0;
+}
+constexpr bool plan_has_alt(int n) {
+    int k = 0;
+    while (radix_at(n, k) != 0) ++k;
+    for (int i = 0; i < k; ++i)
+        if (radix_at_v(n, i, 1) != radix_at(n, i)) return true;
+    return false;
+}
 constexpr int num_passes(int n) {
     int k = 0;
     while (radix_at(n, k) != 0) ++k;
@@ -624,17 +641,17 @@ __device__ inline void cpass(const float2* __restrict__ in, float2* __restrict__
     }
 }
 
-template <int N, int NL, int LS, int ES, int SIGN, bool LF, int GAP = 0, int P = 0, int NS = 1>
+template <int N, int NL, int LS, int ES, int SIGN, bool LF, int GAP = 0, int ALT = 0, int P = 0, int NS = 1>
 __device__ inline float2* cfft(float2* in, float2* out, const float2* tw) {
     static_assert(GAP == 0 || LS == 1, "gapped lines are unit-stride");
     static_assert(plan_product(N) == N, "the radix plan multiplies out to the transform length");
     if constexpr (P == num_passes(N)) {
         return in;
     } else {
-        constexpr int R = radix_at(N, P);
+        constexpr int R = radix_at_v(N, P, ALT);
         cpass<R, N, NS, NL, LS, ES, SIGN, LF, GAP>(in, out, tw);
         __syncthreads();
-        return cfft<N, NL, LS, ES, SIGN, LF, GAP, P + 1, NS * R>(out, in, tw);
+        return cfft<N, NL, LS, ES, SIGN, LF, GAP, ALT, P + 1, NS * R>(out, in, tw);
     }
 }
 
@@ -894,7 +911,7 @@ __device__ inline float mode_gain(const GainC& c, const double* cf, float a2, fl
 typedef __attribute__((address_space(1))) const float cgfloat;
 typedef __attribute__((address_space(1))) const unsigned long long cgu64;   // a complex pair
 
-template <int N0, int N1, int NX, int G, int TYPE>
+template <int N0, int N1, int NX, int G, int TYPE, int ALT>
 __device__ __noinline__ void process_group(const BItem* __restrict__ items, const FPlan* __restrict__ plans,
                                            const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out,
                                            int bufcplx) {
@@ -1032,7 +1049,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     cur = oth;
     oth = (cur == bufA) ? bufB : bufA;
     if constexpr (NX == 2) {
-        cur = cfft<N0, G * H1, 1, SPITCH, -1, true, H1>(cur, oth, twc);
+        cur = cfft<N0, G * H1, 1, SPITCH, -1, true, H1, ALT>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
     // ---- per-mode gain with 1/(N0 N1) of the unnormalised transforms.  2-D: the
@@ -1123,7 +1140,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
     __syncthreads();
     // ---- inverse: columns, rows (c2r)
     if constexpr (NX == 2) {
-        cur = cfft<N0, G * H1, 1, SPITCH, +1, true, H1>(cur, oth, twc);
+        cur = cfft<N0, G * H1, 1, SPITCH, +1, true, H1, ALT>(cur, oth, twc);
         oth = (cur == bufA) ? bufB : bufA;
     }
     // Merge of the half spectra X into the N1/2-point inverse inputs Z, per pair
@@ -1370,6 +1387,16 @@ constexpr int group_g() {
     return G;
 }
 
+// Schedule variants of a group type (2 bits): bit 0 halves the filters per
+// workgroup (when more than one fits), bit 1 reverses the radix order of the
+// column transforms (when that changes the plan).  The autotuner picks one per
+// type; 0 is the default.
+constexpr int SCHED_HALF_G = 1, SCHED_COL_ALT = 2, NSCHED = 4;
+template <int N0, int N1>
+constexpr int group_g_v(int v) {
+    return (v & SCHED_HALF_G) && group_g<N0, N1>() > 1 ? group_g<N0, N1>() / 2 : group_g<N0, N1>();
+}
+
 __global__ void __launch_bounds__(FUSED_THREADS)
 k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__ items,
         const FPlan* __restrict__ plans, int* ctr, const double* __restrict__ zall, int nzmax,
@@ -1392,24 +1419,34 @@ k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__
         const int type = __builtin_amdgcn_readfirstlane(pmf_gi.type);
         __syncthreads();
         if (it >= ngroups) break;
-#define PMF_GROUP(T, N0, N1, NX) \
-    case T: process_group<N0, N1, NX, group_g<N0, N1>(), T>(items, plans, zall, nzmax, ll_out, bufcplx); break;
+        // group record type = base type * NSCHED + schedule variant
+#define PMF_GROUP_V(T, N0, N1, NX, V)                                                                       \
+    case T * NSCHED + V:                                                                                    \
+        process_group<N0, N1, NX, group_g_v<N0, N1>(V), T, (V & SCHED_COL_ALT) ? 1 : 0>(items, plans, zall, \
+                                                                                        nzmax, ll_out, bufcplx); \
+        break;
+#define PMF_GROUP_2D(T, N)           \
+    PMF_GROUP_V(T, N, N, 2, 0)       \
+    PMF_GROUP_V(T, N, N, 2, 1)       \
+    PMF_GROUP_V(T, N, N, 2, 2)       \
+    PMF_GROUP_V(T, N, N, 2, 3)
         switch (type) {
-            PMF_GROUP(GT_2D_128, 128, 128, 2)
-            PMF_GROUP(GT_2D_96, 96, 96, 2)
-            PMF_GROUP(GT_2D_64, 64, 64, 2)
-            PMF_GROUP(GT_2D_48, 48, 48, 2)
-            PMF_GROUP(GT_2D_32, 32, 32, 2)
-            PMF_GROUP(GT_1D_256, 1, 256, 1)
-            PMF_GROUP(GT_1D_192, 1, 192, 1)
-            PMF_GROUP(GT_1D_128, 1, 128, 1)
-            PMF_GROUP(GT_1D_96, 1, 96, 1)
-            PMF_GROUP(GT_1D_64, 1, 64, 1)
-            PMF_GROUP(GT_1D_48, 1, 48, 1)
-            PMF_GROUP(GT_1D_32, 1, 32, 1)
+            PMF_GROUP_2D(GT_2D_128, 128)
+            PMF_GROUP_2D(GT_2D_96, 96)
+            PMF_GROUP_2D(GT_2D_64, 64)
+            PMF_GROUP_2D(GT_2D_48, 48)
+            PMF_GROUP_2D(GT_2D_32, 32)
+            PMF_GROUP_V(GT_1D_256, 1, 256, 1, 0)
+            PMF_GROUP_V(GT_1D_192, 1, 192, 1, 0)
+            PMF_GROUP_V(GT_1D_128, 1, 128, 1, 0)
+            PMF_GROUP_V(GT_1D_96, 1, 96, 1, 0)
+            PMF_GROUP_V(GT_1D_64, 1, 64, 1, 0)
+            PMF_GROUP_V(GT_1D_48, 1, 48, 1, 0)
+            PMF_GROUP_V(GT_1D_32, 1, 32, 1, 0)
             default: break;
         }
-#undef PMF_GROUP
+#undef PMF_GROUP_2D
+#undef PMF_GROUP_V
     }
 }
 
@@ -1438,13 +1475,31 @@ static int group_type(int nx, int n0, int n1) {
     return -1;
 }
 
-static int group_capacity(int type) {
+// the schedule variants offered for a group type (those that differ from the default)
+static bool sched_offered(int type, int v) {
+    if (v == 0) return true;
+    int gmax = 1;
+    bool alt = false;
     switch (type) {
-        case GT_2D_128: return group_g<128, 128>();
-        case GT_2D_96: return group_g<96, 96>();
-        case GT_2D_64: return group_g<64, 64>();
-        case GT_2D_48: return group_g<48, 48>();
-        case GT_2D_32: return group_g<32, 32>();
+        case GT_2D_128: gmax = group_g<128, 128>(); alt = plan_has_alt(128); break;
+        case GT_2D_96: gmax = group_g<96, 96>(); alt = plan_has_alt(96); break;
+        case GT_2D_64: gmax = group_g<64, 64>(); alt = plan_has_alt(64); break;
+        case GT_2D_48: gmax = group_g<48, 48>(); alt = plan_has_alt(48); break;
+        case GT_2D_32: gmax = group_g<32, 32>(); alt = plan_has_alt(32); break;
+        default: return false;   // 1-D types: the default schedule only
+    }
+    if ((v & SCHED_HALF_G) && gmax < 2) return false;
+    if ((v & SCHED_COL_ALT) && !alt) return false;
+    return true;
+}
+
+static int group_capacity(int type, int v) {
+    switch (type) {
+        case GT_2D_128: return group_g_v<128, 128>(v);
+        case GT_2D_96: return group_g_v<96, 96>(v);
+        case GT_2D_64: return group_g_v<64, 64>(v);
+        case GT_2D_48: return group_g_v<48, 48>(v);
+        case GT_2D_32: return group_g_v<32, 32>(v);
         case GT_1D_256: return group_g<1, 256>();
         case GT_1D_192: return group_g<1, 192>();
         case GT_1D_128: return group_g<1, 128>();
@@ -1593,8 +1648,10 @@ static int pow2_at_least(int v) {
 // grids first (the persistent workgroups take the longest work first).  Array
 // form without allocation: order (n ints) is working space, sorted receives the
 // items in group order, groups at most n records (*ngroups of them).  Ties keep
-// the input order.  Returns the largest complex LDS need of a group.
-static int group_items_arr(const BItem* items, int n, int* order, BItem* sorted, GItem* groups, int* ngroups) {
+// the input order.  sched (null: defaults) holds the schedule variant per group
+// type.  Returns the largest complex LDS need of a group.
+static int group_items_arr(const BItem* items, int n, int* order, BItem* sorted, GItem* groups, int* ngroups,
+                           const int* sched) {
     for (int i = 0; i < n; ++i) order[i] = i;
     std::sort(order, order + n, [&](int a, int b) {
         const long pa = (long)items[a].n0 * items[a].n1, pb = (long)items[b].n0 * items[b].n1;
@@ -1607,14 +1664,15 @@ static int group_items_arr(const BItem* items, int n, int* order, BItem* sorted,
     for (int q = 0; q < n;) {
         const BItem& b = items[order[q]];
         const int type = group_type(b.nx, b.n0, b.n1);
-        const int G = group_capacity(type);
+        const int v = sched && sched_offered(type, sched[type]) ? sched[type] : 0;
+        const int G = group_capacity(type, v);
         GItem gi;
         gi.first = q;
         gi.n0 = b.n0;
         gi.n1 = b.n1;
         gi.nx = b.nx;
         gi.seg = std::max(32, pow2_at_least(b.n1));
-        gi.type = type;
+        gi.type = type * NSCHED + v;
         gi.pad = 0;
         int cnt = 0;
         while (q < n && cnt < G && items[order[q]].n0 == b.n0 && items[order[q]].n1 == b.n1 &&
@@ -1631,13 +1689,14 @@ static int group_items_arr(const BItem* items, int n, int* order, BItem* sorted,
     return maxcplx;
 }
 
-static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sorted, std::vector<GItem>& groups) {
+static int group_items(const std::vector<BItem>& items, std::vector<BItem>& sorted, std::vector<GItem>& groups,
+                       const int* sched) {
     const int n = (int)items.size();
     std::vector<int> order(n);
     sorted.assign(n, BItem{});
     groups.assign(n, GItem{});
     int ng = 0;
-    const int maxcplx = group_items_arr(items.data(), n, order.data(), sorted.data(), groups.data(), &ng);
+    const int maxcplx = group_items_arr(items.data(), n, order.data(), sorted.data(), groups.data(), &ng, sched);
     groups.resize(ng);
     return maxcplx;
 }
@@ -1692,7 +1751,7 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     }
     std::vector<BItem> sorted;
     std::vector<GItem> groups;
-    const int maxcplx = group_items(items, sorted, groups);
+    const int maxcplx = group_items(items, sorted, groups, ctx->sched);
     c->ngroups = (int)groups.size();
     c->order.resize(n);
     for (int q = 0; q < n; ++q) c->order[q] = sorted[q].idx;
@@ -1878,7 +1937,7 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
     }
     std::vector<BItem> sorted;
     std::vector<GItem> groups;
-    const int maxcplx = group_items(items, sorted, groups);
+    const int maxcplx = group_items(items, sorted, groups, ctx->sched);
     const int ng = (int)groups.size();
     const size_t lds = fused_lds(maxcplx);
     auto it = db->per_cu.find(lds);
@@ -2041,6 +2100,263 @@ extern "C" pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int*
     return PMF_OK;
 }
 
+// ==================================================================== schedule autotuning
+// Each 2-D group type has up to four compile-time schedules (filters per
+// workgroup full or half, column radix order default or reversed).  The tuner
+// times them with the real kernels on a synthetic batch with the caller's mix of
+// sizes (the persistent launch balances all sizes together, so a size's best
+// schedule depends on the mix) and keeps the choice per type in the context; it
+// is cached as a small JSON file keyed by device, HIP runtime, library build and
+// mix.
+
+namespace pmf {
+
+static const int TUNE_N[5] = {32, 48, 64, 96, 128};
+static const char* const BUILD_STAMP = __DATE__ " " __TIME__;
+
+static std::string tune_key(int device) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return std::string();
+    int rt = 0;
+    if (hipRuntimeGetVersion(&rt) != hipSuccess) return std::string();
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "pmf-sched-1 arch=%s cus=%d hip=%d build=%s", p.gcnArchName,
+                  p.multiProcessorCount, rt, BUILD_STAMP);
+    return buf;
+}
+
+// the schedules of a cache file whose key matches, else false
+static bool tune_read(const char* path, const std::string& key, int* out) {
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return false;
+    std::string s;
+    char b[4096];
+    size_t r;
+    while ((r = std::fread(b, 1, sizeof b, fp)) > 0) s.append(b, r);
+    std::fclose(fp);
+    if (s.find("\"key\": \"" + key + "\"") == std::string::npos) return false;
+    const size_t sp = s.find("\"schedules\"");
+    if (sp == std::string::npos) return false;
+    for (int i = 0; i < 5; ++i) {
+        char name[32];
+        std::snprintf(name, sizeof name, "\"%dx%d\": ", TUNE_N[i], TUNE_N[i]);
+        const size_t q = s.find(name, sp);
+        int v = -1;
+        if (q == std::string::npos || std::sscanf(s.c_str() + q + std::strlen(name), "%d", &v) != 1) return false;
+        if (v < 0 || v >= NSCHED || !sched_offered(group_type(2, TUNE_N[i], TUNE_N[i]), v)) return false;
+        out[i] = v;
+    }
+    return true;
+}
+
+static bool tune_write(const char* path, const std::string& key, const int* sched, const double (*ms)[NSCHED],
+                       const int* mix, int steps) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "wb");
+    if (!fp) return false;
+    std::fprintf(fp, "{\n  \"key\": \"%s\",\n  \"mix\": [%d, %d, %d, %d, %d],\n  \"steps\": %d,\n  \"schedules\": {",
+                 key.c_str(), mix[0], mix[1], mix[2], mix[3], mix[4], steps);
+    for (int i = 0; i < 5; ++i) std::fprintf(fp, "%s\"%dx%d\": %d", i ? ", " : "", TUNE_N[i], TUNE_N[i], sched[i]);
+    std::fprintf(fp, "},\n  \"kernel_ms\": {");
+    for (int i = 0; i < 5; ++i) {
+        std::fprintf(fp, "%s\"%dx%d\": [", i ? ", " : "", TUNE_N[i], TUNE_N[i]);
+        for (int v = 0; v < NSCHED; ++v) {
+            if (ms[i][v] > 0.0) std::fprintf(fp, "%s%.6f", v ? ", " : "", ms[i][v]);
+            else std::fprintf(fp, "%snull", v ? ", " : "");
+        }
+        std::fprintf(fp, "]");
+    }
+    std::fprintf(fp, "}\n}\n");
+    const bool ok = std::fclose(fp) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+// one fusable synthetic 2-D filter of N x N points: sheared stable drift, linear
+// measurement of both components, exact integrator, FP32 density
+static void tune_model(int N, pmf_model* m, pmf_prior* p) {
+    std::memset(m, 0, sizeof *m);
+    std::memset(p, 0, sizeof *p);
+    m->nx = 2;
+    const double A[4] = {-0.5, 0.3, -0.2, -0.4};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) m->A[i * 2 + j] = A[i * 2 + j];
+    m->Q[0] = 0.5;
+    m->Q[3] = 0.8;
+    m->grid = PMF_GRID_FOURIER;
+    m->N[0] = m->N[1] = N;
+    m->span_sigmas = 8.0;
+    m->t_nominal = 0.05;
+    m->integrator = PMF_INT_EXACT;
+    m->substeps = 1;
+    m->precision = PMF_FP32;
+    m->interp = PMF_INTERP_AUTO;
+    m->meas_kind = PMF_H_LINEAR;
+    m->nz = 2;
+    m->H[0] = m->H[3] = 1.0;
+    m->noise_ncomp = 1;
+    m->noise_w[0] = 1.0;
+    m->noise_cov[0] = m->noise_cov[3] = 0.09;   // row-major nz x nz
+    p->ncomp = 1;
+    p->w[0] = 1.0;
+    p->cov[0] = p->cov[3] = 0.09;               // row-major nx x nx
+}
+
+}  // namespace pmf
+
+extern "C" pmf_status pmf_autotune(pmf_ctx* ctx, const int* counts, int steps, const char* cache_path, char* report,
+                                   size_t report_len) {
+    using namespace pmf;
+    if (!ctx) return fail(PMF_E_INVALID, "ctx is NULL");
+    int mix[5];
+    long total = 0;
+    for (int i = 0; i < 5; ++i) {
+        mix[i] = counts ? counts[i] : 1024;
+        if (mix[i] < 0 || mix[i] > 65536) return fail(PMF_E_INVALID, "filters per size must be in 0..65536");
+        total += mix[i];
+    }
+    if (total < 1) return fail(PMF_E_INVALID, "the mix has no filters");
+    if (steps < 1 || steps > 1000) return fail(PMF_E_INVALID, "steps must be in 1..1000");
+    if (report && report_len) report[0] = '\0';
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::string key = tune_key(ctx->device);
+    if (key.empty()) return fail(PMF_E_DEVICE, "device properties for the tuning key");
+    {
+        char mb[96];
+        std::snprintf(mb, sizeof mb, " mix=%d,%d,%d,%d,%d", mix[0], mix[1], mix[2], mix[3], mix[4]);
+        key += mb;
+    }
+    int chosen[5] = {};
+    double ms[5][NSCHED] = {};
+    std::string rep;
+    char line[256];
+    if (cache_path && tune_read(cache_path, key, chosen)) {
+        for (int i = 0; i < 5; ++i) ctx->sched[group_type(2, TUNE_N[i], TUNE_N[i])] = chosen[i];
+        batch_cache_release(ctx);
+        rep = std::string("schedules from ") + cache_path + ":";
+        for (int i = 0; i < 5; ++i) {
+            std::snprintf(line, sizeof line, " %dx%d:%d", TUNE_N[i], TUNE_N[i], chosen[i]);
+            rep += line;
+        }
+        rep += "\n";
+    } else {
+        const bool prof = ctx->profile;
+        int saved[16];
+        std::memcpy(saved, ctx->sched, sizeof saved);
+        pmf_status s = PMF_OK;
+        // the synthetic mix, all sizes in one batch
+        std::vector<pmf_filter*> fs;
+        for (int i = 0; i < 5 && s == PMF_OK; ++i) {
+            pmf_model m;
+            pmf_prior p;
+            tune_model(TUNE_N[i], &m, &p);
+            for (int k = 0; k < mix[i] && s == PMF_OK; ++k) {
+                pmf_filter* f = nullptr;
+                s = pmf_create(ctx, &m, &p, &f);
+                if (s == PMF_OK) fs.push_back(f);
+            }
+        }
+        const int n = (int)fs.size();
+        const double T = 0.05;
+        std::vector<double> z(2 * (size_t)std::max(n, 1), 0.0);
+        // mean fused-kernel time of the whole mix under the context's schedules
+        auto time_mix = [&](double* out) {
+            batch_cache_release(ctx);
+            ctx->profile = false;
+            for (int k = 0; k < 2 && s == PMF_OK; ++k) s = pmf_batch_step(ctx, fs.data(), n, T, z.data(), nullptr, nullptr);
+            ctx->profile = true;
+            ctx->ev_used = 0;
+            for (int k = 0; k < steps && s == PMF_OK; ++k)
+                s = pmf_batch_step(ctx, fs.data(), n, T, z.data(), nullptr, nullptr);
+            double tot = 0.0;
+            int nl = 0;
+            if (s == PMF_OK) s = pmf_batch_kernel_time(ctx, &tot, &nl);
+            if (s == PMF_OK && nl > 0) *out = std::min(*out, tot / nl);
+        };
+        for (int i = 0; i < 5; ++i) ctx->sched[group_type(2, TUNE_N[i], TUNE_N[i])] = 0;
+        // one pass of coordinate descent over the sizes present, largest first:
+        // each size's variants timed on the whole mix (three rounds, fastest mean
+        // kept); a variant replaces the current one only when at least 1 % faster
+        for (int i = 4; i >= 0 && s == PMF_OK; --i) {
+            const int N = TUNE_N[i];
+            const int type = group_type(2, N, N);
+            std::vector<int> offered;
+            for (int v = 0; v < NSCHED; ++v)
+                if (sched_offered(type, v)) offered.push_back(v);
+            if (mix[i] == 0 || offered.size() < 2) {
+                std::snprintf(line, sizeof line, "%dx%d: %s -> 0\n", N, N,
+                              mix[i] == 0 ? "not in the mix" : "one schedule");
+                rep = line + rep;
+                continue;
+            }
+            for (int v : offered) ms[i][v] = 1e300;
+            for (int r = 0; r < 3 && s == PMF_OK; ++r)
+                for (int v : offered) {
+                    if (s != PMF_OK) break;
+                    ctx->sched[type] = v;
+                    time_mix(&ms[i][v]);
+                }
+            if (s != PMF_OK) break;
+            int best = 0;
+            for (int v : offered)
+                if (ms[i][v] < ms[i][best]) best = v;
+            if (!(ms[i][best] < 0.99 * ms[i][0])) best = 0;
+            ctx->sched[type] = chosen[i] = best;
+            std::string l;
+            std::snprintf(line, sizeof line, "%dx%d (%d of %d filters), mix kernel:", N, N, mix[i], n);
+            l += line;
+            for (int v : offered) {
+                std::snprintf(line, sizeof line, " v%d %.4f ms", v, ms[i][v]);
+                l += line;
+            }
+            std::snprintf(line, sizeof line, " -> %d\n", best);
+            rep = l + line + rep;
+        }
+        batch_cache_release(ctx);
+        for (pmf_filter* f : fs) pmf_destroy(f);
+        ctx->profile = prof;
+        ctx->ev_used = 0;
+        if (s != PMF_OK) {
+            std::memcpy(ctx->sched, saved, sizeof saved);
+            return s;
+        }
+        for (int i = 0; i < 5; ++i)
+            for (int v = 0; v < NSCHED; ++v)
+                if (ms[i][v] >= 1e300) ms[i][v] = 0.0;
+        if (cache_path && !tune_write(cache_path, key, chosen, ms, mix, steps))
+            return fail(PMF_E_INVALID, std::string("cannot write the schedule cache ") + cache_path);
+    }
+    if (report && report_len) {
+        const size_t k = std::min(report_len - 1, rep.size());
+        std::memcpy(report, rep.data(), k);
+        report[k] = '\0';
+    }
+    return PMF_OK;
+}
+
+extern "C" pmf_status pmf_get_schedule(pmf_ctx* ctx, int nx, int N, int* variant) {
+    using namespace pmf;
+    if (!ctx || !variant) return fail(PMF_E_INVALID, "NULL argument");
+    const int type = group_type(nx, nx == 2 ? N : 1, N);
+    if (type < 0) return fail(PMF_E_INVALID, "no fused form for this grid size");
+    *variant = sched_offered(type, ctx->sched[type]) ? ctx->sched[type] : 0;
+    return PMF_OK;
+}
+
+extern "C" pmf_status pmf_set_schedule(pmf_ctx* ctx, int nx, int N, int variant) {
+    using namespace pmf;
+    if (!ctx) return fail(PMF_E_INVALID, "ctx is NULL");
+    const int type = group_type(nx, nx == 2 ? N : 1, N);
+    if (type < 0) return fail(PMF_E_INVALID, "no fused form for this grid size");
+    if (variant < 0 || variant >= NSCHED || !sched_offered(type, variant))
+        return fail(PMF_E_INVALID, "schedule variant not offered for this grid size");
+    if (ctx->sched[type] != variant) {
+        ctx->sched[type] = variant;
+        batch_cache_release(ctx);
+    }
+    return PMF_OK;
+}
+
 // ==================================================================== step without allocation
 // pmf_batch_step_noalloc: the same planning and fused kernels, with their
 // per-step records (items, groups, plans, z, log-likelihoods, work counter) in a
@@ -2152,7 +2468,7 @@ extern "C" pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* fi
         b.n1 = f->model.nx == 2 ? f->model.N[1] : f->model.N[0];
     }
     int ng = 0;
-    const int maxcplx = group_items_arr(na_items, n, na_order, na_sorted, na_groups, &ng);
+    const int maxcplx = group_items_arr(na_items, n, na_order, na_sorted, na_groups, &ng, ctx->sched);
     // z rows in item order, stride 3 (the kernels' layout)
     for (int q = 0; q < n; ++q)
         for (int j = 0; j < 3; ++j)

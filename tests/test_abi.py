@@ -46,9 +46,9 @@ def test_struct_layouts_match_header_sizes():
     if cc is None:
         pytest.skip("no C compiler")
     from paper_2412_07240_amd import binding
-    src = ('#include "pmf.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu\\n",'
+    src = ('#include "pmf.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu %zu\\n",'
            'sizeof(pmf_model),sizeof(pmf_prior),sizeof(pmf_state_header),sizeof(pmf_completion),'
-           'sizeof(pmf_server_stats));return 0;}\n')
+           'sizeof(pmf_server_stats),sizeof(pmf_allocator));return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         open(c, "w").write(src)
@@ -58,4 +58,5 @@ def test_struct_layouts_match_header_sizes():
     assert [int(x) for x in out] == [ctypes.sizeof(binding.pmf_model), ctypes.sizeof(binding.pmf_prior),
                                      ctypes.sizeof(binding.pmf_state_header),
                                      ctypes.sizeof(binding.pmf_completion),
-                                     ctypes.sizeof(binding.pmf_server_stats)]
+                                     ctypes.sizeof(binding.pmf_server_stats),
+                                     ctypes.sizeof(binding.pmf_allocator)]

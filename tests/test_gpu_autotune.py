@@ -1,0 +1,194 @@
+"""Schedule variants of the fused kernel and the autotuner.
+
+Each offered variant of each 2-D size steps the same filters as the default
+schedule, each step within the per-step FP32 bar of the FP64 oracle from the
+same pre-step state (as the batched-step tests), and close to the default
+schedule's run: the variants change rounding only (the column radix order, and
+the rows per thread of the FP64 reductions, which follow the filters per
+workgroup).  Then the tuner: its
+choice is an offered variant, its JSON cache is keyed and read back without
+timing, and the allocation-free step under a tuned schedule equals
+pmf_batch_step."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_common import check_density, fp32_update_tol, note, update_amplification
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (32, 48, 64, 96, 128)
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2412_07240_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.pmf_ctx_create(0)
+    yield c
+    B.pmf_ctx_destroy(c)
+
+
+def zmat(scs, k):
+    z = np.zeros((len(scs), 2))
+    for i, sc in enumerate(scs):
+        z[i] = sc.z[k]
+    return z
+
+
+def offered(B, ctx, N):
+    out = []
+    for v in range(4):
+        try:
+            B.pmf_set_schedule(ctx, 2, N, v)
+            out.append(v)
+        except B.PmfError:
+            pass
+    B.pmf_set_schedule(ctx, 2, N, 0)
+    return out
+
+
+def run(B, ctx, scs, K, variant, check_every=0):
+    """K batched steps of fresh filters under the given schedule of their size;
+    every check_every-th filter's steps against the oracle.  Returns the final
+    states and log-likelihoods."""
+    N = scs[0].model.N[0]
+    B.pmf_set_schedule(ctx, 2, N, variant)
+    assert B.pmf_get_schedule(ctx, 2, N) == variant
+    fs = [B.pmf_create(ctx, sc.model, sc.prior) for sc in scs]
+    lls = []
+    worst = 0.0
+    try:
+        for k in range(K):
+            before = [B.pmf_get_state(f)[1:] for f in fs] if check_every else None
+            lls.append(B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, k), want_loglik=True))
+            for i in range(0, len(scs), check_every or len(scs) + 1):
+                sc = scs[i]
+                c, M, t, P = before[i]
+                st = oracle.State(np.array(c), np.array(M), t, np.asarray(P, float))
+                st, _ = oracle.predict(sc.model, st, sc.T)
+                amp = update_amplification(sc.model, st, sc.z[k])
+                st, ll_o, _, _, _ = oracle.update(sc.model, st, sc.z[k])
+                _, c2, M2, t2, P2 = B.pmf_get_state(fs[i])
+                e1, em, _, _ = check_density(sc.model, c2, M2, P2, st, fp32_update_tol(amp),
+                                             what=f"{N}x{N} variant {variant} step {k} filter {i}", designed=True)
+                worst = max(worst, e1, em)
+                if not np.isnan(ll_o):
+                    assert abs(lls[-1][i] - ll_o) <= 1e-4 * max(1.0, abs(ll_o)), (N, variant, k, i)
+        states = [B.pmf_get_state(f)[1:] for f in fs]
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+        B.pmf_set_schedule(ctx, 2, N, 0)
+    return states, np.array(lls), worst
+
+
+@pytest.mark.parametrize("N", SIZES)
+def test_schedule_variants(B, ctx, N):
+    vs = offered(B, ctx, N)
+    note(f"case: {N}x{N} schedule variants {vs}")
+    assert vs[0] == 0
+    # a ragged last group for every filters-per-workgroup choice
+    scs = [W.batched_filter(i, K=3, sizes=(N,)) for i in range(19)]
+    ref, ll_ref, w0 = run(B, ctx, scs, 3, 0, check_every=6)
+    for v in vs[1:]:
+        st, ll, w = run(B, ctx, scs, 3, v, check_every=6)
+        # rounding-level differences from the default run after three steps
+        assert np.allclose(ll, ll_ref, rtol=1e-4, atol=1e-4, equal_nan=True), (N, v)
+        dP = 0.0
+        for i, (a, b) in enumerate(zip(st, ref)):
+            assert np.allclose(a[0], b[0], rtol=0, atol=1e-3 * abs(np.diag(b[1])).max()), (N, v, i)
+            dP = max(dP, np.abs(a[3] - b[3]).max() / np.abs(b[3]).max())
+        assert dP <= 1e-3, (N, v, dP)
+        note(f"  variant {v}: worst sampled error vs oracle {w:.2e} (default {w0:.2e}); "
+             f"max density difference from the default run {dP:.1e} of the peak")
+    with pytest.raises(B.PmfError):
+        B.pmf_set_schedule(ctx, 2, N, 4)
+
+
+def test_schedule_arguments(B, ctx):
+    note("case: schedule and tuner arguments")
+    for bad in ({32: -1}, {N: 0 for N in SIZES}, {32: 65537}):
+        with pytest.raises(B.PmfError):
+            B.pmf_autotune(ctx, bad, 2)
+    with pytest.raises(B.PmfError):
+        B.pmf_autotune(ctx, {32: 4}, 0)
+    for bad in ((2, 40, 0), (3, 32, 0), (1, 64, 1), (2, 256, 0)):
+        with pytest.raises(B.PmfError):
+            B.pmf_set_schedule(ctx, *bad)
+    assert B.pmf_get_schedule(ctx, 1, 64) == 0
+    B.pmf_set_schedule(ctx, 1, 64, 0)
+
+
+def test_autotune_and_cache(B, tmp_path):
+    note("case: autotune a mix of 48 filters per size (none of 64 x 64), 2 steps, JSON cache")
+    ctx = B.pmf_ctx_create(0)
+    path = tmp_path / "sched.json"
+    mix = {32: 48, 48: 48, 64: 0, 96: 48, 128: 48}
+    try:
+        offers = {N: offered(B, ctx, N) for N in SIZES}
+        rep = B.pmf_autotune(ctx, mix, 2, str(path))
+        note("  " + rep.replace("\n", "\n  "))
+        data = json.loads(path.read_text())
+        assert data["key"].startswith("pmf-sched-1 arch=gfx950") and data["key"].endswith("mix=48,48,0,48,48")
+        assert data["mix"] == [mix[N] for N in SIZES]
+        for N in SIZES:
+            v = data["schedules"][f"{N}x{N}"]
+            assert v in offers[N] and B.pmf_get_schedule(ctx, 2, N) == v
+            times = data["kernel_ms"][f"{N}x{N}"]
+            if len(offers[N]) > 1 and mix[N] > 0:
+                timed = [t for t in times if t is not None]
+                assert len(timed) == len(offers[N]), (N, times)
+                # the fastest, when at least 1 % below the default; else the default
+                best = min(offers[N], key=lambda u: times[u])
+                assert v == (best if times[best] < 0.99 * times[0] else 0), (N, times, v)
+            else:
+                assert v == 0 and all(t is None for t in times), (N, times, v)
+        # read back from the cache by a new context: nothing timed, same schedules
+        ctx2 = B.pmf_ctx_create(0)
+        try:
+            rep2 = B.pmf_autotune(ctx2, mix, 2, str(path))
+            assert rep2.startswith("schedules from"), rep2
+            for N in SIZES:
+                assert B.pmf_get_schedule(ctx2, 2, N) == data["schedules"][f"{N}x{N}"]
+        finally:
+            B.pmf_ctx_destroy(ctx2)
+        # a cache with another key is timed again and rewritten
+        data["key"] = "another device"
+        path.write_text(json.dumps(data))
+        rep3 = B.pmf_autotune(ctx, mix, 1, str(path))
+        assert not rep3.startswith("schedules from")
+        assert json.loads(path.read_text())["key"].startswith("pmf-sched-1")
+    finally:
+        B.pmf_ctx_destroy(ctx)
+
+
+def test_noalloc_under_non_default_schedules(B):
+    note("case: no-allocation step with every size on its last offered variant")
+    ctx = B.pmf_ctx_create(0)
+    try:
+        for N in SIZES:
+            B.pmf_set_schedule(ctx, 2, N, offered(B, ctx, N)[-1])
+        scs = W.batched_workload(40, K=2)
+        fa = [B.pmf_create(ctx, sc.model, sc.prior) for sc in scs]
+        fb = [B.pmf_create(ctx, sc.model, sc.prior) for sc in scs]
+        try:
+            z = zmat(scs, 0)
+            ll_a = B.pmf_batch_step_noalloc(ctx, fa, scs[0].T, z)
+            ll_b = B.pmf_batch_step(ctx, fb, scs[0].T, z, want_loglik=True)
+            assert np.array_equal(ll_a, ll_b, equal_nan=True)
+            for f, g in zip(fa, fb):
+                assert np.array_equal(B.pmf_get_state(f)[4], B.pmf_get_state(g)[4])
+        finally:
+            for f in fa + fb:
+                B.pmf_destroy(f)
+    finally:
+        B.pmf_ctx_destroy(ctx)
