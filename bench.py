@@ -6,7 +6,8 @@ Workload (the batched configuration the throughput target is quoted on):
 [-1, 0]) and Q (diagonal in [0.05, 1]), grid N x N with N drawn uniformly from
 {32, 48, 64, 96, 128}, linear-Gaussian measurements, exact integrator, FP32
 densities with FP64 reductions; one step = predict(T = 0.05) + update(z) of every
-filter = a planning kernel and one fused persistent launch.
+filter = a planning kernel and one fused launch (a workgroup per group of same-size
+filters).
 
 Prints ONE JSON line.  `value` = grid points carried through one full cycle per
 second (whole job, inputs resident in HBM).  Also reported: the fused kernel's
@@ -235,7 +236,7 @@ def run_batched(args):
         "data": "synthetic",
         "config": {"workload": f"batched: {nf} independent 2-D filters, N x N with N uniform in "
                                "{32,48,64,96,128}, exact integrator, linear-Gaussian update, "
-                               "planning kernel + one fused persistent launch per step",
+                               "planning kernel + one fused launch per step (a workgroup per group of same-size filters)",
                    "filters": nf, "points_per_step": pts, "T": T, "reductions": "f64",
                    "schedules": schedules,
                    "autotune": None if args.no_autotune else

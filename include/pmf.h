@@ -236,7 +236,7 @@ pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, doubl
  * tight serving loops, harnesses that forbid allocation): pmf_batch_step without
  * any allocation.  Same arguments, filters and results as pmf_batch_step, at most
  * 4096 filters (more -> PMF_E_INVALID before anything runs).  The per-step
- * records (items, groups, plans, staged z, log-likelihoods, work counter; under
+ * records (items, groups, plans, staged z, log-likelihoods; under
  * 2 MiB) live in a file-scope device array that each GPU holds until the process
  * ends; the per-filter constants live in the filter (allocated by pmf_create).
  * No hipMalloc/hipFree or other allocating call is made.  Synchronous: returns

@@ -1,7 +1,8 @@
-// Batched predict + update: one persistent fused launch per step.
+// Batched predict + update: one fused launch per step.
 //
-// A workgroup takes the next filter of a work list (largest grid first) and runs
-// its whole cycle with the density resident in LDS:
+// A workgroup takes one group of same-size filters (groups in launch order,
+// largest grids first) and runs their whole cycle with the densities resident in
+// LDS:
 //   load -> row r2c FFT (N/2-point complex FFT + split) -> column FFT ->
 //   per-mode gain -> inverse column FFT -> row c2r (merge + N/2-point inverse) ->
 //   likelihood (FP64 log-likelihood, FP32 exp) with FP64 moment sums ->
@@ -420,17 +421,14 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ zs, int nzma
             if (q < nzmax) zd[q] = z[q];
 }
 
-// One thread per filter; thread 0 also clears the work counter of the fused
-// launch.  zsrc: the step's measurements, one row of nzmax per item in item
+// One thread per filter.  zsrc: the step's measurements, one row of nzmax per item in item
 // order (possibly in mapped host memory), so that its load needs no field of the
 // item; zdst (optional): device copy of them, same order, for the fused kernel.
 // Narrow workgroups spread the filters' latency-bound round trips over every
 // compute unit.
 __global__ void __launch_bounds__(PLAN_THREADS) k_batch_plan(const BItem* __restrict__ items, FPlan* __restrict__ plans, int n,
-                             const double* __restrict__ zsrc, double* __restrict__ zdst, int nzmax,
-                             int* __restrict__ ctr) {
+                             const double* __restrict__ zsrc, double* __restrict__ zdst, int nzmax) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *ctr = 0;
     if (i >= n) return;
     const BItem I = items[i];
     const double* zs = zsrc + (size_t)i * nzmax;
@@ -501,14 +499,15 @@ __device__ __noinline__ float trig_interp_1d(const float* Po, int n, double nu) 
     return (float)acc;
 }
 
-// cubic Lagrange weights through nodes -1, 0, 1, 2 at t in [0, 1)
+// cubic Lagrange weights through nodes -1, 0, 1, 2 at t in [0, 1]: each weight a
+// polynomial in t, sharing (t^2 - 1) / 6 (eleven operations).  At t = 0 they are
+// exactly (0, 1, 0, 0); at t = 1, (w0, 0, 1, 0) with |w0| one rounding of 1/3
 __device__ inline void cubic_weights(float t, float* w) {
-    const float tp = t + 1.f, tm = t - 1.f, tm2 = t - 2.f;
-    const float a = t * tm, d = tp * t;
-    w[0] = a * tm2 * (-1.f / 6.f);
-    w[1] = tp * tm * tm2 * 0.5f;
-    w[2] = d * tm2 * -0.5f;
-    w[3] = d * tm * (1.f / 6.f);
+    const float c = fmaf(t * t, 1.f / 6.f, -1.f / 6.f);             // (t^2 - 1) / 6
+    w[0] = t * fmaf(t, fmaf(t, -1.f / 6.f, 0.5f), -1.f / 3.f);      // -t (t - 1)(t - 2) / 6
+    w[1] = c * fmaf(t, 3.f, -6.f);                                   // (t + 1)(t - 1)(t - 2) / 2
+    w[2] = t * fmaf(t, fmaf(t, -0.5f, 0.5f), 1.f);                   // -(t + 1) t (t - 2) / 2
+    w[3] = t * c;                                                    // (t + 1) t (t - 1) / 6
 }
 
 // ---------------------------------------------------------------- the fused kernel
@@ -857,9 +856,7 @@ __device__ void filter_commit(const FState& F, double* ll_out) {
 extern __shared__ __align__(16) unsigned char pmf_fsm[];
 __shared__ FState pmf_FS[GMAX];
 __shared__ double pmf_slots[32 * 8 + GMAX * 8];
-__shared__ int pmf_item;
-__shared__ GItem pmf_gi;   // the group being processed, written by thread 0 of the kernel loop
-__shared__ int pmf_twtype; // group type whose twiddle tables the LDS holds (-1: none)
+__shared__ GItem pmf_gi;   // the workgroup's group, written by thread 0 at the start
 
 typedef __attribute__((address_space(1))) float gfloat;
 // The interval's gain constants of one filter, read once per thread from its
@@ -912,7 +909,7 @@ typedef __attribute__((address_space(1))) const float cgfloat;
 typedef __attribute__((address_space(1))) const unsigned long long cgu64;   // a complex pair
 
 template <int N0, int N1, int NX, int G, int TYPE, int ALT>
-__device__ __noinline__ void process_group(const BItem* __restrict__ items, const FPlan* __restrict__ plans,
+__device__ __forceinline__ void process_group(const BItem* __restrict__ items, const FPlan* __restrict__ plans,
                                            const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out,
                                            int bufcplx) {
     // the group's first item and size, uniform (scalar registers; no per-thread copy)
@@ -962,28 +959,24 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
         FS[tid].zrow = zall + (size_t)(GI.first + gg) * nzmax;
         FS[tid].idx = idx;
     }
-    // twiddle tables of this group type, unless the previous group of this
-    // workgroup left them (the tables sit after both buffers, at a fixed place)
-    if (__builtin_amdgcn_readfirstlane(pmf_twtype) != TYPE) {
-        for (int i = tid; i < H1; i += NT) {
+    // twiddle tables of this group type (after both buffers)
+    for (int i = tid; i < H1; i += NT) {
+        float sn, cs;
+        sincospif(-2.0f * i / H1, &sn, &cs);
+        twr[i] = make_float2(cs, sn);
+    }
+    if (NX == 2)
+        for (int i = tid; i < N0; i += NT) {
             float sn, cs;
-            sincospif(-2.0f * i / H1, &sn, &cs);
-            twr[i] = make_float2(cs, sn);
+            sincospif(-2.0f * i / N0, &sn, &cs);
+            twc[i] = make_float2(cs, sn);
         }
-        if (NX == 2)
-            for (int i = tid; i < N0; i += NT) {
-                float sn, cs;
-                sincospif(-2.0f * i / N0, &sn, &cs);
-                twc[i] = make_float2(cs, sn);
-            }
-        for (int i = tid; i <= H1; i += NT) {
-            float sn, cs;
-            sincospif(-2.0f * i / N1, &sn, &cs);
-            twp[i] = make_float2(cs, sn);
-        }
+    for (int i = tid; i <= H1; i += NT) {
+        float sn, cs;
+        sincospif(-2.0f * i / N1, &sn, &cs);
+        twp[i] = make_float2(cs, sn);
     }
     __syncthreads();
-    if (tid == 0) pmf_twtype = TYPE;
 
     // ---- load: super-row L = r*G + g holds row r of filter g as complex pairs.
     // Every load of the thread is issued before the first wait: the addresses are
@@ -1312,7 +1305,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                     // taps outside the grid are zero: columns -1 and N1 read the zero
                     // pad floats, rows -1 and N0 the zero guard rows (without GUARD
                     // they get weight zero and read rows 0 and N0 - 1 instead)
-                    const float* q = Pog + i0 * RSO + (i1 - 1);
+                    const float* q = Pog + __umul24(i0, RSO) + (i1 - 1);
                     const bool top = !GUARD && i0 == 0, bot = !GUARD && i0 == N0 - 2;
                     if (top) w0[0] = 0.f;
                     if (bot) w0[3] = 0.f;
@@ -1327,6 +1320,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
             };
             if constexpr (FLAT) {
                 constexpr int STEP = RPS * SEGW;
+#pragma unroll 2
                 for (int p = tr * SEGW + j; p < N0 * N1; p += STEP) {
                     const int r = p / N1, c = p - r * N1;
                     const double u0 = (double)r - half0, u1 = (double)c - half1;
@@ -1340,6 +1334,7 @@ __device__ __noinline__ void process_group(const BItem* __restrict__ items, cons
                 double nu0 = F.amap[0] * ((double)tr - half0) + F.amap[1] * uj + F.bmap[0];
                 double nu1 = F.amap[2] * ((double)tr - half0) + F.amap[3] * uj + F.bmap[1];
                 const double dn0 = F.amap[0] * RPS, dn1 = F.amap[2] * RPS;
+#pragma unroll 2
                 for (int r = tr; r < N0; r += RPS, nu0 += dn0, nu1 += dn1) {
                     const float val = interp_at(nu0, nu1);
                     Pout[r * N1 + j] = val;
@@ -1398,27 +1393,18 @@ constexpr int group_g_v(int v) {
 }
 
 __global__ void __launch_bounds__(FUSED_THREADS)
-k_fused(const GItem* __restrict__ groups, int ngroups, const BItem* __restrict__ items,
-        const FPlan* __restrict__ plans, int* ctr, const double* __restrict__ zall, int nzmax,
-        double* __restrict__ ll_out, int bufcplx) {
-    // no twiddle tables in LDS yet.  The barrier keeps this block apart from the
-    // loop's claim below: without it the compiler merged the two thread-0 blocks
-    // into a rotated loop in which wave 0 passed the loop's first barrier before
-    // lane 0 had made the first claim (the workgroup then read an unwritten
-    // group record)
-    if (threadIdx.x == 0) pmf_twtype = -1;
+k_fused(const GItem* __restrict__ groups, const BItem* __restrict__ items, const FPlan* __restrict__ plans,
+        const double* __restrict__ zall, int nzmax, double* __restrict__ ll_out, int bufcplx) {
+    // One workgroup per group: the dispatcher hands the groups out in launch
+    // order, largest grids first, as compute units free up.  Each group type's
+    // function is inlined into its own branch, so no call saves and restores
+    // registers through scratch memory (a persistent loop over claimed groups
+    // needed the group functions out of line: inlined into the loop, the
+    // compiler kept their loop-invariant addressing live across all of them)
+    if (threadIdx.x == 0) pmf_gi = groups[blockIdx.x];
     __syncthreads();
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const int next = atomicAdd(ctr, 1);
-            pmf_item = next;
-            if (next < ngroups) pmf_gi = groups[next];
-        }
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(pmf_item);
+    {
         const int type = __builtin_amdgcn_readfirstlane(pmf_gi.type);
-        __syncthreads();
-        if (it >= ngroups) break;
         // group record type = base type * NSCHED + schedule variant
 #define PMF_GROUP_V(T, N0, N1, NX, V)                                                                       \
     case T * NSCHED + V:                                                                                    \
@@ -1534,7 +1520,6 @@ struct BatchCache {
     pmf::FConst* d_consts = nullptr;
     double* d_z = nullptr;
     double* d_ll = nullptr;
-    int* d_ctr = nullptr;
     // z staging: step k writes slot k % ZSLOTS of mapped pinned memory, which its
     // planning kernel reads.  An event is recorded after every ZEVERY-th step only
     // (an event costs several microseconds of GPU time between steps); before
@@ -1562,7 +1547,6 @@ static void cache_free(pmf_ctx* ctx, BatchCache* c) {
     ctx_free(ctx, c->d_consts, nullptr);
     ctx_free(ctx, c->d_z, nullptr);
     ctx_free(ctx, c->d_ll, nullptr);
-    ctx_free(ctx, c->d_ctr, nullptr);
     for (int i = 0; i < BatchCache::ZSLOTS; ++i)
         if (c->h_z[i]) (void)hipHostFree(c->h_z[i]);
     for (int i = 0; i < 2; ++i)
@@ -1645,7 +1629,7 @@ static int pow2_at_least(int v) {
 }
 
 // Same-size filters in groups of at most the group type's capacity, largest
-// grids first (the persistent workgroups take the longest work first).  Array
+// grids first (the dispatcher hands the longest work out first).  Array
 // form without allocation: order (n ints) is working space, sorted receives the
 // items in group order, groups at most n records (*ngroups of them).  Ties keep
 // the input order.  sched (null: defaults) holds the schedule variant per group
@@ -1767,7 +1751,6 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     c->d_plans = static_cast<FPlan*>(A(sizeof(FPlan) * n));
     c->d_z = static_cast<double*>(A(sizeof(double) * n * nzmax));
     c->d_ll = static_cast<double*>(A(sizeof(double) * n));
-    c->d_ctr = static_cast<int*>(A(sizeof(int)));
     if (!ok) return fail(PMF_E_NOMEM, "batch allocation failed");
     for (int q = 0; q < n; ++q) sorted[q].k = c->d_consts + sorted[q].idx;
     hipError_t e = hipMemcpy(c->d_consts, consts.data(), sizeof(FConst) * n, hipMemcpyHostToDevice);
@@ -1788,10 +1771,7 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, FUSED_THREADS, c->lds);
     if (e != hipSuccess) return hip_fail(e, "occupancy");
     if (per_cu < 1) return fail(PMF_E_INVALID, "fused kernel does not fit on a compute unit");
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, ctx->device);
-    if (e != hipSuccess) return hip_fail(e, "device properties");
-    c->grid = std::min(c->ngroups, per_cu * prop.multiProcessorCount);
+    c->grid = c->ngroups;   // one workgroup per group
     return PMF_OK;
 }
 
@@ -1802,7 +1782,6 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
 struct DynBatch {
     int cap = 0;                     // filters the buffers hold
     pmf::FPlan* d_plans = nullptr;   // device
-    int* d_ctr = nullptr;
     // mapped pinned host memory, read (items, groups, z) and written (log-likelihoods)
     // by the kernels in place: a served batch is two launches, no copies
     pmf::BItem* h_items = nullptr;
@@ -1814,7 +1793,6 @@ struct DynBatch {
     double* m_z = nullptr;
     double* m_ll = nullptr;
     bool attr = false;
-    int ncu = 0;
     std::map<size_t, int> per_cu;    // resident fused workgroups per CU, by LDS size
 };
 
@@ -1822,13 +1800,11 @@ namespace pmf {
 
 static void dyn_free_buffers(pmf_ctx* ctx, DynBatch* db) {
     ctx_free(ctx, db->d_plans, nullptr);
-    ctx_free(ctx, db->d_ctr, nullptr);
     if (db->h_items) (void)hipHostFree(db->h_items);
     if (db->h_groups) (void)hipHostFree(db->h_groups);
     if (db->h_z) (void)hipHostFree(db->h_z);
     if (db->h_ll) (void)hipHostFree(db->h_ll);
     db->d_plans = nullptr;
-    db->d_ctr = nullptr;
     db->h_items = db->m_items = nullptr;
     db->h_groups = db->m_groups = nullptr;
     db->h_z = db->h_ll = db->m_z = db->m_ll = nullptr;
@@ -1874,7 +1850,6 @@ static pmf_status dyn_reserve(pmf_ctx* ctx, DynBatch* db, int n) {
         return p;
     };
     db->d_plans = static_cast<FPlan*>(A(sizeof(FPlan) * cap));
-    db->d_ctr = static_cast<int*>(A(sizeof(int)));
     hipError_t e = hipSuccess;
     auto H = [&](void** h, void** m, size_t bytes) {
         if (e != hipSuccess) return;
@@ -1903,10 +1878,6 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
     if (!db->attr) {
         const pmf_status ls = fused_lds_attribute();
         if (ls != PMF_OK) return ls;
-        hipDeviceProp_t prop;
-        e = hipGetDeviceProperties(&prop, ctx->device);
-        if (e != hipSuccess) return hip_fail(e, "fused kernel set-up");
-        db->ncu = prop.multiProcessorCount;
         db->attr = true;
     }
     std::vector<BItem> items(n);
@@ -1946,9 +1917,8 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, k_fused, FUSED_THREADS, lds);
         if (e != hipSuccess) return hip_fail(e, "occupancy");
         if (pc < 1) return fail(PMF_E_INVALID, "fused kernel does not fit on a compute unit");
-        it = db->per_cu.emplace(lds, pc).first;
+        db->per_cu.emplace(lds, pc);
     }
-    const int grid = std::min(ng, it->second * db->ncu);
     // the staging set is written in place (the caller reuses a set only after the
     // launch that read it has completed); the kernels read it, and write the
     // log-likelihoods, through its mapped device addresses
@@ -1957,9 +1927,9 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
     for (int q = 0; q < n; ++q)   // rows in item order
         std::memcpy(db->h_z + (size_t)q * 3, z + (size_t)sorted[q].idx * 3, sizeof(double) * 3);
     hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st,
-                       db->m_items, db->d_plans, n, db->m_z, nullptr, 3, db->d_ctr);
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, db->m_groups, ng, db->m_items,
-                       db->d_plans, db->d_ctr, db->m_z, 3, db->m_ll, maxcplx);
+                       db->m_items, db->d_plans, n, db->m_z, nullptr, 3);
+    hipLaunchKernelGGL(k_fused, dim3(ng), dim3(FUSED_THREADS), lds, st, db->m_groups, db->m_items, db->d_plans,
+                       db->m_z, 3, db->m_ll, maxcplx);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "served batch launch");
     return PMF_OK;
@@ -2048,24 +2018,22 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             hipEvent_t t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
             ctx->ev_used++;
             ctx->ev_stream = st;
-            hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st, c->d_items, c->d_plans, n,
-                               c->hz_dev[slot], c->d_z, c->nzmax, c->d_ctr);
+            hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st,
+                               c->d_items, c->d_plans, n, c->hz_dev[slot], c->d_z, c->nzmax);
             e = hipEventRecord(t0, st);
             if (e == hipSuccess) {
-                hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups,
-                                   c->ngroups, c->d_items, c->d_plans, c->d_ctr, c->d_z, c->nzmax, c->d_ll,
-                                   c->bufcplx);
+                hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups, c->d_items,
+                                   c->d_plans, c->d_z, c->nzmax, c->d_ll, c->bufcplx);
                 e = hipGetLastError();
             }
             if (e == hipSuccess) e = hipEventRecord(t1, st);
         }
     } else {
-        // plan every filter (reading its z from the slot, clearing the work
-        // counter), then the fused kernel
+        // plan every filter (reading its z from the slot), then the fused kernel
         hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st,
-                           c->d_items, c->d_plans, n, c->hz_dev[slot], c->d_z, c->nzmax, c->d_ctr);
-        hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups, c->ngroups,
-                           c->d_items, c->d_plans, c->d_ctr, c->d_z, c->nzmax, c->d_ll, c->bufcplx);
+                           c->d_items, c->d_plans, n, c->hz_dev[slot], c->d_z, c->nzmax);
+        hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, st, c->d_groups, c->d_items,
+                           c->d_plans, c->d_z, c->nzmax, c->d_ll, c->bufcplx);
         e = hipGetLastError();
     }
     if (e == hipSuccess && k % BatchCache::ZEVERY == BatchCache::ZEVERY - 1) e = hipEventRecord(c->ev[evi], st);
@@ -2104,7 +2072,7 @@ extern "C" pmf_status pmf_batch_kernel_time(pmf_ctx* ctx, double* total_ms, int*
 // Each 2-D group type has up to four compile-time schedules (filters per
 // workgroup full or half, column radix order default or reversed).  The tuner
 // times them with the real kernels on a synthetic batch with the caller's mix of
-// sizes (the persistent launch balances all sizes together, so a size's best
+// sizes (one launch balances all sizes together, so a size's best
 // schedule depends on the mix) and keeps the choice per type in the context; it
 // is cached as a small JSON file keyed by device, HIP runtime, library build and
 // mix.
@@ -2359,16 +2327,15 @@ extern "C" pmf_status pmf_set_schedule(pmf_ctx* ctx, int nx, int N, int variant)
 
 // ==================================================================== step without allocation
 // pmf_batch_step_noalloc: the same planning and fused kernels, with their
-// per-step records (items, groups, plans, z, log-likelihoods, work counter) in a
-// file-scope device array instead of library allocations.
+// per-step records (items, groups, plans, z, log-likelihoods) in a file-scope
+// device array instead of library allocations.
 
 namespace pmf {
 
 constexpr int NOALLOC_MAX = 4096;   // filters per call
 constexpr size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 // byte offsets of the parts inside the array (each 256-byte aligned)
-constexpr size_t NA_CTR = 0;
-constexpr size_t NA_ITEMS = 256;
+constexpr size_t NA_ITEMS = 0;
 constexpr size_t NA_GROUPS = NA_ITEMS + al256(sizeof(BItem) * NOALLOC_MAX);
 constexpr size_t NA_PLANS = NA_GROUPS + al256(sizeof(GItem) * NOALLOC_MAX);
 constexpr size_t NA_Z = NA_PLANS + al256(sizeof(FPlan) * NOALLOC_MAX);
@@ -2388,7 +2355,6 @@ namespace pmf {
 constexpr int NA_MAXDEV = 64;
 static std::mutex na_mu;                      // one call at a time (host staging, scratch)
 static unsigned char* na_ptr[NA_MAXDEV] = {};   // device address of scratch, per device
-static int na_ncu[NA_MAXDEV] = {};
 // host staging, reused by every call (calls are serialised by na_mu)
 static BItem na_items[NOALLOC_MAX], na_sorted[NOALLOC_MAX];
 static GItem na_groups[NOALLOC_MAX];
@@ -2396,9 +2362,9 @@ static int na_order[NOALLOC_MAX];
 static pmf_filter* na_seen[NOALLOC_MAX];
 static double na_z[3 * NOALLOC_MAX], na_ll[NOALLOC_MAX];
 
-// the scratch address, compute-unit count and LDS attribute of device dev
-// (the device is current); set up on its first call
-static pmf_status na_device(int dev, unsigned char** ptr, int* ncu) {
+// the scratch address and LDS attribute of device dev (the device is current);
+// set up on its first call
+static pmf_status na_device(int dev, unsigned char** ptr) {
     if (dev < 0 || dev >= NA_MAXDEV) return fail(PMF_E_INVALID, "device index beyond 64");
     if (!na_ptr[dev]) {
         void* p = nullptr;
@@ -2406,14 +2372,9 @@ static pmf_status na_device(int dev, unsigned char** ptr, int* ncu) {
         if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
         const pmf_status ls = fused_lds_attribute();
         if (ls != PMF_OK) return ls;
-        hipDeviceProp_t prop;
-        e = hipGetDeviceProperties(&prop, dev);
-        if (e != hipSuccess) return hip_fail(e, "device properties");
-        na_ncu[dev] = prop.multiProcessorCount;
         na_ptr[dev] = static_cast<unsigned char*>(p);
     }
     *ptr = na_ptr[dev];
-    *ncu = na_ncu[dev];
     return PMF_OK;
 }
 
@@ -2429,8 +2390,7 @@ extern "C" pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* fi
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     unsigned char* base = nullptr;
-    int ncu = 0;
-    pmf_status s = na_device(ctx->device, &base, &ncu);
+    pmf_status s = na_device(ctx->device, &base);
     if (s != PMF_OK) return s;
     const hipStream_t st = static_cast<hipStream_t>(stream);
 
@@ -2478,23 +2438,20 @@ extern "C" pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* fi
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, FUSED_THREADS, lds);
     if (e != hipSuccess) return hip_fail(e, "occupancy");
     if (per_cu < 1) return fail(PMF_E_INVALID, "fused kernel does not fit on a compute unit");
-    const int grid = std::min(ng, per_cu * ncu);
 
     BItem* d_items = reinterpret_cast<BItem*>(base + NA_ITEMS);
     GItem* d_groups = reinterpret_cast<GItem*>(base + NA_GROUPS);
     FPlan* d_plans = reinterpret_cast<FPlan*>(base + NA_PLANS);
     double* d_z = reinterpret_cast<double*>(base + NA_Z);
     double* d_ll = reinterpret_cast<double*>(base + NA_LL);
-    int* d_ctr = reinterpret_cast<int*>(base + NA_CTR);
     e = hipMemcpyAsync(d_items, na_sorted, sizeof(BItem) * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_groups, na_groups, sizeof(GItem) * ng, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_z, na_z, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "no-allocation step upload");
-    // the planning kernel clears the work counter (thread 0) before the fused kernel runs
     hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0, st,
-                       d_items, d_plans, n, d_z, nullptr, 3, d_ctr);
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(FUSED_THREADS), lds, st, d_groups, ng, d_items, d_plans, d_ctr,
-                       d_z, 3, d_ll, maxcplx);
+                       d_items, d_plans, n, d_z, nullptr, 3);
+    hipLaunchKernelGGL(k_fused, dim3(ng), dim3(FUSED_THREADS), lds, st, d_groups, d_items, d_plans, d_z, 3, d_ll,
+                       maxcplx);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(na_ll, d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -15,16 +15,26 @@ import oracle.pmf as OP
 import workloads as W
 
 
+def _fma32(a, b, c):
+    """float32 fused multiply-add: the exact a b + c rounded once (the product of two
+    float32 values is exact in float64, and so is its sum with c at these magnitudes
+    up to one float64 rounding, far below float32's)."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+
+
 def _fp32_weights(t, pts):
     """Cubic Lagrange weights at t through the unit-spaced taps pts = i0 - 1 .. i0 + 2,
-    evaluated as the kernel does: s = float32(t - i0), weights in float32."""
+    evaluated as the kernel does: s = float32(t - i0), each weight a polynomial in s
+    in float32 with fused multiply-adds."""
+    f = np.float32
     i0 = pts[..., 1]
-    s = (t - i0).astype(np.float32)
-    one, half, sixth = np.float32(1), np.float32(0.5), np.float32(1.0 / 6.0)
-    tp, tm, tm2 = s + one, s - one, s - np.float32(2)
-    a, d = s * tm, tp * s
-    w = np.stack([a * tm2 * -sixth, tp * tm * tm2 * half, d * tm2 * -half, d * tm * sixth], axis=-1)
-    return w.astype(np.float64)
+    s = (t - i0).astype(f)
+    c = _fma32(s * s, f(1.0 / 6.0), f(-1.0 / 6.0))
+    w0 = s * _fma32(s, _fma32(s, f(-1.0 / 6.0), f(0.5)), f(-1.0 / 3.0))
+    w1 = c * _fma32(s, f(3.0), f(-6.0))
+    w2 = s * _fma32(s, _fma32(s, f(-0.5), f(0.5)), f(1.0))
+    w3 = s * c
+    return np.stack([w0, w1, w2, w3], axis=-1).astype(np.float64)
 
 
 def _cell(model, M):
