@@ -305,9 +305,11 @@ pmf_status pmf_set_schedule(pmf_ctx* ctx, int nx, int N, int variant);
  * and that pmf_batch_step accepts (Fourier, FP32, nx <= 2, the sizes listed
  * there) runs that pair as one fused cycle, batched with the other such tracks
  * taken in the same pass that have the same T (up to 4 fused batches on the
- * device at once); every other op runs alone through pmf_predict / pmf_update on
- * one of 4 HIP streams, concurrently with the fused batches.  One op (or fused
- * pair) of a track is on the device at a time, so a track's ops run in submission
+ * device at once); every other op runs through pmf_predict / pmf_update on the
+ * least loaded of 4 HIP streams, concurrently with the fused batches, a predict
+ * and the update queued after it as one run (back to back on that stream).  One
+ * op, fused pair or run of a track is on the device at a time, so a track's ops
+ * run in submission
  * order; results equal the direct calls on the same filter (fused pairs: bit for
  * bit equal to pmf_batch_step of the filter alone).  Admission: a track that
  * does not fit the server's device-memory budget waits (its ops are queued)

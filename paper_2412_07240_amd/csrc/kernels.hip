@@ -122,9 +122,11 @@ template <typename C, typename T, int R> __device__ inline void dft_direct(C* a,
 }
 
 // One Stockham autosort pass over `nlines` lines held in LDS (pitch `pitch`).
+// tw: the n-th roots of unity e^{-2 pi i m / n}, m < n, in LDS; the twiddle
+// e^{sign 2 pi i k r / (Ns R)} is entry k r n / (Ns R) (conjugated for sign > 0).
 template <typename T, int R>
-__device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* out, int n, int Ns,
-                              int nlines, int pitch, int sign) {
+__device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* out, const typename V2<T>::t* tw,
+                              int n, int Ns, int nlines, int pitch, int sign) {
     using C = typename V2<T>::t;
     const int nb = n / R;
     for (int w = threadIdx.x; w < nlines * nb; w += blockDim.x) {
@@ -136,13 +138,11 @@ __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* ou
         for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
         const int k = j % Ns;
         if (k) {
+            const int step = k * (n / (Ns * R));
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                T sn, cs;
-                sincospi_t((T)(2 * sign * k * r) / (T)(Ns * R), &sn, &cs);
-                C w2;
-                w2.x = cs;
-                w2.y = sn;
+                C w2 = tw[r * step];
+                if (sign > 0) w2.y = -w2.y;
                 v[r] = cmul(v[r], w2);
             }
         }
@@ -161,26 +161,39 @@ __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* ou
     }
 }
 
-// All passes of an n-point transform of ntl lines held in LDS (A, ping-ponging
-// with B); returns the buffer holding the result.  Every thread must call it.
+// The n-th roots of unity e^{-2 pi i m / n}, m < n, into tw (block-wide; the
+// caller's barrier publishes them).
 template <typename T>
-__device__ typename V2<T>::t* fft_passes(typename V2<T>::t* A, typename V2<T>::t* B, int n, int ntl, int pitch,
-                                         int sign, const FftPlan& plan) {
+__device__ inline void fft_roots(typename V2<T>::t* tw, int n) {
+    for (int m = threadIdx.x; m < n; m += blockDim.x) {
+        T sn, cs;
+        sincospi_t((T)(-2 * m) / (T)n, &sn, &cs);
+        tw[m].x = cs;
+        tw[m].y = sn;
+    }
+}
+
+// All passes of an n-point transform of ntl lines held in LDS (A, ping-ponging
+// with B; tw from fft_roots); returns the buffer holding the result.  Every
+// thread must call it.
+template <typename T>
+__device__ typename V2<T>::t* fft_passes(typename V2<T>::t* A, typename V2<T>::t* B, const typename V2<T>::t* tw,
+                                         int n, int ntl, int pitch, int sign, const FftPlan& plan) {
     using C = typename V2<T>::t;
     int Ns = 1;
     C* in = A;
     C* out = B;
     for (int p = 0; p < plan.np; ++p) {
         const int R = plan.r[p];
-        if (R == 8) stockham_pass<T, 8>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 4) stockham_pass<T, 4>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 3) stockham_pass<T, 3>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 5) stockham_pass<T, 5>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 7) stockham_pass<T, 7>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 11) stockham_pass<T, 11>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 13) stockham_pass<T, 13>(in, out, n, Ns, ntl, pitch, sign);
-        else if (R == 17) stockham_pass<T, 17>(in, out, n, Ns, ntl, pitch, sign);
-        else stockham_pass<T, 2>(in, out, n, Ns, ntl, pitch, sign);
+        if (R == 8) stockham_pass<T, 8>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (R == 4) stockham_pass<T, 4>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (R == 3) stockham_pass<T, 3>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (R == 5) stockham_pass<T, 5>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (R == 7) stockham_pass<T, 7>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (R == 11) stockham_pass<T, 11>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (R == 13) stockham_pass<T, 13>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (R == 17) stockham_pass<T, 17>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else stockham_pass<T, 2>(in, out, tw, n, Ns, ntl, pitch, sign);
         __syncthreads();
         C* tmp = in;
         in = out;
@@ -201,8 +214,10 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
     const int pitch = n + 1;
     C* A = reinterpret_cast<C*>(smem_fft);
     C* B = A + TL * pitch;
+    C* tw = B + TL * pitch;
     const int L0 = blockIdx.x * TL;
     const int ntl = min(TL, nlines - L0);
+    fft_roots<T>(tw, n);
     for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
         int t, k;
         size_t addr;
@@ -226,7 +241,7 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
         A[t * pitch + k] = v;
     }
     __syncthreads();
-    const C* in = fft_passes<T>(A, B, n, ntl, pitch, sign, plan);
+    const C* in = fft_passes<T>(A, B, tw, n, ntl, pitch, sign, plan);
     for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
         int t, k;
         size_t addr;
@@ -259,8 +274,10 @@ __global__ void k_dst1_axis(const T* src, T* dst, int n, int s, int nlines, FftP
     const int L = 2 * (n + 1), pitch = L + 1;
     C* A = reinterpret_cast<C*>(smem_dst);
     C* B = A + TL * pitch;
+    C* tw = B + TL * pitch;
     const int L0 = blockIdx.x * TL;
     const int ntl = min(TL, nlines - L0);
+    fft_roots<T>(tw, L);
     for (int e = threadIdx.x; e < ntl * L; e += blockDim.x) {
         int t, k;
         if (s == 1) {
@@ -284,7 +301,7 @@ __global__ void k_dst1_axis(const T* src, T* dst, int n, int s, int nlines, FftP
         A[t * pitch + k] = c;
     }
     __syncthreads();
-    const C* Y = fft_passes<T>(A, B, L, ntl, pitch, -1, plan);
+    const C* Y = fft_passes<T>(A, B, tw, L, ntl, pitch, -1, plan);
     for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
         int t, k;
         if (s == 1) {
@@ -1087,6 +1104,26 @@ __global__ void k_copy(T* dst, const T* src, int ntot) {
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// Lines per block of the LDS transforms along one axis: enough blocks for about
+// two per compute unit (one transform of a small filter is otherwise a handful of
+// blocks, each running all its lines' passes in turn), at most about 2048 points
+// per block, and both line buffers plus the roots of unity within 64 KiB.
+static inline int lines_per_block(int len, int nlines, size_t csize) {
+    const int cap = (int)((65536 / csize - len) / (2 * (size_t)(len + 1)));
+    int TL = std::min(2048 / len, std::max(1, nlines / 512));
+    if (TL > cap) TL = cap;
+    if (TL < 1) TL = 1;
+    if (TL > nlines) TL = nlines;
+    return TL;
+}
+
+// threads per block for `points` points in LDS: about two points per thread, whole
+// waves, 64..256
+static inline int block_threads(int points) {
+    const int t = (points / 2 + 63) / 64 * 64;
+    return std::min(256, std::max(64, t));
+}
+
 template <typename T>
 hipError_t launch_fft_axis(const KModel& m, int a, const T* rsrc, void* X, T* rdst, int sign,
                            hipStream_t st) {
@@ -1094,15 +1131,10 @@ hipError_t launch_fft_axis(const KModel& m, int a, const T* rsrc, void* X, T* rd
     int s = 1;
     for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
     const int nlines = m.ntot / n;
-    // lines per block: about 2048 points, and the two LDS buffers within 64 KiB
-    const int cap = (int)(65536 / (2 * (size_t)(n + 1) * sizeof(typename V2<T>::t)));
-    int TL = 2048 / n;
-    if (TL > cap) TL = cap;
-    if (TL < 1) TL = 1;
-    if (TL > nlines) TL = nlines;
-    const size_t lds = 2 * (size_t)TL * (n + 1) * sizeof(typename V2<T>::t);
+    const int TL = lines_per_block(n, nlines, sizeof(typename V2<T>::t));
+    const size_t lds = (2 * (size_t)TL * (n + 1) + n) * sizeof(typename V2<T>::t);
     const FftPlan plan = make_plan(n);
-    hipLaunchKernelGGL(k_fft_axis<T>, dim3(cdiv(nlines, TL)), dim3(256), lds, st, rsrc,
+    hipLaunchKernelGGL(k_fft_axis<T>, dim3(cdiv(nlines, TL)), dim3(block_threads(TL * n)), lds, st, rsrc,
                        static_cast<typename V2<T>::t*>(X), rdst, n, s, nlines, sign, plan, TL);
     return hipGetLastError();
 }
@@ -1301,15 +1333,11 @@ hipError_t launch_dst1_axis(const KModel& m, int a, const T* src, T* dst, hipStr
     int s = 1;
     for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
     const int nlines = m.ntot / n;
-    // lines per block: about 2048 extended points, both LDS buffers within 64 KiB
-    const int cap = (int)(65536 / (2 * (size_t)(L + 1) * sizeof(typename V2<T>::t)));
-    int TL = 2048 / L;
-    if (TL > cap) TL = cap;
-    if (TL < 1) TL = 1;
-    if (TL > nlines) TL = nlines;
-    const size_t lds = 2 * (size_t)TL * (L + 1) * sizeof(typename V2<T>::t);
+    const int TL = lines_per_block(L, nlines, sizeof(typename V2<T>::t));
+    const size_t lds = (2 * (size_t)TL * (L + 1) + L) * sizeof(typename V2<T>::t);
     const FftPlan plan = make_plan(L);
-    hipLaunchKernelGGL(k_dst1_axis<T>, dim3(cdiv(nlines, TL)), dim3(256), lds, st, src, dst, n, s, nlines, plan, TL);
+    hipLaunchKernelGGL(k_dst1_axis<T>, dim3(cdiv(nlines, TL)), dim3(block_threads(TL * L)), lds, st, src, dst, n, s,
+                       nlines, plan, TL);
     return hipGetLastError();
 }
 

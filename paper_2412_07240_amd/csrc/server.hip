@@ -54,12 +54,14 @@ struct Taken {
 };
 
 // work on the device whose completion the worker waits for: a fused batch
-// (predict/update pairs, ops = p0 u0 p1 u1 ...) or one single op
+// (predict/update pairs, ops = p0 u0 p1 u1 ...), or the single ops of one track
+// (one op, or a predict and the update after it) launched back to back
 struct Flight {
     hipEvent_t ev = nullptr;
     std::vector<Taken> ops;
-    int dyn = -1;            // fused: staging set holding the log-likelihoods
-    pmf_status launch = PMF_OK;
+    int dyn = -1;                       // fused: staging set holding the log-likelihoods
+    pmf_status launch = PMF_OK;         // fused: the batch's launch status
+    std::vector<pmf_status> launches;   // single ops: each op's launch status
 };
 
 }  // namespace
@@ -69,7 +71,8 @@ struct Launcher {
     std::thread th;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Taken> q;
+    std::deque<std::vector<Taken>> q;   // runs of one track's ops
+    std::atomic<int> load{0};           // ops handed to it and not yet retired
     hipStream_t st = nullptr;
 };
 
@@ -153,12 +156,15 @@ static void retire(pmf_server* s, Flight& fl, hipError_t ev_state) {
             status[2 * j + 1] = st != PMF_OK ? st : (std::isnan(out[j]) ? PMF_E_DEGENERATE : PMF_OK);
         }
     } else {
-        pmf_status st = fl.launch;
-        if (st == PMF_OK && !dev_ok) st = PMF_E_DEVICE;
-        status[0] = st;
-        if (fl.ops[0].op.op == PMF_OP_UPDATE && st == PMF_OK) {
-            ll[0] = s->h_ll[fl.ops[0].track];
-            if (std::isnan(ll[0])) status[0] = PMF_E_DEGENERATE;
+        // at most one update per run: its log-likelihood is in the track's slot
+        for (size_t i = 0; i < n; ++i) {
+            pmf_status st = fl.launches[i];
+            if (st == PMF_OK && !dev_ok) st = PMF_E_DEVICE;
+            status[i] = st;
+            if (fl.ops[i].op.op == PMF_OP_UPDATE && st == PMF_OK) {
+                ll[i] = s->h_ll[fl.ops[i].track];
+                if (std::isnan(ll[i])) status[i] = PMF_E_DEGENERATE;
+            }
         }
     }
     post(s, fl, status, ll);
@@ -170,9 +176,11 @@ static void retire(pmf_server* s, Flight& fl, hipError_t ev_state) {
 // as soon as their track (and, for fused batches, a staging set) is free.  A
 // track whose FIFO starts with predict(T) + update(z) and that the fused kernel
 // accepts runs that pair as one fused cycle, batched with the other such tracks
-// taken in the same pass that have the same T; every other op runs alone on one
-// of the single-op streams.  One op (or fused pair) of a track is on the device
-// at a time, so each track's ops run in submission order.
+// taken in the same pass that have the same T; every other op runs through the
+// generic path on the least loaded of the single-op streams, a predict followed
+// by an update of the same track as one run (back to back on one stream, no
+// round trip through the worker in between).  One op, fused pair or run of a
+// track is on the device at a time, so each track's ops run in submission order.
 static void worker_main(pmf_server* s) {
     (void)hipSetDevice(s->ctx->device);
     std::vector<Flight> flights;
@@ -213,7 +221,7 @@ static void worker_main(pmf_server* s) {
         }
         // 2. take the next op of every idle track with queued ops
         std::map<double, std::vector<Taken>> fused;   // T -> predict/update pairs
-        std::vector<Taken> singles;
+        std::vector<std::vector<Taken>> singles;      // runs of one track's ops
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (s->ready.empty()) {
@@ -251,8 +259,13 @@ static void worker_main(pmf_server* s) {
                     t.q.pop_front();
                     t.q.pop_front();
                 } else {
-                    singles.push_back({id, t.q[0], t.f});
+                    std::vector<Taken> run{{id, t.q[0], t.f}};
                     t.q.pop_front();
+                    if (run[0].op.op == PMF_OP_PREDICT && !t.q.empty() && t.q[0].op == PMF_OP_UPDATE) {
+                        run.push_back({id, t.q[0], t.f});
+                        t.q.pop_front();
+                    }
+                    singles.push_back(std::move(run));
                 }
                 t.busy = true;
             }
@@ -279,25 +292,31 @@ static void worker_main(pmf_server* s) {
             dyn_busy[d] = true;
             flights.push_back(std::move(fl));
         }
-        for (Taken& tk : singles) {
-            Launcher& L = s->launchers[rr++ % SINGLE_STREAMS];
+        for (std::vector<Taken>& run : singles) {
+            // the launcher with the fewest ops outstanding (ties: round robin)
+            int best = rr++ % SINGLE_STREAMS;
+            for (int q = 0; q < SINGLE_STREAMS; ++q)
+                if (s->launchers[q].load.load() < s->launchers[best].load.load()) best = q;
+            Launcher& L = s->launchers[best];
+            L.load += (int)run.size();
             {
                 std::lock_guard<std::mutex> lk(L.mu);
-                L.q.push_back(tk);
+                L.q.push_back(std::move(run));
             }
             L.cv.notify_one();
         }
     }
 }
 
-// A single-op launcher: puts the ops handed to it on its stream (each followed by
-// an event) and retires them as their events complete, so that the host cost of
-// the generic path's many launches is spread over several threads.
+// A single-op launcher: puts the runs handed to it on its stream (each run's ops
+// back to back, then an event) and retires them as their events complete, so
+// that the host cost of the generic path's many launches is spread over several
+// threads.
 static void launcher_main(pmf_server* s, Launcher* L) {
     (void)hipSetDevice(s->ctx->device);
     std::vector<Flight> flights;
     std::vector<hipEvent_t> ev_free;
-    std::vector<Taken> take;
+    std::vector<std::vector<Taken>> take;
     for (;;) {
         for (size_t i = 0; i < flights.size();) {
             const hipError_t q = flights[i].ev ? hipEventQuery(flights[i].ev) : hipSuccess;
@@ -305,6 +324,7 @@ static void launcher_main(pmf_server* s, Launcher* L) {
                 ++i;
                 continue;
             }
+            L->load -= (int)flights[i].ops.size();
             retire(s, flights[i], q);
             if (flights[i].ev) ev_free.push_back(flights[i].ev);
             flights[i] = std::move(flights.back());
@@ -324,19 +344,20 @@ static void launcher_main(pmf_server* s, Launcher* L) {
                 }
             }
             while (!L->q.empty()) {
-                take.push_back(L->q.front());
+                take.push_back(std::move(L->q.front()));
                 L->q.pop_front();
             }
         }
-        for (Taken& tk : take) {
-            pmf_filter* f = tk.f;
+        for (std::vector<Taken>& run : take) {
             Flight fl;
-            fl.ops.push_back(tk);
-            if (tk.op.op == PMF_OP_PREDICT) {
-                fl.launch = pmf_predict(f, tk.op.T, L->st);
-            } else {
-                s->h_ll[tk.track] = NAN;
-                fl.launch = pmf_update(f, tk.op.z, &s->h_ll[tk.track], L->st);
+            fl.ops = std::move(run);
+            for (const Taken& tk : fl.ops) {
+                if (tk.op.op == PMF_OP_PREDICT) {
+                    fl.launches.push_back(pmf_predict(tk.f, tk.op.T, L->st));
+                } else {
+                    s->h_ll[tk.track] = NAN;
+                    fl.launches.push_back(pmf_update(tk.f, tk.op.z, &s->h_ll[tk.track], L->st));
+                }
             }
             hipEvent_t e = nullptr;
             if (!ev_free.empty()) {
