@@ -865,8 +865,9 @@ __device__ inline void lagrange4(double t, const double* x, double* w) {
     }
 }
 
-// Tensor cubic Lagrange interpolation in the old grid's computational coordinates.
-template <typename T>
+// Tensor cubic Lagrange interpolation in the old grid's computational coordinates,
+// specialised per dimension NX (every axis loop unrolled, taps in registers).
+template <typename T, int NX>
 __global__ void __launch_bounds__(RED_THREADS)
 k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T* out,
                   double* part, int chunk) {
@@ -876,98 +877,100 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
     const Grid& gn = d->gn;
     const int lo = blockIdx.x * chunk;
     const int hi = min(m.ntot, lo + chunk);
+    const bool fourier = m.grid == PMF_GRID_FOURIER;
     double acc[NACC];
     for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
     for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
         double u[MS] = {0, 0, 0, 0}, x[MS], r[MS], nu[MS] = {0, 0, 0, 0};
         int idx[MS] = {0, 0, 0, 0};
         node_coords(m, tab, j, u, idx);
-        to_phys(gn, m.nx, u, x);
-        for (int a = 0; a < m.nx; ++a) r[a] = x[a] - go.c[a];
-        mat_vec(nu, go.Mi, r, m.nx);
+        to_phys(gn, NX, u, x);
+#pragma unroll
+        for (int a = 0; a < NX; ++a) r[a] = x[a] - go.c[a];
+        mat_vec(nu, go.Mi, r, NX);
         bool inside = true;
-        int tapidx[MS][4];
-        double tw[MS][4];
-        for (int a = 0; a < m.nx; ++a) {
+        int tapidx[NX][4];
+        double tw[NX][4];
+#pragma unroll
+        for (int a = 0; a < NX; ++a) {
             const int n = m.N[a];
-            if (m.grid == PMF_GRID_FOURIER) {
+            if (fourier) {
                 const double q = nu[a] + (double)(n / 2);
-                if (!(q >= 0.0 && q <= (double)(n - 1))) {
-                    inside = false;
-                    break;
-                }
-                const int i0 = (int)floor(q);
-                const double xs[4] = {(double)(i0 - 1), (double)i0, (double)(i0 + 1), (double)(i0 + 2)};
-                lagrange4(q, xs, tw[a]);
+                inside = inside && q >= 0.0 && q <= (double)(n - 1);
+                const int i0 = (int)floor(fmin(fmax(q, 0.0), (double)(n - 1)));
+                // the cubic through nodes i0 - 1 .. i0 + 2 (unit spacing) at t = q - i0
+                const double t = q - (double)i0, tp = t + 1.0, tm = t - 1.0, tm2 = t - 2.0;
+                tw[a][0] = -t * tm * tm2 / 6.0;
+                tw[a][1] = tp * tm * tm2 / 2.0;
+                tw[a][2] = -tp * t * tm2 / 2.0;
+                tw[a][3] = tp * t * tm / 6.0;
+#pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int ii = i0 - 1 + k;
-                    tapidx[a][k] = ii;
-                    if (ii < 0 || ii > n - 1) tw[a][k] = 0.0;
+                    const bool ok = ii >= 0 && ii <= n - 1;
+                    tapidx[a][k] = ok ? ii : i0;
+                    if (!ok) tw[a][k] = 0.0;
                 }
             } else {
                 const double q = nu[a];
-                if (!(q >= -1.0 && q <= 1.0)) {
-                    inside = false;
-                    break;
-                }
+                inside = inside && q >= -1.0 && q <= 1.0;
+                const double qc = fmin(fmax(q, -1.0), 1.0);
                 const int nn = n + 1;
-                int k0 = (int)floor((double)nn * acos(-q) / M_PI);
+                int k0 = (int)floor((double)nn * acos(-qc) / M_PI);
                 k0 = k0 < 0 ? 0 : (k0 > nn - 1 ? nn - 1 : k0);
                 int ks = k0 - 1;
                 ks = ks < 0 ? 0 : (ks > nn - 3 ? nn - 3 : ks);
                 const double* v = tab + a * TAB_STRIDE + TAB_V;
-                lagrange4(q, v + ks, tw[a]);
+                lagrange4(qc, v + ks, tw[a]);
+#pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int kk = ks + k;
-                    tapidx[a][k] = kk - 1;
-                    if (kk < 1 || kk > n) tw[a][k] = 0.0;
+                    const bool ok = kk >= 1 && kk <= n;
+                    tapidx[a][k] = ok ? kk - 1 : 0;
+                    if (!ok) tw[a][k] = 0.0;
                 }
             }
         }
         double val = 0.0;
         if (inside) {
-            if (m.nx == 1) {
-                for (int k = 0; k < 4; ++k)
-                    if (tw[0][k] != 0.0) val += tw[0][k] * (double)in[tapidx[0][k]];
-            } else if (m.nx == 2) {
+            if constexpr (NX == 1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) val += tw[0][k] * (double)in[tapidx[0][k]];
+            } else if constexpr (NX == 2) {
+#pragma unroll
                 for (int k0 = 0; k0 < 4; ++k0) {
-                    if (tw[0][k0] == 0.0) continue;
+                    const T* row = in + (size_t)tapidx[0][k0] * m.N[1];
                     double rs = 0.0;
-                    for (int k1 = 0; k1 < 4; ++k1)
-                        if (tw[1][k1] != 0.0)
-                            rs += tw[1][k1] * (double)in[(size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]];
+#pragma unroll
+                    for (int k1 = 0; k1 < 4; ++k1) rs += tw[1][k1] * (double)row[tapidx[1][k1]];
                     val += tw[0][k0] * rs;
                 }
-            } else if (m.nx == 3) {
+            } else if constexpr (NX == 3) {
+#pragma unroll
                 for (int k0 = 0; k0 < 4; ++k0) {
-                    if (tw[0][k0] == 0.0) continue;
                     double ps = 0.0;
+#pragma unroll
                     for (int k1 = 0; k1 < 4; ++k1) {
-                        if (tw[1][k1] == 0.0) continue;
+                        const T* row = in + ((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2];
                         double rs = 0.0;
-                        for (int k2 = 0; k2 < 4; ++k2)
-                            if (tw[2][k2] != 0.0)
-                                rs += tw[2][k2] *
-                                      (double)in[((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2] +
-                                                 tapidx[2][k2]];
+#pragma unroll
+                        for (int k2 = 0; k2 < 4; ++k2) rs += tw[2][k2] * (double)row[tapidx[2][k2]];
                         ps += tw[1][k1] * rs;
                     }
                     val += tw[0][k0] * ps;
                 }
             } else {
                 for (int k0 = 0; k0 < 4; ++k0) {
-                    if (tw[0][k0] == 0.0) continue;
                     double s1 = 0.0;
                     for (int k1 = 0; k1 < 4; ++k1) {
-                        if (tw[1][k1] == 0.0) continue;
                         double s2 = 0.0;
+#pragma unroll
                         for (int k2 = 0; k2 < 4; ++k2) {
-                            if (tw[2][k2] == 0.0) continue;
-                            const size_t row =
-                                (((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2] + tapidx[2][k2]) * m.N[3];
+                            const T* row =
+                                in + (((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2] + tapidx[2][k2]) * m.N[3];
                             double s3 = 0.0;
-                            for (int k3 = 0; k3 < 4; ++k3)
-                                if (tw[3][k3] != 0.0) s3 += tw[3][k3] * (double)in[row + tapidx[3][k3]];
+#pragma unroll
+                            for (int k3 = 0; k3 < 4; ++k3) s3 += tw[3][k3] * (double)row[tapidx[3][k3]];
                             s2 += tw[2][k2] * s3;
                         }
                         s1 += tw[1][k1] * s2;
@@ -1214,8 +1217,12 @@ hipError_t launch_interp(const KModel& m, DevDesc* d, const double* tab, double*
     for (int a = 0; a < m.nx; ++a)
         hipLaunchKernelGGL(k_interp_axis<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, W, a, seq[a],
                            seq[a + 1], part, chunk, a == m.nx - 1 ? 1 : 0);
-    hipLaunchKernelGGL(k_interp_lagrange<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, post, res, part,
-                       chunk);
+    switch (m.nx) {
+        case 1: hipLaunchKernelGGL((k_interp_lagrange<T, 1>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, post, res, part, chunk); break;
+        case 2: hipLaunchKernelGGL((k_interp_lagrange<T, 2>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, post, res, part, chunk); break;
+        case 3: hipLaunchKernelGGL((k_interp_lagrange<T, 3>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, post, res, part, chunk); break;
+        default: hipLaunchKernelGGL((k_interp_lagrange<T, 4>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, post, res, part, chunk); break;
+    }
     hipLaunchKernelGGL(k_interp_finalize, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb);
     return hipGetLastError();
 }
