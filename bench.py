@@ -292,6 +292,21 @@ def run_batched(args):
         after = [B.pmf_get_state(fs[i])[1:] for i in sample]
         sampled = (sample, before, after, Z[k].copy())
         k += 1
+        # 8 steps per call through one captured graph (pmf_batch_run), synchronous,
+        # beside the plain per-step launches of the timed region
+        Kg, reps = 8, 5
+        zg = np.stack([Z[(k + j) % K] for j in range(Kg)])
+        B.pmf_batch_run(ctx, fa, T, zg)        # capture + first replay
+        tg = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            B.pmf_batch_run(ctx, fa, T, zg)
+            tg.append(1e3 * (time.perf_counter() - t1) / Kg)
+        out["graph_run"] = {"ms_per_step": float(np.median(tg)), "steps_per_call": Kg,
+                            "plain_ms_per_step": ms_per_step,
+                            "what": "pmf_batch_run: 8 steps captured into one HIP graph, replayed (z upload, "
+                                    "log-likelihoods back and a host synchronisation per call), median of 5 calls"}
+        log(f"bench: graph of {Kg} steps {np.median(tg):.3f} ms/step vs plain {ms_per_step:.3f} ms/step")
         # plain single-filter FP64 GPU path on a sample of the same filters
         sub = scs[:64]
         ff = [B.pmf_create(ctx, sc.model.with_(precision=W.FP64), sc.prior) for sc in sub]

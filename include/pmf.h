@@ -232,6 +232,18 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
 pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T,
                           const double* z, double* loglik, void* stream);
 
+/* K cycles predict(T) + update(z_k) of n filters back to back, for measurements
+ * known ahead (replays, offline passes, benchmarks): the same filters, results
+ * and rules as K calls of pmf_batch_step (bit for bit).  z: K rows of n * nz_max
+ * doubles (row k: step k, filter order as `filters`); loglik: NULL or K * n
+ * doubles (row k: step k).  1 <= K <= 256.  The K steps' launches (planning and
+ * fused kernel per step) are captured into one HIP graph per filter set, T and K,
+ * cached with the batch set-up, and replayed on a private stream after one copy
+ * of all K rows of z.  Synchronous: waits for the caller's `stream` first, and
+ * returns when the K steps have completed and loglik is written. */
+pmf_status pmf_batch_run(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, int K,
+                         const double* z, double* loglik, void* stream);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid allocation): pmf_batch_step without
  * any allocation.  Same arguments, filters and results as pmf_batch_step, at most

@@ -100,6 +100,7 @@ def lib():
             "pmf_set_state": (ip, [vp, vp, C.c_size_t]),
             "pmf_batch_step": (ip, [vp, C.POINTER(vp), ip, C.c_double, dp, dp, vp]),
             "pmf_batch_step_noalloc": (ip, [vp, C.POINTER(vp), ip, C.c_double, dp, dp, vp]),
+            "pmf_batch_run": (ip, [vp, C.POINTER(vp), ip, C.c_double, ip, dp, dp, vp]),
             "pmf_density_ptr": (vp, [vp]),
             "pmf_stream_sync": (ip, [vp]),
             "pmf_batch_profile": (ip, [vp, ip]),
@@ -129,7 +130,7 @@ def lib():
 
 EXPORTED = ("pmf_ctx_create", "pmf_ctx_destroy", "pmf_create", "pmf_destroy", "pmf_predict",
             "pmf_update", "pmf_moments", "pmf_sync_status", "pmf_last_substeps", "pmf_get_state",
-            "pmf_set_state", "pmf_batch_step", "pmf_batch_step_noalloc", "pmf_density_ptr", "pmf_stream_sync", "pmf_batch_profile",
+            "pmf_set_state", "pmf_batch_step", "pmf_batch_step_noalloc", "pmf_batch_run", "pmf_density_ptr", "pmf_stream_sync", "pmf_batch_profile",
             "pmf_batch_kernel_time", "pmf_autotune", "pmf_get_schedule", "pmf_set_schedule", "pmf_last_error", "pmf_server_create", "pmf_server_destroy",
             "pmf_server_add_track", "pmf_server_remove_track", "pmf_server_submit", "pmf_server_submit_cycle", "pmf_server_poll",
             "pmf_server_drain", "pmf_server_stats_get", "pmf_server_filter")
@@ -385,6 +386,19 @@ def pmf_batch_step(ctx, filters, T: float, z, stream=None, want_loglik: bool = F
                                 _stream(stream)))
     if want_loglik:
         _check(lib().pmf_stream_sync(_stream(stream)))
+    return ll
+
+
+def pmf_batch_run(ctx, filters, T: float, z, stream=None):
+    """K cycles at once from z of shape (K, n, nz_max) (one captured graph,
+    synchronous); returns the (K, n) log-likelihoods."""
+    fa = filters if isinstance(filters, FilterArray) else FilterArray(filters)
+    n = fa.n
+    zz = np.ascontiguousarray(np.asarray(z, float).reshape(-1, n, np.asarray(z).shape[-1]))
+    K = zz.shape[0]
+    ll = np.full((K, n), np.nan)
+    _check(lib().pmf_batch_run(ctx, fa.arr, n, float(T), K, zz.ctypes.data_as(C.POINTER(C.c_double)),
+                               ll.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
     return ll
 
 

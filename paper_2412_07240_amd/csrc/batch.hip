@@ -1534,9 +1534,33 @@ struct BatchCache {
     int grid = 0, bufcplx = 0;
     std::vector<int> order;                   // filter index of each item
     long long leaves_seen = -1;               // pmf_ctx::batch_leaves when all filters last entered
+    // pmf_batch_run: K steps captured into one graph, replayed on a private stream
+    int run_k = 0;
+    hipStream_t run_st = nullptr;
+    hipGraph_t run_graph = nullptr;
+    hipGraphExec_t run_exec = nullptr;
+    double* d_zrun = nullptr;                 // K rows of n * nzmax, item order
+    double* d_llrun = nullptr;                // K rows of n, item order
+    double* h_zrun = nullptr;                 // pinned staging of both
+    double* h_llrun = nullptr;
+    hipEvent_t run_ev = nullptr;
 };
 
 namespace pmf {
+
+// the captured K-step graph and its buffers (the private stream stays)
+static void run_free(pmf_ctx* ctx, BatchCache* c) {
+    if (c->run_exec) (void)hipGraphExecDestroy(c->run_exec);
+    if (c->run_graph) (void)hipGraphDestroy(c->run_graph);
+    ctx_free(ctx, c->d_zrun, nullptr);
+    ctx_free(ctx, c->d_llrun, nullptr);
+    if (c->h_zrun) (void)hipHostFree(c->h_zrun);
+    if (c->h_llrun) (void)hipHostFree(c->h_llrun);
+    c->run_exec = nullptr;
+    c->run_graph = nullptr;
+    c->d_zrun = c->d_llrun = c->h_zrun = c->h_llrun = nullptr;
+    c->run_k = 0;
+}
 
 static void cache_free(pmf_ctx* ctx, BatchCache* c) {
     if (!c) return;
@@ -1551,6 +1575,9 @@ static void cache_free(pmf_ctx* ctx, BatchCache* c) {
         if (c->h_z[i]) (void)hipHostFree(c->h_z[i]);
     for (int i = 0; i < 2; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    run_free(ctx, c);
+    if (c->run_st) (void)hipStreamDestroy(c->run_st);
+    if (c->run_ev) (void)hipEventDestroy(c->run_ev);
     delete c;
 }
 
@@ -1937,14 +1964,14 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
 
 }  // namespace pmf
 
-extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, const double* z,
-                                     double* loglik, void* stream) {
-    using namespace pmf;
-    if (!ctx || n < 1 || !filters || !z) return fail(PMF_E_INVALID, "NULL argument or n < 1");
-    if (!std::isfinite(T) || !(T > 0.0)) return fail(PMF_E_INVALID, "T must be finite and > 0");
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    const hipStream_t st = static_cast<hipStream_t>(stream);
+namespace pmf {
+
+// The cached launch set-up for (filters, T, stream), validated and built when the
+// set is new or one of its filters took other calls since; zrows rows of z (each
+// n * nz_max) are checked for finite values then.
+static pmf_status batch_prepare(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, const double* z, int zrows,
+                                hipStream_t st, BatchCache** out) {
+    hipError_t e = hipSuccess;
     BatchCache* c = ctx->batch;
     const bool same = c && c->n == n && c->T == T && c->stream == st &&
                       std::equal(filters, filters + n, c->filters.begin());
@@ -1959,7 +1986,7 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             if (!batch_fusable(filters[i], &why)) return fail(PMF_E_INVALID, "filter not fusable: " + why);
             nzmax = std::max(nzmax, filters[i]->model.nz);
         }
-        for (int i = 0; i < n * nzmax; ++i)
+        for (size_t i = 0; i < (size_t)zrows * n * nzmax; ++i)
             if (!std::isfinite(z[i])) return fail(PMF_E_INVALID, "non-finite measurement");
         if (!same) {
             // a filter listed twice would be stepped twice in one launch, racing with itself
@@ -1981,6 +2008,25 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
             c = ctx->batch;
         }
         c->leaves_seen = ctx->batch_leaves;
+    }
+    *out = c;
+    return PMF_OK;
+}
+
+}  // namespace pmf
+
+extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, const double* z,
+                                     double* loglik, void* stream) {
+    using namespace pmf;
+    if (!ctx || n < 1 || !filters || !z) return fail(PMF_E_INVALID, "NULL argument or n < 1");
+    if (!std::isfinite(T) || !(T > 0.0)) return fail(PMF_E_INVALID, "T must be finite and > 0");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchCache* c = nullptr;
+    {
+        const pmf_status s = batch_prepare(ctx, filters, n, T, z, 1, st, &c);
+        if (s != PMF_OK) return s;
     }
     const int nzmax = c->nzmax;
     // stage z in mapped pinned memory, rows in item order, checking it on the way;
@@ -2039,6 +2085,76 @@ extern "C" pmf_status pmf_batch_step(pmf_ctx* ctx, pmf_filter* const* filters, i
     if (e == hipSuccess && k % BatchCache::ZEVERY == BatchCache::ZEVERY - 1) e = hipEventRecord(c->ev[evi], st);
     if (e == hipSuccess && loglik) e = hipMemcpyAsync(loglik, c->d_ll, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return PMF_OK;
+}
+
+extern "C" pmf_status pmf_batch_run(pmf_ctx* ctx, pmf_filter* const* filters, int n, double T, int K,
+                                    const double* z, double* loglik, void* stream) {
+    using namespace pmf;
+    if (!ctx || n < 1 || !filters || !z) return fail(PMF_E_INVALID, "NULL argument or n < 1");
+    if (K < 1 || K > 256) return fail(PMF_E_INVALID, "K must be in 1..256");
+    if (!std::isfinite(T) || !(T > 0.0)) return fail(PMF_E_INVALID, "T must be finite and > 0");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchCache* c = nullptr;
+    {
+        const pmf_status s = batch_prepare(ctx, filters, n, T, z, K, st, &c);
+        if (s != PMF_OK) return s;
+    }
+    const int nzmax = c->nzmax;
+    const size_t zn = (size_t)K * n * nzmax;
+    for (size_t i = 0; i < zn; ++i)
+        if (!std::isfinite(z[i])) return fail(PMF_E_INVALID, "non-finite measurement");
+    // the caller's earlier work on these filters first: the run goes on a private stream
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess && !c->run_st) e = hipStreamCreateWithFlags(&c->run_st, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "batch run set-up");
+    if (c->run_k != K) {
+        run_free(ctx, c);
+        c->d_zrun = static_cast<double*>(ctx_alloc(ctx, sizeof(double) * zn, nullptr));
+        c->d_llrun = static_cast<double*>(ctx_alloc(ctx, sizeof(double) * K * n, nullptr));
+        if (!c->d_zrun || !c->d_llrun) {
+            run_free(ctx, c);
+            return fail(PMF_E_NOMEM, "batch run buffers");
+        }
+        e = hipHostMalloc(reinterpret_cast<void**>(&c->h_zrun), sizeof(double) * zn, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&c->h_llrun), sizeof(double) * K * n, hipHostMallocDefault);
+        // the K steps as one graph: per step the planning kernel (z from row k of
+        // the device copy) and the fused kernel (log-likelihoods into row k)
+        if (e == hipSuccess) e = hipStreamBeginCapture(c->run_st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int k = 0; k < K; ++k) {
+                const double* zk = c->d_zrun + (size_t)k * n * nzmax;
+                hipLaunchKernelGGL(k_batch_plan, dim3((n + PLAN_THREADS - 1) / PLAN_THREADS), dim3(PLAN_THREADS), 0,
+                                   c->run_st, c->d_items, c->d_plans, n, zk, nullptr, nzmax);
+                hipLaunchKernelGGL(k_fused, dim3(c->grid), dim3(FUSED_THREADS), c->lds, c->run_st, c->d_groups,
+                                   c->d_items, c->d_plans, zk, nzmax, c->d_llrun + (size_t)k * n, c->bufcplx);
+            }
+            const hipError_t el = hipGetLastError();
+            e = hipStreamEndCapture(c->run_st, &c->run_graph);
+            if (e == hipSuccess) e = el;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->run_exec, c->run_graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            run_free(ctx, c);
+            return hip_fail(e, "batch run capture");
+        }
+        c->run_k = K;
+    }
+    // measurements in item order, one copy for all K steps
+    for (int k = 0; k < K; ++k)
+        for (int q = 0; q < n; ++q)
+            std::memcpy(c->h_zrun + ((size_t)k * n + q) * nzmax, z + ((size_t)k * n + c->order[q]) * nzmax,
+                        sizeof(double) * nzmax);
+    e = hipMemcpyAsync(c->d_zrun, c->h_zrun, sizeof(double) * zn, hipMemcpyHostToDevice, c->run_st);
+    if (e == hipSuccess) e = hipGraphLaunch(c->run_exec, c->run_st);
+    if (e == hipSuccess && loglik)
+        e = hipMemcpyAsync(c->h_llrun, c->d_llrun, sizeof(double) * K * n, hipMemcpyDeviceToHost, c->run_st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->run_st);
+    if (e != hipSuccess) return hip_fail(e, "batch run");
+    if (loglik) std::memcpy(loglik, c->h_llrun, sizeof(double) * K * n);   // filter order
     return PMF_OK;
 }
 
