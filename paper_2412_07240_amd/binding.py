@@ -390,11 +390,16 @@ def pmf_batch_step(ctx, filters, T: float, z, stream=None, want_loglik: bool = F
 
 
 def pmf_batch_run(ctx, filters, T: float, z, stream=None):
-    """K cycles at once from z of shape (K, n, nz_max) (one captured graph,
-    synchronous); returns the (K, n) log-likelihoods."""
+    """K cycles at once from z of shape (K, n, nz_max), or (K, n) when every nz is 1
+    (one captured graph, synchronous); returns the (K, n) log-likelihoods."""
     fa = filters if isinstance(filters, FilterArray) else FilterArray(filters)
     n = fa.n
-    zz = np.ascontiguousarray(np.asarray(z, float).reshape(-1, n, np.asarray(z).shape[-1]))
+    zz = np.asarray(z, float)
+    if zz.ndim == 2:
+        zz = zz[:, :, None]
+    if zz.ndim != 3 or zz.shape[1] != n:
+        raise ValueError(f"z must have shape (K, {n}, nz_max) or (K, {n}), not {np.shape(z)}")
+    zz = np.ascontiguousarray(zz)
     K = zz.shape[0]
     ll = np.full((K, n), np.nan)
     _check(lib().pmf_batch_run(ctx, fa.arr, n, float(T), K, zz.ctypes.data_as(C.POINTER(C.c_double)),
