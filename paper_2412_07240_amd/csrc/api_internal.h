@@ -20,7 +20,7 @@ struct pmf_ctx {
     std::vector<hipEvent_t> ev_pool;             // start/stop pairs, reused
     int ev_used = 0;
     hipStream_t ev_stream = nullptr;
-    int sched[16] = {};                          // fused-kernel schedule per group type (autotuner)
+    int sched[40] = {};                          // fused-kernel schedule per group type (autotuner)
 };
 
 struct pmf_filter {

@@ -1371,8 +1371,15 @@ __device__ __forceinline__ void process_group(const BItem* __restrict__ items, c
 // group types served by the fused kernel
 enum {
     GT_2D_128, GT_2D_96, GT_2D_64, GT_2D_48, GT_2D_32,
-    GT_1D_256, GT_1D_192, GT_1D_128, GT_1D_96, GT_1D_64, GT_1D_48, GT_1D_32, GT_COUNT
+    GT_1D_256, GT_1D_192, GT_1D_128, GT_1D_96, GT_1D_64, GT_1D_48, GT_1D_32,
+    // rectangular 2-D grids N0 x N1 (N0 != N1, both in 128, 96, 64, 48, 32):
+    // GT_2R + 5 i0 + i1 with i the position in that list (the diagonal unused)
+    GT_2R, GT_COUNT = GT_2R + 25
 };
+static_assert(GT_COUNT <= 40, "pmf_ctx::sched holds one entry per group type");
+
+constexpr int size_index_c(int n) { return n == 128 ? 0 : n == 96 ? 1 : n == 64 ? 2 : n == 48 ? 3 : n == 32 ? 4 : -1; }
+constexpr int rect_type(int n0, int n1) { return GT_2R + 5 * size_index_c(n0) + size_index_c(n1); }
 
 template <int N0, int N1>
 constexpr int group_g() {
@@ -1429,6 +1436,27 @@ k_fused(const GItem* __restrict__ groups, const BItem* __restrict__ items, const
             PMF_GROUP_V(GT_1D_64, 1, 64, 1, 0)
             PMF_GROUP_V(GT_1D_48, 1, 48, 1, 0)
             PMF_GROUP_V(GT_1D_32, 1, 32, 1, 0)
+            // rectangular 2-D grids: the default schedule only
+            PMF_GROUP_V(rect_type(128, 96), 128, 96, 2, 0)
+            PMF_GROUP_V(rect_type(128, 64), 128, 64, 2, 0)
+            PMF_GROUP_V(rect_type(128, 48), 128, 48, 2, 0)
+            PMF_GROUP_V(rect_type(128, 32), 128, 32, 2, 0)
+            PMF_GROUP_V(rect_type(96, 128), 96, 128, 2, 0)
+            PMF_GROUP_V(rect_type(96, 64), 96, 64, 2, 0)
+            PMF_GROUP_V(rect_type(96, 48), 96, 48, 2, 0)
+            PMF_GROUP_V(rect_type(96, 32), 96, 32, 2, 0)
+            PMF_GROUP_V(rect_type(64, 128), 64, 128, 2, 0)
+            PMF_GROUP_V(rect_type(64, 96), 64, 96, 2, 0)
+            PMF_GROUP_V(rect_type(64, 48), 64, 48, 2, 0)
+            PMF_GROUP_V(rect_type(64, 32), 64, 32, 2, 0)
+            PMF_GROUP_V(rect_type(48, 128), 48, 128, 2, 0)
+            PMF_GROUP_V(rect_type(48, 96), 48, 96, 2, 0)
+            PMF_GROUP_V(rect_type(48, 64), 48, 64, 2, 0)
+            PMF_GROUP_V(rect_type(48, 32), 48, 32, 2, 0)
+            PMF_GROUP_V(rect_type(32, 128), 32, 128, 2, 0)
+            PMF_GROUP_V(rect_type(32, 96), 32, 96, 2, 0)
+            PMF_GROUP_V(rect_type(32, 64), 32, 64, 2, 0)
+            PMF_GROUP_V(rect_type(32, 48), 32, 48, 2, 0)
             default: break;
         }
 #undef PMF_GROUP_2D
@@ -1437,7 +1465,22 @@ k_fused(const GItem* __restrict__ groups, const BItem* __restrict__ items, const
 }
 
 // host copy of the group sizes / types
+static int size_index(int n) {
+    switch (n) {
+        case 128: return 0;
+        case 96: return 1;
+        case 64: return 2;
+        case 48: return 3;
+        case 32: return 4;
+    }
+    return -1;
+}
+
 static int group_type(int nx, int n0, int n1) {
+    if (nx == 2 && n0 != n1) {
+        const int i0 = size_index(n0), i1 = size_index(n1);
+        return (i0 < 0 || i1 < 0) ? -1 : GT_2R + 5 * i0 + i1;
+    }
     if (nx == 2 && n0 == n1) {
         switch (n1) {
             case 128: return GT_2D_128;
@@ -1493,6 +1536,26 @@ static int group_capacity(int type, int v) {
         case GT_1D_64: return group_g<1, 64>();
         case GT_1D_48: return group_g<1, 48>();
         case GT_1D_32: return group_g<1, 32>();
+        case rect_type(128, 96): return group_g<128, 96>();
+        case rect_type(128, 64): return group_g<128, 64>();
+        case rect_type(128, 48): return group_g<128, 48>();
+        case rect_type(128, 32): return group_g<128, 32>();
+        case rect_type(96, 128): return group_g<96, 128>();
+        case rect_type(96, 64): return group_g<96, 64>();
+        case rect_type(96, 48): return group_g<96, 48>();
+        case rect_type(96, 32): return group_g<96, 32>();
+        case rect_type(64, 128): return group_g<64, 128>();
+        case rect_type(64, 96): return group_g<64, 96>();
+        case rect_type(64, 48): return group_g<64, 48>();
+        case rect_type(64, 32): return group_g<64, 32>();
+        case rect_type(48, 128): return group_g<48, 128>();
+        case rect_type(48, 96): return group_g<48, 96>();
+        case rect_type(48, 64): return group_g<48, 64>();
+        case rect_type(48, 32): return group_g<48, 32>();
+        case rect_type(32, 128): return group_g<32, 128>();
+        case rect_type(32, 96): return group_g<32, 96>();
+        case rect_type(32, 64): return group_g<32, 64>();
+        case rect_type(32, 48): return group_g<32, 48>();
     }
     return 0;
 }
@@ -1644,7 +1707,7 @@ bool model_fusable(const pmf_model& m, std::string* why) {
     if (m.integrator != PMF_INT_EXACT && m.substeps > FUSED_LMAX) return *why = "more than 64 substeps", false;
     const int n0 = m.nx == 2 ? m.N[0] : 1, n1 = m.nx == 2 ? m.N[1] : m.N[0];
     if (group_type(m.nx, n0, n1) < 0)
-        return *why = "grid size without a fused form (2-D: N x N, N in {32,48,64,96,128}; "
+        return *why = "grid size without a fused form (2-D: N0 x N1, N0 and N1 in {32,48,64,96,128}; "
                       "1-D: N in {32,48,64,96,128,192,256})", false;
     return true;
 }

@@ -59,22 +59,23 @@ def test_torch_caching_allocator_backs_filters_and_batches(B):
     assert torch.cuda.memory_allocated(0) == base
 
 
-def test_batch_refuses_rectangular_2d_grids_up_front(B):
-    """The fused kernel has square forms only (N x N, N in {32, 48, 64, 96, 128}):
-    a rectangular 2-D filter is refused before anything runs, and still steps
-    through pmf_predict / pmf_update."""
+def test_batch_refuses_grids_without_a_fused_form_up_front(B):
+    """The fused kernel has forms for N0 x N1 with N0, N1 in {32, 48, 64, 96, 128}
+    (square and rectangular): any other 2-D grid is refused before anything runs,
+    and still steps through pmf_predict / pmf_update."""
     ctx = B.pmf_ctx_create(0)
     try:
         sc = W.batched_workload(1, K=1)[0]
-        m = sc.model.with_(N=(64, 32))
-        f = B.pmf_create(ctx, m, sc.prior)
-        try:
-            with pytest.raises(B.PmfError) as e:
-                B.pmf_batch_step(ctx, [f], sc.T, np.asarray(sc.z[:1]))
-            assert e.value.status == B.PMF_E_INVALID and "fused form" in str(e.value)
-            B.pmf_predict(f, sc.T)
-            assert np.isfinite(B.pmf_update(f, sc.z[0], want_loglik=True))
-        finally:
-            B.pmf_destroy(f)
+        for N in ((80, 64), (64, 40)):
+            m = sc.model.with_(N=N)
+            f = B.pmf_create(ctx, m, sc.prior)
+            try:
+                with pytest.raises(B.PmfError) as e:
+                    B.pmf_batch_step(ctx, [f], sc.T, np.asarray(sc.z[:1]))
+                assert e.value.status == B.PMF_E_INVALID and "fused form" in str(e.value), (N, str(e.value))
+                B.pmf_predict(f, sc.T)
+                assert np.isfinite(B.pmf_update(f, sc.z[0], want_loglik=True))
+            finally:
+                B.pmf_destroy(f)
     finally:
         B.pmf_ctx_destroy(ctx)

@@ -5,6 +5,8 @@ Bar (FP32 densities): L1 <= 1e-5 and every point within 1e-5 of the peak, per
 filter per step, vs the oracle started from the same state; designed grids
 within the bars derived in gpu_common (step 1e-5 relative, centre 1e-4 cells);
 log-likelihood to 1e-4 relative."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -81,6 +83,34 @@ def test_batch_lockstep_mixed_sizes(B, ctx):
             before = [B.pmf_get_state(f)[1:] for f in fs]
             lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, k), want_loglik=True)
             what = f"lockstep step {k}"
+            _K[what] = k
+            worst = check_against_oracle(B, fs, scs, before, lls, what)
+            note(f"  step {k}: worst L1 {worst[0]:.2e}  pointwise {worst[1]:.2e}  "
+                 f"grid dM {worst[2]:.1e}  dc {worst[3]:.1e} cells")
+    finally:
+        for f in fs:
+            B.pmf_destroy(f)
+
+
+RECT = ((128, 32), (32, 128), (96, 48), (48, 128), (64, 96), (128, 64), (32, 48))
+
+
+def test_batch_rectangular_grids_lockstep(B, ctx):
+    """Rectangular N0 x N1 grids in one batch with square ones: three steps, each
+    against the oracle's step from the same pre-step state (the FP32 bars of the
+    mixed-size test); counts per shape leave ragged last groups."""
+    scs = []
+    for i in range(30):
+        sc = W.batched_filter(200 + i, K=3)
+        n0, n1 = RECT[i % len(RECT)] if i < 26 else (sc.model.N[0], sc.model.N[0])
+        scs.append(dataclasses.replace(sc, model=sc.model.with_(N=(n0, n1))))
+    note(f"case: batch of 30 2-D filters, rectangular shapes {RECT} and 4 square")
+    fs = make(B, ctx, scs)
+    try:
+        for k in range(3):
+            before = [B.pmf_get_state(f)[1:] for f in fs]
+            lls = B.pmf_batch_step(ctx, fs, scs[0].T, zmat(scs, k), want_loglik=True)
+            what = f"rectangular step {k}"
             _K[what] = k
             worst = check_against_oracle(B, fs, scs, before, lls, what)
             note(f"  step {k}: worst L1 {worst[0]:.2e}  pointwise {worst[1]:.2e}  "
