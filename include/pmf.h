@@ -219,8 +219,11 @@ pmf_status pmf_set_state(pmf_filter* f, const void* host_buf, size_t bytes);
 /* One predict(T) + update(z) cycle for n >= 1 filters in one fused launch
  * (Fourier grids, FP32 densities; nx = 2 with N0 x N1, N0 and N1 each in 32, 48,
  * 64, 96, 128 (square or rectangular); nx = 1 with N in 32, 48, 64, 96, 128, 192,
- * 256; the RK4 and Euler integrators with at most 64 substeps; other filters,
- * n < 1 and NULL arguments are rejected with PMF_E_INVALID before anything runs).
+ * 256; other filters, n < 1 and NULL arguments are rejected with PMF_E_INVALID
+ * before anything runs).  RK4 and Euler filters take at most 64 substeps in the
+ * fused form: one whose clamp asks for more at run time is left as it was by
+ * the cycle (grid, time, density up to FP32 rounding) with PMF_E_INVALID in its
+ * status word, for the caller to step it through pmf_predict / pmf_update.
  * z: n * nz_max doubles, row f holds filter f's measurement (nz_max = largest nz);
  * copied into pinned staging before the call returns (the caller may reuse it).
  * loglik: NULL or n doubles written by an asynchronous copy (as pmf_update).

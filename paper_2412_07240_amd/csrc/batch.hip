@@ -336,6 +336,15 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ zs, int nzma
     P.etr = etr;
     P.tnew = t0 + T;
     P.status = status0;
+    if (P.bad) {
+        // more substeps than the fused form holds: the cycle leaves the filter as it
+        // was (unit gain, no grid move or time step; the update is rejected) and
+        // flags PMF_E_INVALID, so that the caller can run it on the generic path
+        P.gc[0] = P.gc[1] = P.gc[2] = 0.0;
+        P.etr = 1.0;
+        P.tnew = t0;
+        mat_eye(Phi, n);
+    }
     // grid follows x' = A x
     double c2[MS], M2[MSQ];
     mat_zero(M2);
@@ -358,7 +367,7 @@ __device__ void plan_one(const BItem& I, const double* __restrict__ zs, int nzma
     P.Wnom[0] = Wn0;
     P.Wnom[1] = Wn1;
     P.span = span;
-    P.integ = integ;
+    P.integ = P.bad ? PMF_INT_EXACT : integ;
     P.interp = interp;
     P.nx = n;
     P.par = par;
@@ -845,7 +854,7 @@ __device__ void filter_commit(const FState& F, double* ll_out) {
         ll_out[F.idx] = F.loglik;
     } else {
         d->loglik = NAN;
-        d->status = P.status | PMF_E_DEGENERATE | F.bits | (P.bad ? PMF_E_INVALID : 0);
+        d->status = P.status | F.bits | (P.bad ? PMF_E_INVALID : PMF_E_DEGENERATE);
         d->pscale = 1.0;
         ll_out[F.idx] = NAN;
     }

@@ -120,6 +120,43 @@ def test_batch_rectangular_grids_lockstep(B, ctx):
             B.pmf_destroy(f)
 
 
+def test_batch_step_beyond_the_fused_substep_limit_leaves_the_filter(B, ctx):
+    """An RK4 filter whose clamp needs more substeps than the fused form holds (64)
+    at run time: the batched cycle leaves its grid, time and density as they were
+    (the density up to the FP32 round trip of the transforms), flags PMF_E_INVALID,
+    and the same filter then steps on the generic path like its twin."""
+    A = np.array([[-0.2, 0.1], [0.05, -0.3]])
+    m = W.ModelSpec(nx=2, A=A, Q=np.diag([0.5, 0.5]), N=(32, 32), t_nominal=0.05, integrator=W.INT_RK4,
+                    substeps=1, precision=W.FP32, meas_kind=W.H_LINEAR, nz=2, H=np.eye(2),
+                    **W.gaussian_noise(0.3 ** 2 * np.eye(2)))
+    prior = W.gaussian_prior([0.0, 0.0], 0.3 ** 2 * np.eye(2))
+    T = 1.0
+    assert oracle.substeps(m, oracle.create(m, prior), T) > 64   # the case's premise
+    note("case: RK4 filter needing more than 64 substeps in a batched step (32^2, T = 1)")
+    f = B.pmf_create(ctx, m, prior)
+    g = B.pmf_create(ctx, m, prior)
+    try:
+        _, c0, M0, t0, P0 = B.pmf_get_state(f)
+        z = np.array([[0.1, -0.05]])
+        B.pmf_batch_step(ctx, [f], T, z)
+        st = B.lib().pmf_sync_status(f, None)
+        assert st & B.PMF_E_INVALID and not st & B.PMF_E_DEGENERATE, st
+        _, c1, M1, t1, P1 = B.pmf_get_state(f)
+        assert np.array_equal(c1, c0) and np.array_equal(M1, M0) and t1 == t0
+        d = np.abs(P1 - P0).max() / np.abs(P0).max()
+        note(f"  state kept: density within {d:.1e} of the peak (FFT round trip)")
+        assert d <= 1e-5
+        # the generic path takes it, as it takes the twin
+        for h in (f, g):
+            B.pmf_predict(h, T)
+        lf = B.pmf_update(f, z[0], want_loglik=True)
+        lg = B.pmf_update(g, z[0], want_loglik=True)
+        assert np.isfinite(lf) and abs(lf - lg) <= 1e-4 * max(1.0, abs(lg)), (lf, lg)
+    finally:
+        B.pmf_destroy(f)
+        B.pmf_destroy(g)
+
+
 @pytest.mark.timeout(900)
 def test_batch_50_steps_free_running_and_per_step(B, ctx):
     """40 mixed-size filters carried through 50 batched steps with no
