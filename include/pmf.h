@@ -135,6 +135,12 @@ typedef struct {
 typedef struct pmf_ctx pmf_ctx;
 typedef struct pmf_filter pmf_filter;
 
+/* Checks a model as pmf_create does, on the host only (no device is touched):
+ * PMF_OK, or PMF_E_INVALID with the reason in pmf_last_error().  With fusable
+ * not NULL, *fusable is set to 1 if pmf_batch_step accepts filters of this model
+ * and to 0 otherwise, the reason then written to why (NULL, or why_len bytes). */
+pmf_status pmf_model_check(const pmf_model* model, int* fusable, char* why, size_t why_len);
+
 /* Context bound to one HIP device.  `a` may be NULL (hipMalloc/hipFree); else
  * every device allocation of the context's filters and batches goes through
  * a->alloc / a->free (e.g. a framework's caching allocator), which may be called

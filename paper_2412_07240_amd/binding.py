@@ -87,6 +87,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
         sig = {
+            "pmf_model_check": (ip, [C.POINTER(pmf_model), C.POINTER(C.c_int), C.c_char_p, C.c_size_t]),
             "pmf_ctx_create": (ip, [ip, C.POINTER(pmf_allocator), C.POINTER(vp)]),
             "pmf_ctx_destroy": (None, [vp]),
             "pmf_create": (ip, [vp, C.POINTER(pmf_model), C.POINTER(pmf_prior), C.POINTER(vp)]),
@@ -128,7 +129,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("pmf_ctx_create", "pmf_ctx_destroy", "pmf_create", "pmf_destroy", "pmf_predict",
+EXPORTED = ("pmf_model_check", "pmf_ctx_create", "pmf_ctx_destroy", "pmf_create", "pmf_destroy", "pmf_predict",
             "pmf_update", "pmf_moments", "pmf_sync_status", "pmf_last_substeps", "pmf_get_state",
             "pmf_set_state", "pmf_batch_step", "pmf_batch_step_noalloc", "pmf_batch_run", "pmf_density_ptr", "pmf_stream_sync", "pmf_batch_profile",
             "pmf_batch_kernel_time", "pmf_autotune", "pmf_get_schedule", "pmf_set_schedule", "pmf_last_error", "pmf_server_create", "pmf_server_destroy",
@@ -271,6 +272,16 @@ def pmf_ctx_create(device: int = 0, allocator=None):
 def pmf_ctx_destroy(ctx) -> None:
     lib().pmf_ctx_destroy(ctx)
     _ctx_allocators.pop(getattr(ctx, "value", ctx), None)
+
+
+def pmf_model_check(model):
+    """(fusable, reason) for a valid model (reason "" when fusable); raises
+    PmfError for a model pmf_create would refuse.  Host only: no device is used."""
+    m = make_model(model)
+    fus = C.c_int(0)
+    buf = C.create_string_buffer(512)
+    _check(lib().pmf_model_check(C.byref(m), C.byref(fus), buf, len(buf)))
+    return bool(fus.value), buf.value.decode()
 
 
 def pmf_create(ctx, model, prior):

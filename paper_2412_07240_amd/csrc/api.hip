@@ -338,6 +338,24 @@ using namespace pmf;
 
 extern "C" {
 
+pmf_status pmf_model_check(const pmf_model* model, int* fusable, char* why, size_t why_len) {
+    using namespace pmf;
+    if (why && why_len) why[0] = '\0';
+    const pmf_status s = check_model(model);
+    if (s != PMF_OK) return s;
+    if (fusable) {
+        std::string reason;
+        const bool ok = model_fusable(*model, &reason);
+        *fusable = ok ? 1 : 0;
+        if (!ok && why && why_len) {
+            const size_t k = std::min(why_len - 1, reason.size());
+            std::memcpy(why, reason.data(), k);
+            why[k] = '\0';
+        }
+    }
+    return PMF_OK;
+}
+
 const char* pmf_last_error(void) { return g_last_error.c_str(); }
 
 pmf_status pmf_ctx_create(int device, const pmf_allocator* a, pmf_ctx** out) {
