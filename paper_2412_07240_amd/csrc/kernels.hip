@@ -508,6 +508,19 @@ __device__ inline void node_coords(const KModel& m, const double* tab, int j, do
     }
 }
 
+// the same for a compile-time dimension (the axis loop unrolled)
+template <int NX>
+__device__ inline void node_coords_n(const KModel& m, const double* tab, int j, double* u, int* idx) {
+    int rem = j;
+#pragma unroll
+    for (int a = NX - 1; a >= 0; --a) {
+        const int s = rem % m.N[a];
+        rem /= m.N[a];
+        idx[a] = s;
+        u[a] = tab[a * TAB_STRIDE + s];
+    }
+}
+
 __device__ inline double node_qw(const KModel& m, const double* tab, const int* idx) {
     if (m.grid == PMF_GRID_FOURIER) return 1.0;
     double q = 1.0;
@@ -580,37 +593,60 @@ __device__ inline void acc_point(double* acc, double w, const double* u, bool bo
     if (boundary) acc[NACC - 1] += w;
 }
 
-// fixed-order block reduction of NV doubles per thread (RED_THREADS threads)
+// the same sums over the first NX coordinates only (the others stay zero)
+template <int NX>
+__device__ inline void acc_point_n(double* acc, double w, const double* u, bool boundary) {
+    acc[0] += w;
+#pragma unroll
+    for (int a = 0; a < NX; ++a) {
+        const double wu = w * u[a];
+        acc[1 + a] += wu;
+#pragma unroll
+        for (int b = a; b < NX; ++b) acc[5 + pk(a, b)] += wu * u[b];
+    }
+    if (boundary) acc[NACC - 1] += w;
+}
+
+// Fixed-order block reduction of NV doubles per thread (RED_THREADS threads, all
+// of which must call it): a butterfly over the 64 lanes of each wave (partner
+// lanes add the same two values, so every lane of a wave ends with the same sum),
+// then every thread adds the per-wave sums in wave order.  No barrier inside a
+// wave's tree; two block barriers in all.  Every thread returns the block sums.
 template <int NV>
 __device__ void block_sum(double (&v)[NV], double* sh) {
-    for (int q = 0; q < NV; ++q) sh[q * RED_THREADS + threadIdx.x] = v[q];
+    constexpr int NW = RED_THREADS / 64;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < NV; ++q) sh[q * NW + w] = v[q];
     __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int q = 0; q < NV; ++q)
-                sh[q * RED_THREADS + threadIdx.x] += sh[q * RED_THREADS + threadIdx.x + w];
-        __syncthreads();
+    for (int q = 0; q < NV; ++q) {
+        double t = sh[q * NW];
+        for (int k = 1; k < NW; ++k) t += sh[q * NW + k];
+        v[q] = t;
     }
-    for (int q = 0; q < NV; ++q) v[q] = sh[q * RED_THREADS];
     __syncthreads();
 }
 
 __device__ double block_max(double v, double* sh) {
-    sh[threadIdx.x] = v;
+    constexpr int NW = RED_THREADS / 64;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
-        __syncthreads();
-    }
-    v = sh[0];
+    double t = sh[0];
+    for (int k = 1; k < NW; ++k) t = fmax(t, sh[k]);
     __syncthreads();
-    return v;
+    return t;
 }
 
 // ------------------------------------------------------------------ likelihood + sums
 // mode 0: sums of the density only; mode 1: P_out = P * exp(loglik - s_b) and its sums.
 // Partial b: {s_b, S0, S1[4], S2[10] (packed as pk), Sboundary}, block-relative.
-template <typename T>
+template <typename T, int NX>
 __global__ void __launch_bounds__(RED_THREADS)
 k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T* Pout,
             double* part, int chunk, int mode) {
@@ -625,8 +661,8 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
         for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
             double u[MS] = {0, 0, 0, 0}, x[MS];
             int idx[MS];
-            node_coords(m, tab, j, u, idx);
-            to_phys(g, m.nx, u, x);
+            node_coords_n<NX>(m, tab, j, u, idx);
+            to_phys(g, NX, u, x);
             mx = fmax(mx, loglik_at(m, x, z.v));
         }
         sb = block_max(mx, sh);
@@ -636,17 +672,17 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
     for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
         double u[MS] = {0, 0, 0, 0};
         int idx[MS] = {0, 0, 0, 0};
-        node_coords(m, tab, j, u, idx);
+        node_coords_n<NX>(m, tab, j, u, idx);
         T v = P[j];
         if (mode == 1) {
             double x[MS];
-            to_phys(g, m.nx, u, x);
+            to_phys(g, NX, u, x);
             const double L = loglik_at(m, x, z.v);
             v = v * exp_t((T)(L - sb));
             Pout[j] = v;
         }
         const double w = node_qw(m, tab, idx) * (double)v;
-        acc_point(acc, w, u, node_on_boundary(m, idx));
+        acc_point_n<NX>(acc, w, u, node_on_boundary(m, idx));
     }
     block_sum<NACC>(acc, sh);
     if (threadIdx.x == 0) {
@@ -883,7 +919,7 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
     for (int j = lo + threadIdx.x; j < hi; j += RED_THREADS) {
         double u[MS] = {0, 0, 0, 0}, x[MS], r[MS], nu[MS] = {0, 0, 0, 0};
         int idx[MS] = {0, 0, 0, 0};
-        node_coords(m, tab, j, u, idx);
+        node_coords_n<NX>(m, tab, j, u, idx);
         to_phys(gn, NX, u, x);
 #pragma unroll
         for (int a = 0; a < NX; ++a) r[a] = x[a] - go.c[a];
@@ -982,7 +1018,7 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
         const T vt = (T)val;
         out[j] = vt;
         const double w = node_qw(m, tab, idx) * (double)vt;
-        acc_point(acc, w, u, false);
+        acc_point_n<NX>(acc, w, u, false);
     }
     block_sum<NACC>(acc, sh);
     if (threadIdx.x == 0) {
@@ -1177,8 +1213,12 @@ hipError_t launch_like(const KModel& m, const DevDesc* d, const double* tab, con
                        const T* P, T* Pout, double* part, int nb, int chunk, int mode, hipStream_t st) {
     ZArg za;
     for (int i = 0; i < 3; ++i) za.v[i] = (z && i < m.nz) ? z[i] : 0.0;
-    hipLaunchKernelGGL(k_like_pass<T>, dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, za, P, Pout, part,
-                       chunk, mode);
+    switch (m.nx) {
+        case 1: hipLaunchKernelGGL((k_like_pass<T, 1>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, za, P, Pout, part, chunk, mode); break;
+        case 2: hipLaunchKernelGGL((k_like_pass<T, 2>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, za, P, Pout, part, chunk, mode); break;
+        case 3: hipLaunchKernelGGL((k_like_pass<T, 3>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, za, P, Pout, part, chunk, mode); break;
+        default: hipLaunchKernelGGL((k_like_pass<T, 4>), dim3(nb), dim3(RED_THREADS), 0, st, m, d, tab, za, P, Pout, part, chunk, mode); break;
+    }
     return hipGetLastError();
 }
 
