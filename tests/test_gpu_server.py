@@ -241,3 +241,89 @@ def test_rejected_update_and_invalid_requests(B, ctx):
         assert B.pmf_server_stats_get(srv)["submitted"] == 3
     finally:
         B.pmf_server_destroy(srv)
+
+
+def test_full_size_serving_mix_sampled(B, ctx):
+    """The serving workload at its full size: 10,000 live tracks of the mix (50 % 1-D
+    N 64-256, 40 % 2-D N 32-128, 10 % 3-D N 32-64), two predict + update requests per
+    track submitted as unpaced bursts in shuffled order, so the worker batches across
+    sizes while earlier work is still on the device.  Every request completes with
+    PMF_OK in per-track order; sampled tracks of each dimension end bit for bit where a
+    twin stepped directly ends (fused cycles through pmf_batch_step of the twin alone,
+    the rest through pmf_predict / pmf_update), and their second cycle is held to the
+    oracle in lockstep from the twin's state after the first."""
+    import multiprocessing
+    from gpu_common import check_density, fp32_update_tol, oracle_one_step
+    ntr, K = 10000, 2
+    note(f"case: {ntr} served tracks of the serving mix, {K} cycles each, sampled twins + oracle")
+    scs = [W.serving_track(i, K=K) for i in range(ntr)]
+    nxs = np.array([sc.model.nx for sc in scs])
+    srv = B.pmf_server_create(ctx, 64 << 30, ntr)
+    twins = []
+    try:
+        ids = [B.pmf_server_add_track(srv, sc.model, sc.prior) for sc in scs]
+        rng = np.random.default_rng(np.random.SeedSequence([241207240, 11]))
+        tag = 0
+        who = {}
+        for k in range(K):
+            for i in rng.permutation(ntr):
+                B.pmf_server_submit_cycle(srv, ids[i], scs[i].T, scs[i].z[k], tag=tag)
+                who[tag] = (int(i), k)
+                tag += 2
+        B.pmf_server_drain(srv)
+        done = B.pmf_server_poll(srv, cap=2 * tag + 16)
+        assert len(done) == tag
+        bad = [c for c in done if c["status"] != B.PMF_OK]
+        assert not bad, bad[:5]
+        seen = {}
+        for c in done:                               # completions of a track in submission order
+            i, k = who[c["tag"] - (c["tag"] & 1)]
+            assert c["track"] == ids[i]
+            assert c["tag"] > seen.get(i, -1), (i, c["tag"], seen.get(i))
+            seen[i] = c["tag"]
+        by_tag = {c["tag"]: c for c in done}
+        fused = np.mean([c["fused"] for c in done if c["op"] == B.PMF_OP_UPDATE])
+        st = B.pmf_server_stats_get(srv)
+        note(f"  completed {st['completed']}, fused fraction {fused:.3f}, device bytes {st['used_bytes']}")
+        assert st["completed"] == st["submitted"] == tag and st["fused_ops"] + st["single_ops"] == tag
+        # sampled tracks: 4 of each dimension
+        inv = {v: t for t, v in who.items()}
+        sample = [int(i) for nx in (1, 2, 3) for i in rng.choice(np.flatnonzero(nxs == nx), 4, replace=False)]
+        mid, ll_last = [], []
+        for i in sample:
+            sc = scs[i]
+            f = B.pmf_create(ctx, sc.model, sc.prior)
+            twins.append(f)
+            for k in range(K):
+                if k == K - 1:
+                    _, c0, M0, t0, P0 = B.pmf_get_state(f)
+                    mid.append((sc, k, c0, M0, t0, P0))
+                cu = by_tag[inv[(i, k)] + 1]
+                if cu["fused"]:
+                    ll = B.pmf_batch_step(ctx, [f], sc.T, np.asarray(sc.z[k])[None, :], want_loglik=True)[0]
+                else:
+                    B.pmf_predict(f, sc.T)
+                    ll = B.pmf_update(f, sc.z[k], want_loglik=True)
+                assert cu["loglik"] == ll, (i, k, cu["loglik"], ll)
+            ll_last.append(ll)
+            _, c1, M1, t1, P1 = B.pmf_get_state(B.pmf_server_filter(srv, ids[i]))
+            _, c2, M2, t2, P2 = B.pmf_get_state(f)
+            assert t1 == t2, (i, t1, t2)
+            np.testing.assert_array_equal(c1, c2)
+            np.testing.assert_array_equal(M1, M2)
+            np.testing.assert_array_equal(P1, P2)
+        note(f"  {len(sample)} sampled tracks bit for bit equal to their twins")
+        with multiprocessing.get_context("spawn").Pool(8) as pool:
+            ref = pool.map(oracle_one_step, mid)
+        worst = [0.0, 0.0]
+        for (sc, k, *_), f, (c_o, M_o, t_o, P_o, ll_o, amp), ll in zip(mid, twins, ref, ll_last):
+            _, c2, M2, t2, P2 = B.pmf_get_state(f)
+            e1, em, _, _ = check_density(sc.model, c2, M2, P2, oracle.State(c_o, M_o, t_o, P_o),
+                                         fp32_update_tol(amp), what=f"track N={sc.model.N}", designed=True)
+            assert abs(ll - ll_o) <= 1e-4 * max(1.0, abs(ll_o)), (sc.model.N, ll, ll_o)
+            worst = [max(worst[0], e1), max(worst[1], em)]
+        note(f"  second cycle vs oracle (lockstep): worst L1 {worst[0]:.2e}, pointwise {worst[1]:.2e} of the peak")
+    finally:
+        for f in twins:
+            B.pmf_destroy(f)
+        B.pmf_server_destroy(srv)
