@@ -508,16 +508,59 @@ __device__ __noinline__ float trig_interp_1d(const float* Po, int n, double nu) 
     return (float)acc;
 }
 
-// cubic Lagrange weights through nodes -1, 0, 1, 2 at t in [0, 1]: each weight a
-// polynomial in t, sharing (t^2 - 1) / 6 (eleven operations).  At t = 0 they are
-// exactly (0, 1, 0, 0); at t = 1, (w0, 0, 1, 0) with |w0| one rounding of 1/3
+// cubic Lagrange weights through nodes -1, 0, 1, 2 at t in [0, 1] (nine
+// operations).  With s = 1 - t and p = t s, the weights factor as
+// w0 = -p (1 + s) / 6, w1 = (1 + p / 2) s, w2 = (1 + p / 2) t, w3 = -p (1 + t) / 6
+// (from (t + 1)(2 - t) = 2 + p).  At t = 0 they are exactly (0, 1, 0, 0) and at
+// t = 1 exactly (0, 0, 1, 0)
 __device__ inline void cubic_weights(float t, float* w) {
-    const float c = fmaf(t * t, 1.f / 6.f, -1.f / 6.f);             // (t^2 - 1) / 6
-    w[0] = t * fmaf(t, fmaf(t, -1.f / 6.f, 0.5f), -1.f / 3.f);      // -t (t - 1)(t - 2) / 6
-    w[1] = c * fmaf(t, 3.f, -6.f);                                   // (t + 1)(t - 1)(t - 2) / 2
-    w[2] = t * fmaf(t, fmaf(t, -0.5f, 0.5f), 1.f);                   // -(t + 1) t (t - 2) / 2
-    w[3] = t * c;                                                    // (t + 1) t (t - 1) / 6
+    const float s = 1.f - t;
+    const float p = t * s;
+    const float h = fmaf(p, 0.5f, 1.f);
+    w[0] = p * fmaf(s, -1.f / 6.f, -1.f / 6.f);
+    w[1] = h * s;
+    w[2] = h * t;
+    w[3] = p * fmaf(t, -1.f / 6.f, -1.f / 6.f);
 }
+
+typedef __attribute__((address_space(3))) const float lcfloat;
+
+// LDS bases of the four rows of a 16-tap stencil, for a posterior whose rows are
+// RSO floats apart: row a of the stencil at offset off starts at base + off + a RSO
+// (a = 0..3; base is the top-left tap of the stencil at offset 0).
+// Each row's four taps are read as two ds_read2 pairs.  Rows 0 and 1 share one base
+// when their offsets fit the 8-bit read2 offset field; the other bases are hidden
+// from the compiler by an empty asm, once per thread before the loop over points,
+// since it would otherwise rebuild a base for every pair of taps whose offset does
+// not fit (four or six address adds per point instead of one or three).
+template <int RSO>
+struct StencilRows {
+    static constexpr bool PAIRED = RSO + 3 <= 255;
+    lcfloat* b[4];
+    __device__ __forceinline__ explicit StencilRows(lcfloat* base) {
+        const unsigned a0 = (unsigned)(size_t)base;
+        unsigned a1 = a0 + 4u * RSO, a2 = a0 + 8u * RSO, a3 = a0 + 12u * RSO;
+        if constexpr (PAIRED) {
+            asm("" : "+v"(a2));
+        } else {
+            asm("" : "+v"(a1), "+v"(a2), "+v"(a3));
+        }
+        b[0] = base;
+        b[1] = (lcfloat*)(size_t)a1;
+        b[2] = (lcfloat*)(size_t)a2;
+        b[3] = (lcfloat*)(size_t)a3;
+    }
+    // sum_a w0[a] sum_b w1[b] P[a][b] over the stencil at offset off
+    __device__ __forceinline__ float apply(unsigned off, const float* w0, const float* w1) const {
+        float rs[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            lcfloat* row = PAIRED ? (a < 2 ? b[0] + off + a * RSO : b[2] + off + (a - 2) * RSO) : b[a] + off;
+            rs[a] = w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3];
+        }
+        return w0[0] * rs[0] + w0[1] * rs[1] + w0[2] * rs[2] + w0[3] * rs[3];
+    }
+};
 
 // ---------------------------------------------------------------- the fused kernel
 // Specialised at compile time per group type (N0 x N1 grid, G filters side by
@@ -1301,6 +1344,8 @@ __device__ __forceinline__ void process_group(const BItem* __restrict__ items, c
         gfloat* Pout = (gfloat*)F.pout;
         const float* Pog = Po + g * RPO;
         if constexpr (NX == 2) {
+            // the top-left tap (row -1, column -1) of node (0, 0)'s stencil (guard layouts only)
+            const StencilRows<RSO> rows((lcfloat*)(Pog - (GUARD ? RSO + 1 : 0)));
             // the cubic interpolant of the posterior at old index coordinates (nu0, nu1)
             auto interp_at = [&](double nu0, double nu1) -> float {
                 float val = 0.f;
@@ -1314,15 +1359,19 @@ __device__ __forceinline__ void process_group(const BItem* __restrict__ items, c
                     // taps outside the grid are zero: columns -1 and N1 read the zero
                     // pad floats, rows -1 and N0 the zero guard rows (without GUARD
                     // they get weight zero and read rows 0 and N0 - 1 instead)
-                    const float* q = Pog + __umul24(i0, RSO) + (i1 - 1);
-                    const bool top = !GUARD && i0 == 0, bot = !GUARD && i0 == N0 - 2;
-                    if (top) w0[0] = 0.f;
-                    if (bot) w0[3] = 0.f;
-                    const float* rows[4] = {top ? q : q - RSO, q, q + RSO, bot ? q + RSO : q + 2 * RSO};
+                    if constexpr (GUARD) {
+                        val = rows.apply(__umul24(i0, RSO) + (unsigned)i1, w0, w1);
+                    } else {
+                        const float* q = Pog + __umul24(i0, RSO) + (i1 - 1);
+                        const bool top = i0 == 0, bot = i0 == N0 - 2;
+                        if (top) w0[0] = 0.f;
+                        if (bot) w0[3] = 0.f;
+                        const float* rows[4] = {top ? q : q - RSO, q, q + RSO, bot ? q + RSO : q + 2 * RSO};
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const float* row = rows[a];
-                        val += w0[a] * (w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3]);
+                        for (int a = 0; a < 4; ++a) {
+                            const float* row = rows[a];
+                            val += w0[a] * (w1[0] * row[0] + w1[1] * row[1] + w1[2] * row[2] + w1[3] * row[3]);
+                        }
                     }
                 }
                 return val;

@@ -24,16 +24,19 @@ def _fma32(a, b, c):
 
 def _fp32_weights(t, pts):
     """Cubic Lagrange weights at t through the unit-spaced taps pts = i0 - 1 .. i0 + 2,
-    evaluated as the kernel does: s = float32(t - i0), each weight a polynomial in s
-    in float32 with fused multiply-adds."""
+    evaluated as the kernel does: s = float32(t - i0), then in float32 with fused
+    multiply-adds, from u = 1 - s and p = s u:
+    w0 = p (-(1 + u) / 6), w1 = (1 + p / 2) u, w2 = (1 + p / 2) s, w3 = p (-(1 + s) / 6)."""
     f = np.float32
     i0 = pts[..., 1]
     s = (t - i0).astype(f)
-    c = _fma32(s * s, f(1.0 / 6.0), f(-1.0 / 6.0))
-    w0 = s * _fma32(s, _fma32(s, f(-1.0 / 6.0), f(0.5)), f(-1.0 / 3.0))
-    w1 = c * _fma32(s, f(3.0), f(-6.0))
-    w2 = s * _fma32(s, _fma32(s, f(-0.5), f(0.5)), f(1.0))
-    w3 = s * c
+    u = (f(1.0) - s).astype(f)
+    p = (s * u).astype(f)
+    h = _fma32(p, f(0.5), f(1.0))
+    w0 = (p * _fma32(u, f(-1.0 / 6.0), f(-1.0 / 6.0))).astype(f)
+    w1 = (h * u).astype(f)
+    w2 = (h * s).astype(f)
+    w3 = (p * _fma32(s, f(-1.0 / 6.0), f(-1.0 / 6.0))).astype(f)
     return np.stack([w0, w1, w2, w3], axis=-1).astype(np.float64)
 
 

@@ -147,9 +147,14 @@ def test_autotune_and_cache(B, tmp_path):
             if len(offers[N]) > 1 and mix[N] > 0:
                 timed = [t for t in times if t is not None]
                 assert len(timed) == len(offers[N]), (N, times)
-                # the fastest, when at least 1 % below the default; else the default
-                best = min(offers[N], key=lambda u: times[u])
-                assert v == (best if times[best] < 0.99 * times[0] else 0), (N, times, v)
+                # the fastest, when at least 1 % below the default; else the default.  The
+                # cache keeps the times to 1e-6 ms, so two of them can tie there: the
+                # choice is then any of the tied fastest (rounding margin 1e-4 relative)
+                tmin = min(times[u] for u in offers[N])
+                if v == 0:
+                    assert tmin >= 0.99 * times[0] * (1 - 1e-4), (N, times, v)
+                else:
+                    assert times[v] == tmin and times[v] <= 0.99 * times[0] * (1 + 1e-4), (N, times, v)
             else:
                 assert v == 0 and all(t is None for t in times), (N, times, v)
         # read back from the cache by a new context: nothing timed, same schedules
