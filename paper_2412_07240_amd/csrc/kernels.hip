@@ -98,27 +98,49 @@ template <typename C, typename T> __device__ inline void dft5(C* a, int s) {
     a[3] = csub(m2, r2);
 }
 
-// R-point DFT by the definition (odd prime R without a factored butterfly: 7, 11,
-// 13, 17): the R roots of unity once, then X_k = sum_r a_r w^{(r k) mod R}
-template <typename C, typename T, int R> __device__ inline void dft_direct(C* a, int s) {
-    C w[R];
+// R-point DFT for an odd prime R without a factored butterfly (7, 11, 13, 17), by
+// pairing r with R - r: with t_r = a_r + a_{R-r}, d_r = a_r - a_{R-r} (r = 1..H,
+// H = (R - 1) / 2), cos / sin of 2 pi m / R written c_m, s_m,
+//   X_0 = a_0 + sum_r t_r,   X_k, X_{R-k} = A_k +- i s B_k  (k = 1..H),
+//   A_k = a_0 + sum_r c_{rk} t_r,   B_k = sum_r s_{rk} d_r   (rk taken mod R),
+// about a quarter of the real multiplications of the plain sum.  wr[m - 1] holds
+// e^{-2 pi i m / R}, m = 1..H (from the LDS root table).
+template <typename C, typename T, int R> __device__ inline void dft_odd(C* a, int s, const C* wr) {
+    constexpr int H = (R - 1) / 2;
+    T cm[H + 1], sm[H + 1];
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        T sn, cs;
-        sincospi_t((T)(2 * s * m) / (T)R, &sn, &cs);
-        w[m].x = cs;
-        w[m].y = sn;
+    for (int m = 1; m <= H; ++m) {
+        cm[m] = wr[m - 1].x;
+        sm[m] = -wr[m - 1].y;
     }
-    C out[R];
+    C t[H + 1], d[H + 1];
+    C x0 = a[0];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        C acc = a[0];
-#pragma unroll
-        for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(a[r], w[(r * k) % R]));
-        out[k] = acc;
+    for (int r = 1; r <= H; ++r) {
+        t[r] = cadd(a[r], a[R - r]);
+        d[r] = csub(a[r], a[R - r]);
+        x0 = cadd(x0, t[r]);
     }
 #pragma unroll
-    for (int k = 0; k < R; ++k) a[k] = out[k];
+    for (int k = 1; k <= H; ++k) {
+        C A = a[0], Bv;
+        Bv.x = (T)0;
+        Bv.y = (T)0;
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            const int m = (r * k) % R;
+            const T c = m <= H ? cm[m] : cm[R - m];
+            const T sn = m <= H ? sm[m] : -sm[R - m];
+            A.x += c * t[r].x;
+            A.y += c * t[r].y;
+            Bv.x += sn * d[r].x;
+            Bv.y += sn * d[r].y;
+        }
+        const C iB = cmul_si(Bv, s);
+        a[k] = cadd(A, iB);
+        a[R - k] = csub(A, iB);
+    }
+    a[0] = x0;
 }
 
 // One Stockham autosort pass over `nlines` lines held in LDS (pitch `pitch`).
@@ -128,7 +150,15 @@ template <typename T, int R>
 __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* out, const typename V2<T>::t* tw,
                               int n, int Ns, int nlines, int pitch, int sign) {
     using C = typename V2<T>::t;
+    constexpr bool ODD = R == 7 || R == 11 || R == 13 || R == 17;
     const int nb = n / R;
+    // the R-th roots of unity e^{-2 pi i m / R}, m = 1..(R-1)/2, of the odd-prime
+    // butterflies: entries m n / R of the table (dft_odd applies the sign)
+    C wr[ODD ? (R - 1) / 2 : 1];
+    if constexpr (ODD) {
+#pragma unroll
+        for (int m = 1; m <= (R - 1) / 2; ++m) wr[m - 1] = tw[m * nb];
+    }
     for (int w = threadIdx.x; w < nlines * nb; w += blockDim.x) {
         const int line = w / nb, j = w - line * nb;
         const C* src = in + line * pitch;
@@ -146,15 +176,12 @@ __device__ void stockham_pass(const typename V2<T>::t* in, typename V2<T>::t* ou
                 v[r] = cmul(v[r], w2);
             }
         }
-        if (R == 2) dft2<C, T>(v);
-        if (R == 3) dft3<C, T>(v, sign);
-        if (R == 4) dft4<C, T>(v, sign);
-        if (R == 8) dft8<C, T>(v, sign);
-        if (R == 5) dft5<C, T>(v, sign);
-        if (R == 7) dft_direct<C, T, 7>(v, sign);
-        if (R == 11) dft_direct<C, T, 11>(v, sign);
-        if (R == 13) dft_direct<C, T, 13>(v, sign);
-        if (R == 17) dft_direct<C, T, 17>(v, sign);
+        if constexpr (R == 2) dft2<C, T>(v);
+        if constexpr (R == 3) dft3<C, T>(v, sign);
+        if constexpr (R == 4) dft4<C, T>(v, sign);
+        if constexpr (R == 8) dft8<C, T>(v, sign);
+        if constexpr (R == 5) dft5<C, T>(v, sign);
+        if constexpr (ODD) dft_odd<C, T, R>(v, sign, wr);
         const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
@@ -176,7 +203,9 @@ __device__ inline void fft_roots(typename V2<T>::t* tw, int n) {
 // All passes of an n-point transform of ntl lines held in LDS (A, ping-ponging
 // with B; tw from fft_roots); returns the buffer holding the result.  Every
 // thread must call it.
-template <typename T>
+// ODD: the plan may hold radix 7, 11, 13 or 17 (their butterflies are compiled in
+// only then: they set the kernel's register count).
+template <typename T, bool ODD>
 __device__ typename V2<T>::t* fft_passes(typename V2<T>::t* A, typename V2<T>::t* B, const typename V2<T>::t* tw,
                                          int n, int ntl, int pitch, int sign, const FftPlan& plan) {
     using C = typename V2<T>::t;
@@ -189,10 +218,10 @@ __device__ typename V2<T>::t* fft_passes(typename V2<T>::t* A, typename V2<T>::t
         else if (R == 4) stockham_pass<T, 4>(in, out, tw, n, Ns, ntl, pitch, sign);
         else if (R == 3) stockham_pass<T, 3>(in, out, tw, n, Ns, ntl, pitch, sign);
         else if (R == 5) stockham_pass<T, 5>(in, out, tw, n, Ns, ntl, pitch, sign);
-        else if (R == 7) stockham_pass<T, 7>(in, out, tw, n, Ns, ntl, pitch, sign);
-        else if (R == 11) stockham_pass<T, 11>(in, out, tw, n, Ns, ntl, pitch, sign);
-        else if (R == 13) stockham_pass<T, 13>(in, out, tw, n, Ns, ntl, pitch, sign);
-        else if (R == 17) stockham_pass<T, 17>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (ODD && R == 7) stockham_pass<T, ODD ? 7 : 2>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (ODD && R == 11) stockham_pass<T, ODD ? 11 : 2>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (ODD && R == 13) stockham_pass<T, ODD ? 13 : 2>(in, out, tw, n, Ns, ntl, pitch, sign);
+        else if (ODD && R == 17) stockham_pass<T, ODD ? 17 : 2>(in, out, tw, n, Ns, ntl, pitch, sign);
         else stockham_pass<T, 2>(in, out, tw, n, Ns, ntl, pitch, sign);
         __syncthreads();
         C* tmp = in;
@@ -206,8 +235,8 @@ __device__ typename V2<T>::t* fft_passes(typename V2<T>::t* A, typename V2<T>::t
 // ------------------------------------------------------------------ FFT along one axis
 // Lines of the C-order array: line L = (o, i) with o < prod(N[<a]), i < s = prod(N[>a]);
 // element k of the line at o*n*s + i + k*s.  A block transforms TL consecutive lines.
-template <typename T>
-__global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, int s,
+template <typename T, bool ODD>
+__global__ void __launch_bounds__(256) k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, int s,
                            int nlines, int sign, FftPlan plan, int TL) {
     using C = typename V2<T>::t;
     extern __shared__ __align__(16) unsigned char smem_fft[];
@@ -241,7 +270,7 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
         A[t * pitch + k] = v;
     }
     __syncthreads();
-    const C* in = fft_passes<T>(A, B, tw, n, ntl, pitch, sign, plan);
+    const C* in = fft_passes<T, ODD>(A, B, tw, n, ntl, pitch, sign, plan);
     for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
         int t, k;
         size_t addr;
@@ -267,8 +296,8 @@ __global__ void k_fft_axis(const T* rsrc, typename V2<T>::t* X, T* rdst, int n, 
 // L = 2 (N + 1) (y_0 = y_{N+1} = 0, y_j = x_j, y_{L-j} = -x_j): DFT(y)_k = -2i X_k.
 // Lines as in k_fft_axis (element j of line (o, i) at o*N*s + i + j*s); each
 // block transforms TL lines in LDS with the same Stockham passes.
-template <typename T>
-__global__ void k_dst1_axis(const T* src, T* dst, int n, int s, int nlines, FftPlan plan, int TL) {
+template <typename T, bool ODD>
+__global__ void __launch_bounds__(256) k_dst1_axis(const T* src, T* dst, int n, int s, int nlines, FftPlan plan, int TL) {
     using C = typename V2<T>::t;
     extern __shared__ __align__(16) unsigned char smem_dst[];
     const int L = 2 * (n + 1), pitch = L + 1;
@@ -301,7 +330,7 @@ __global__ void k_dst1_axis(const T* src, T* dst, int n, int s, int nlines, FftP
         A[t * pitch + k] = c;
     }
     __syncthreads();
-    const C* Y = fft_passes<T>(A, B, tw, L, ntl, pitch, -1, plan);
+    const C* Y = fft_passes<T, ODD>(A, B, tw, L, ntl, pitch, -1, plan);
     for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
         int t, k;
         if (s == 1) {
@@ -1156,6 +1185,13 @@ static inline int lines_per_block(int len, int nlines, size_t csize) {
     return TL;
 }
 
+// whether an FFT plan holds a radix-7, 11, 13 or 17 pass
+static inline bool plan_has_odd(const FftPlan& p) {
+    for (int i = 0; i < p.np; ++i)
+        if (p.r[i] == 7 || p.r[i] == 11 || p.r[i] == 13 || p.r[i] == 17) return true;
+    return false;
+}
+
 // threads per block for `points` points in LDS: about two points per thread, whole
 // waves, 64..256
 static inline int block_threads(int points) {
@@ -1173,8 +1209,12 @@ hipError_t launch_fft_axis(const KModel& m, int a, const T* rsrc, void* X, T* rd
     const int TL = lines_per_block(n, nlines, sizeof(typename V2<T>::t));
     const size_t lds = (2 * (size_t)TL * (n + 1) + n) * sizeof(typename V2<T>::t);
     const FftPlan plan = make_plan(n);
-    hipLaunchKernelGGL(k_fft_axis<T>, dim3(cdiv(nlines, TL)), dim3(block_threads(TL * n)), lds, st, rsrc,
-                       static_cast<typename V2<T>::t*>(X), rdst, n, s, nlines, sign, plan, TL);
+    if (plan_has_odd(plan))
+        hipLaunchKernelGGL((k_fft_axis<T, true>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * n)), lds, st, rsrc,
+                           static_cast<typename V2<T>::t*>(X), rdst, n, s, nlines, sign, plan, TL);
+    else
+        hipLaunchKernelGGL((k_fft_axis<T, false>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * n)), lds, st, rsrc,
+                           static_cast<typename V2<T>::t*>(X), rdst, n, s, nlines, sign, plan, TL);
     return hipGetLastError();
 }
 
@@ -1383,8 +1423,12 @@ hipError_t launch_dst1_axis(const KModel& m, int a, const T* src, T* dst, hipStr
     const int TL = lines_per_block(L, nlines, sizeof(typename V2<T>::t));
     const size_t lds = (2 * (size_t)TL * (L + 1) + L) * sizeof(typename V2<T>::t);
     const FftPlan plan = make_plan(L);
-    hipLaunchKernelGGL(k_dst1_axis<T>, dim3(cdiv(nlines, TL)), dim3(block_threads(TL * L)), lds, st, src, dst, n, s,
-                       nlines, plan, TL);
+    if (plan_has_odd(plan))
+        hipLaunchKernelGGL((k_dst1_axis<T, true>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * L)), lds, st, src,
+                           dst, n, s, nlines, plan, TL);
+    else
+        hipLaunchKernelGGL((k_dst1_axis<T, false>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * L)), lds, st, src,
+                           dst, n, s, nlines, plan, TL);
     return hipGetLastError();
 }
 
