@@ -954,8 +954,8 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
         for (int a = 0; a < NX; ++a) r[a] = x[a] - go.c[a];
         mat_vec(nu, go.Mi, r, NX);
         bool inside = true;
-        int tapidx[NX][4];
-        double tw[NX][4];
+        int first[NX];       // array index of tap 0 along each axis (taps first .. first + 3)
+        double tw[NX][4];    // weights, zero for taps outside the array
 #pragma unroll
         for (int a = 0; a < NX; ++a) {
             const int n = m.N[a];
@@ -969,13 +969,7 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
                 tw[a][1] = tp * tm * tm2 / 2.0;
                 tw[a][2] = -tp * t * tm2 / 2.0;
                 tw[a][3] = tp * t * tm / 6.0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int ii = i0 - 1 + k;
-                    const bool ok = ii >= 0 && ii <= n - 1;
-                    tapidx[a][k] = ok ? ii : i0;
-                    if (!ok) tw[a][k] = 0.0;
-                }
+                first[a] = i0 - 1;
             } else {
                 const double q = nu[a];
                 inside = inside && q >= -1.0 && q <= 1.0;
@@ -987,60 +981,77 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
                 ks = ks < 0 ? 0 : (ks > nn - 3 ? nn - 3 : ks);
                 const double* v = tab + a * TAB_STRIDE + TAB_V;
                 lagrange4(qc, v + ks, tw[a]);
+                // node kk of the n + 2 Gauss-Lobatto nodes is array entry kk - 1
+                // (kk = 0 and n + 1 are the zero end nodes)
+                first[a] = ks - 1;
+            }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int kk = ks + k;
-                    const bool ok = kk >= 1 && kk <= n;
-                    tapidx[a][k] = ok ? kk - 1 : 0;
-                    if (!ok) tw[a][k] = 0.0;
-                }
+            for (int k = 0; k < 4; ++k) {
+                const int ii = first[a] + k;
+                if (ii < 0 || ii > n - 1) tw[a][k] = 0.0;
             }
         }
         double val = 0.0;
         if (inside) {
             if constexpr (NX == 1) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) val += tw[0][k] * (double)in[tapidx[0][k]];
-            } else if constexpr (NX == 2) {
-#pragma unroll
-                for (int k0 = 0; k0 < 4; ++k0) {
-                    const T* row = in + (size_t)tapidx[0][k0] * m.N[1];
-                    double rs = 0.0;
-#pragma unroll
-                    for (int k1 = 0; k1 < 4; ++k1) rs += tw[1][k1] * (double)row[tapidx[1][k1]];
-                    val += tw[0][k0] * rs;
-                }
-            } else if constexpr (NX == 3) {
-#pragma unroll
-                for (int k0 = 0; k0 < 4; ++k0) {
-                    double ps = 0.0;
-#pragma unroll
-                    for (int k1 = 0; k1 < 4; ++k1) {
-                        const T* row = in + ((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2];
-                        double rs = 0.0;
-#pragma unroll
-                        for (int k2 = 0; k2 < 4; ++k2) rs += tw[2][k2] * (double)row[tapidx[2][k2]];
-                        ps += tw[1][k1] * rs;
-                    }
-                    val += tw[0][k0] * ps;
+                for (int k = 0; k < 4; ++k) {
+                    const int ii = min(max(first[0] + k, 0), m.N[0] - 1);
+                    val += tw[0][k] * (double)in[ii];
                 }
             } else {
-                for (int k0 = 0; k0 < 4; ++k0) {
-                    double s1 = 0.0;
-                    for (int k1 = 0; k1 < 4; ++k1) {
-                        double s2 = 0.0;
+                // Along the last (contiguous) axis the four taps are read as four
+                // consecutive entries from b = clamp(first, 0, n - 4), the weights
+                // moved to match (taps outside the array have weight zero, and the
+                // entries that replace them get weight zero); along the other axes
+                // each tap is a 32-bit element offset (index times stride).
+                constexpr int L = NX - 1;
+                const int nl = m.N[L];
+                const int b = min(max(first[L], 0), nl - 4), sh3 = first[L] - b;   // -1 .. 2
+                double wl[4];
 #pragma unroll
-                        for (int k2 = 0; k2 < 4; ++k2) {
-                            const T* row =
-                                in + (((size_t)tapidx[0][k0] * m.N[1] + tapidx[1][k1]) * m.N[2] + tapidx[2][k2]) * m.N[3];
-                            double s3 = 0.0;
+                for (int p = 0; p < 4; ++p) {
+                    const int k = p - sh3;
+                    wl[p] = (k == 0) ? tw[L][0] : (k == 1) ? tw[L][1] : (k == 2) ? tw[L][2] : (k == 3) ? tw[L][3] : 0.0;
+                }
+                int off[NX - 1][4];
+                int stride = nl;
 #pragma unroll
-                            for (int k3 = 0; k3 < 4; ++k3) s3 += tw[3][k3] * (double)row[tapidx[3][k3]];
-                            s2 += tw[2][k2] * s3;
-                        }
-                        s1 += tw[1][k1] * s2;
+                for (int a = NX - 2; a >= 0; --a) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) off[a][k] = min(max(first[a] + k, 0), m.N[a] - 1) * stride;
+                    stride *= m.N[a];
+                }
+                const T* base = in + b;
+                auto row4 = [&](int o) -> double {
+                    const T* r = base + o;
+                    return wl[0] * (double)r[0] + wl[1] * (double)r[1] + wl[2] * (double)r[2] + wl[3] * (double)r[3];
+                };
+                if constexpr (NX == 2) {
+#pragma unroll
+                    for (int k0 = 0; k0 < 4; ++k0) val += tw[0][k0] * row4(off[0][k0]);
+                } else if constexpr (NX == 3) {
+#pragma unroll
+                    for (int k0 = 0; k0 < 4; ++k0) {
+                        double ps = 0.0;
+#pragma unroll
+                        for (int k1 = 0; k1 < 4; ++k1) ps += tw[1][k1] * row4(off[0][k0] + off[1][k1]);
+                        val += tw[0][k0] * ps;
                     }
-                    val += tw[0][k0] * s1;
+                } else {
+#pragma unroll
+                    for (int k0 = 0; k0 < 4; ++k0) {
+                        double s1 = 0.0;
+#pragma unroll
+                        for (int k1 = 0; k1 < 4; ++k1) {
+                            const int o01 = off[0][k0] + off[1][k1];
+                            double s2 = 0.0;
+#pragma unroll
+                            for (int k2 = 0; k2 < 4; ++k2) s2 += tw[2][k2] * row4(o01 + off[2][k2]);
+                            s1 += tw[1][k1] * s2;
+                        }
+                        val += tw[0][k0] * s1;
+                    }
                 }
             }
         }
