@@ -674,7 +674,8 @@ __device__ double block_max(double v, double* sh) {
 
 // ------------------------------------------------------------------ likelihood + sums
 // mode 0: sums of the density only; mode 1: P_out = P * exp(loglik - s_b) and its sums.
-// Partial b: {s_b, S0, S1[4], S2[10] (packed as pk), Sboundary}, block-relative.
+// Partial b: {s_b, S0, S1[4], S2[10] (packed as pk), Sboundary}, block-relative,
+// stored by column: entry q at part[q nb + b].
 template <typename T, int NX>
 __global__ void __launch_bounds__(RED_THREADS)
 k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T* Pout,
@@ -715,62 +716,125 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
     }
     block_sum<NACC>(acc, sh);
     if (threadIdx.x == 0) {
-        double* p = part + (size_t)b * NPART;
-        p[0] = sb;
-        for (int q = 0; q < NACC; ++q) p[1 + q] = acc[q];
+        // partials stored by column: entry q of block b at q nb + b (nb = gridDim.x)
+        part[b] = sb;
+        for (int q = 0; q < NACC; ++q) part[(size_t)(1 + q) * gridDim.x + b] = acc[q];
     }
 }
 
 // Combine the per-block partials (all RED_THREADS threads of one block, fixed
-// tree order): S0..Sb relative to the global shift, in every thread.
+// tree order): S0..Sb relative to the global shift, in every thread.  Partials
+// are stored by column (entry q of block b at q nb + b), so consecutive threads
+// read consecutive doubles.
 __device__ void combine_partials(const double* part, int nb, double* s_out, double* S, double* sh) {
     double mx = -INFINITY;
-    for (int b = threadIdx.x; b < nb; b += RED_THREADS) mx = fmax(mx, part[b * NPART]);
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) mx = fmax(mx, part[b]);
     const double s = block_max(mx, sh);
     double acc[NACC];
     for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
     for (int b = threadIdx.x; b < nb; b += RED_THREADS) {
-        const double f = (s == -INFINITY) ? 0.0 : exp(part[b * NPART] - s);
-        for (int q = 0; q < NACC; ++q) acc[q] += f * part[b * NPART + 1 + q];
+        const double f = (s == -INFINITY) ? 0.0 : exp(part[b] - s);
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) acc[q] += f * part[(size_t)(1 + q) * nb + b];
     }
     block_sum<NACC>(acc, sh);
     for (int q = 0; q < NACC; ++q) S[q] = acc[q];
     *s_out = s;
 }
 
-// mean and covariance from sums in computational coordinates u (x = c + M u)
-__device__ void moments_from_sums(const Grid& g, int nx, const double* S, double* mean, double* cov) {
+// mean and covariance from sums in computational coordinates u (x = c + M u);
+// NX at compile time, so the small matrices live in registers
+template <int NX>
+__device__ __forceinline__ void moments_from_sums(const Grid& g, const double* S, double* mean, double* cov) {
     const double S0 = S[0];
-    double ub[MS] = {S[1] / S0, S[2] / S0, S[3] / S0, S[4] / S0};
-    double Cu[MSQ];
-    mat_zero(Cu);
-    for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < nx; ++b) Cu[a * MS + b] = S[5 + pk(a, b)] / S0 - ub[a] * ub[b];
-    double mu[MS];
-    mat_vec(mu, g.M, ub, nx);
-    for (int a = 0; a < nx; ++a) mean[a] = g.c[a] + mu[a];
-    double t1[MSQ], C[MSQ];
-    mat_mul(t1, g.M, Cu, nx);
-    mat_mul_bt(C, t1, g.M, nx);
-    for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < nx; ++b) cov[a * MS + b] = 0.5 * (C[a * MS + b] + C[b * MS + a]);
+    double ub[NX], Cu[NX][NX];
+#pragma unroll
+    for (int a = 0; a < NX; ++a) ub[a] = S[1 + a] / S0;
+#pragma unroll
+    for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < NX; ++b) Cu[a][b] = S[5 + pk(a, b)] / S0 - ub[a] * ub[b];
+#pragma unroll
+    for (int a = 0; a < NX; ++a) {
+        double mu = 0.0;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) mu += g.M[a * MS + k] * ub[k];
+        mean[a] = g.c[a] + mu;
+    }
+    // C = M Cu M^T
+    double t1[NX][NX], C[NX][NX];
+#pragma unroll
+    for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < NX; ++b) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < NX; ++k) t += g.M[a * MS + k] * Cu[k][b];
+            t1[a][b] = t;
+        }
+#pragma unroll
+    for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < NX; ++b) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < NX; ++k) t += t1[a][k] * g.M[b * MS + k];
+            C[a][b] = t;
+        }
+#pragma unroll
+    for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < NX; ++b) cov[a * MS + b] = 0.5 * (C[a][b] + C[b][a]);
 }
 
-__device__ bool design_grid_dev(const KModel& m, const double* mean, const double* cov, Grid& gn) {
+// Mi = M^-1 and vol = |det M| as grid_finish computes them (the same cofactor
+// arithmetic), with the 4 x 4 minors' indices fixed at compile time
+template <int NX>
+__device__ __forceinline__ void grid_finish_c(Grid& g) {
+    if constexpr (NX < 4) {
+        grid_finish(g, NX);
+    } else {
+        const double* a = g.M;
+        double* r = g.Mi;
+        const double dt = mat_det(a, 4);
+        mat_zero(r);
+        if (dt != 0.0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int rr[3], cc[3], p = 0, q = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (k != i) rr[p++] = k;
+                        if (k != j) cc[q++] = k;
+                    }
+                    const double mn = det3_at(a, rr[0], rr[1], rr[2], cc[0], cc[1], cc[2]);
+                    r[j * MS + i] = (((i + j) & 1) ? -mn : mn) / dt;
+                }
+        }
+        g.vol = fabs(dt);
+    }
+}
+
+template <int NX>
+__device__ __forceinline__ bool design_grid_dev(const KModel& m, const double* mean, const double* cov, Grid& gn) {
     mat_zero(gn.M);
-    for (int a = 0; a < m.nx; ++a) {
+#pragma unroll
+    for (int a = 0; a < NX; ++a) {
         const double v = cov[a * MS + a] + m.Wnom[a * MS + a];
         if (!(v > 0.0) || !isfinite(v)) return false;
         const double h = m.span * sqrt(v);
         gn.M[a * MS + a] = (m.grid == PMF_GRID_FOURIER) ? 2.0 * h / m.N[a] : h;
         gn.c[a] = mean[a];
     }
-    grid_finish(gn, m.nx);
+    grid_finish_c<NX>(gn);
     return true;
 }
 
 // After k_like_pass(mode 1): normaliser, log-likelihood, moments, block factors,
 // new grid.  On failure: ok = 0 and the DEGENERATE bit.  One block.
+template <int NX>
 __global__ void __launch_bounds__(RED_THREADS)
 k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
     __shared__ double sh[NACC * RED_THREADS];
@@ -779,7 +843,7 @@ k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac
     const double mass = d->g.vol * S[0];
     const bool good = isfinite(s) && isfinite(mass) && mass > 0.0;
     if (good)
-        for (int b = threadIdx.x; b < nb; b += RED_THREADS) bfac[b] = exp(part[b * NPART] - s) / mass;
+        for (int b = threadIdx.x; b < nb; b += RED_THREADS) bfac[b] = exp(part[b] - s) / mass;
     if (threadIdx.x != 0) return;
     d->ok = 1;
     if (!good) {
@@ -788,15 +852,17 @@ k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac
         d->s = s;
         d->mass = mass;
         d->loglik = s + log(mass);
-        moments_from_sums(d->g, m.nx, S, d->mean, d->cov);
+        moments_from_sums<NX>(d->g, S, d->mean, d->cov);
         d->bfrac = S[NACC - 1] / S[0];
         if (d->bfrac > BOUNDARY_TOL) d->status |= ST_BOUNDARY;
-        if (!design_grid_dev(m, d->mean, d->cov, d->gn)) d->ok = 0;
+        if (!design_grid_dev<NX>(m, d->mean, d->cov, d->gn)) d->ok = 0;
         // separable spectral interpolation when the old grid is axis aligned
         // (the new one always is); otherwise cubic Lagrange
         bool aligned = true;
-        for (int a = 0; a < m.nx; ++a)
-            for (int b = 0; b < m.nx; ++b)
+#pragma unroll
+        for (int a = 0; a < NX; ++a)
+#pragma unroll
+            for (int b = 0; b < NX; ++b)
                 if (a != b && d->g.M[a * MS + b] != 0.0) aligned = false;
         d->sep = (m.interp == PMF_INTERP_AUTO && aligned) ? 1 : 0;
     }
@@ -807,6 +873,7 @@ k_update_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac
 }
 
 // After k_like_pass(mode 0): mass, moments and 1/mass (in bfac[0..nb)).  One block.
+template <int NX>
 __global__ void __launch_bounds__(RED_THREADS)
 k_sums_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) {
     __shared__ double sh[NACC * RED_THREADS];
@@ -816,7 +883,7 @@ k_sums_finalize(KModel m, DevDesc* d, const double* part, int nb, double* bfac) 
     for (int b = threadIdx.x; b < nb; b += RED_THREADS) bfac[b] = 1.0 / mass;
     if (threadIdx.x != 0) return;
     d->mass = mass;
-    moments_from_sums(d->g, m.nx, S, d->mean, d->cov);
+    moments_from_sums<NX>(d->g, S, d->mean, d->cov);
 }
 
 template <typename T>
@@ -913,9 +980,8 @@ k_interp_axis(KModel m, const DevDesc* d, const double* tab, const double* Wall,
     if (want_sums) {
         block_sum<NACC>(acc, sh);
         if (threadIdx.x == 0) {
-            double* p = part + (size_t)blockIdx.x * NPART;
-            p[0] = 0.0;
-            for (int q = 0; q < NACC; ++q) p[1 + q] = acc[q];
+            part[blockIdx.x] = 0.0;
+            for (int q = 0; q < NACC; ++q) part[(size_t)(1 + q) * gridDim.x + blockIdx.x] = acc[q];
         }
     }
 }
@@ -1062,9 +1128,8 @@ k_interp_lagrange(KModel m, const DevDesc* d, const double* tab, const T* in, T*
     }
     block_sum<NACC>(acc, sh);
     if (threadIdx.x == 0) {
-        double* p = part + (size_t)blockIdx.x * NPART;
-        p[0] = 0.0;
-        for (int q = 0; q < NACC; ++q) p[1 + q] = acc[q];
+        part[blockIdx.x] = 0.0;
+        for (int q = 0; q < NACC; ++q) part[(size_t)(1 + q) * gridDim.x + blockIdx.x] = acc[q];
     }
 }
 
@@ -1275,13 +1340,23 @@ hipError_t launch_like(const KModel& m, const DevDesc* d, const double* tab, con
 
 hipError_t launch_update_finalize(const KModel& m, DevDesc* d, const double* part, int nb, double* bfac,
                                   hipStream_t st) {
-    hipLaunchKernelGGL(k_update_finalize, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac);
+    switch (m.nx) {
+        case 1: hipLaunchKernelGGL(k_update_finalize<1>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+        case 2: hipLaunchKernelGGL(k_update_finalize<2>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+        case 3: hipLaunchKernelGGL(k_update_finalize<3>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+        default: hipLaunchKernelGGL(k_update_finalize<4>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_sums_finalize(const KModel& m, DevDesc* d, const double* part, int nb, double* bfac,
                                 hipStream_t st) {
-    hipLaunchKernelGGL(k_sums_finalize, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac);
+    switch (m.nx) {
+        case 1: hipLaunchKernelGGL(k_sums_finalize<1>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+        case 2: hipLaunchKernelGGL(k_sums_finalize<2>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+        case 3: hipLaunchKernelGGL(k_sums_finalize<3>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+        default: hipLaunchKernelGGL(k_sums_finalize<4>, dim3(1), dim3(RED_THREADS), 0, st, m, d, part, nb, bfac); break;
+    }
     return hipGetLastError();
 }
 
