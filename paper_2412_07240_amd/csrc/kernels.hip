@@ -673,6 +673,7 @@ __device__ double block_max(double v, double* sh) {
 }
 
 // ------------------------------------------------------------------ likelihood + sums
+constexpr int LIKE_CACHE = 1024;   // log-likelihoods kept per block between the two passes
 // mode 0: sums of the density only; mode 1: P_out = P * exp(loglik - s_b) and its sums.
 // Partial b: {s_b, S0, S1[4], S2[10] (packed as pk), Sboundary}, block-relative,
 // stored by column: entry q at part[q nb + b].
@@ -681,9 +682,13 @@ __global__ void __launch_bounds__(RED_THREADS)
 k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T* Pout,
             double* part, int chunk, int mode) {
     __shared__ double sh[NACC * RED_THREADS];
+    // the block's log-likelihoods from the max pass, reused by the multiply pass
+    // (each thread reads back its own entries; blocks of more points recompute)
+    __shared__ double Lsh[LIKE_CACHE];
     const int b = blockIdx.x;
     const int lo = b * chunk;
     const int hi = min(m.ntot, lo + chunk);
+    const bool cached = chunk <= LIKE_CACHE;
     const Grid& g = d->g;
     double sb = 0.0;
     if (mode == 1) {
@@ -693,7 +698,9 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
             int idx[MS];
             node_coords_n<NX>(m, tab, j, u, idx);
             to_phys(g, NX, u, x);
-            mx = fmax(mx, loglik_at(m, x, z.v));
+            const double L = loglik_at(m, x, z.v);
+            if (cached) Lsh[j - lo] = L;
+            mx = fmax(mx, L);
         }
         sb = block_max(mx, sh);
     }
@@ -705,9 +712,14 @@ k_like_pass(KModel m, const DevDesc* d, const double* tab, ZArg z, const T* P, T
         node_coords_n<NX>(m, tab, j, u, idx);
         T v = P[j];
         if (mode == 1) {
-            double x[MS];
-            to_phys(g, NX, u, x);
-            const double L = loglik_at(m, x, z.v);
+            double L;
+            if (cached) {
+                L = Lsh[j - lo];
+            } else {
+                double x[MS];
+                to_phys(g, NX, u, x);
+                L = loglik_at(m, x, z.v);
+            }
             v = v * exp_t((T)(L - sb));
             Pout[j] = v;
         }
