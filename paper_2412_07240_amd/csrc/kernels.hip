@@ -232,6 +232,37 @@ __device__ typename V2<T>::t* fft_passes(typename V2<T>::t* A, typename V2<T>::t
     return in;
 }
 
+// Visits the elements (t, k), t < ntl lines, k < n entries, of a block's lines with
+// consecutive threads on consecutive addresses: consecutive lines t for a strided
+// axis (s > 1), consecutive entries k for the contiguous one.  The counters advance
+// by the block size without a division per element.
+template <typename F>
+__device__ inline void for_line_elems(int ntl, int n, bool strided, F&& f) {
+    const int M = strided ? ntl : n, NMAJ = strided ? n : ntl;
+    const int bd = blockDim.x;
+    int mi = threadIdx.x % M, ma = threadIdx.x / M;
+    const int dmi = bd % M, dma = bd / M;
+    while (ma < NMAJ) {
+        if (strided) f(mi, ma);
+        else f(ma, mi);
+        mi += dmi;
+        ma += dma;
+        if (mi >= M) {
+            mi -= M;
+            ++ma;
+        }
+    }
+}
+
+// Element offset of entry 0 of line L (element k at + k s): (L / s) n s + L mod s,
+// for the block's lines, into lb[0..ntl) (one division pair per line)
+__device__ inline void line_bases(int* lb, int L0, int ntl, int n, int s) {
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) {
+        const int L = L0 + t;
+        lb[t] = (L / s) * n * s + (L % s);
+    }
+}
+
 // ------------------------------------------------------------------ FFT along one axis
 // Lines of the C-order array: line L = (o, i) with o < prod(N[<a]), i < s = prod(N[>a]);
 // element k of the line at o*n*s + i + k*s.  A block transforms TL consecutive lines.
@@ -244,22 +275,14 @@ __global__ void __launch_bounds__(256) k_fft_axis(const T* rsrc, typename V2<T>:
     C* A = reinterpret_cast<C*>(smem_fft);
     C* B = A + TL * pitch;
     C* tw = B + TL * pitch;
+    int* lb = reinterpret_cast<int*>(tw + n);
     const int L0 = blockIdx.x * TL;
     const int ntl = min(TL, nlines - L0);
     fft_roots<T>(tw, n);
-    for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
-        int t, k;
-        size_t addr;
-        if (s == 1) {
-            t = e / n;
-            k = e - t * n;
-            addr = (size_t)(L0 + t) * n + k;
-        } else {
-            t = e % ntl;
-            k = e / ntl;
-            const int L = L0 + t;
-            addr = (size_t)(L / s) * n * s + (L % s) + (size_t)k * s;
-        }
+    line_bases(lb, L0, ntl, n, s);
+    __syncthreads();
+    for_line_elems(ntl, n, s > 1, [&](int t, int k) {
+        const int addr = lb[t] + k * s;
         C v;
         if (rsrc) {
             v.x = rsrc[addr];
@@ -268,26 +291,15 @@ __global__ void __launch_bounds__(256) k_fft_axis(const T* rsrc, typename V2<T>:
             v = X[addr];
         }
         A[t * pitch + k] = v;
-    }
+    });
     __syncthreads();
     const C* in = fft_passes<T, ODD>(A, B, tw, n, ntl, pitch, sign, plan);
-    for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
-        int t, k;
-        size_t addr;
-        if (s == 1) {
-            t = e / n;
-            k = e - t * n;
-            addr = (size_t)(L0 + t) * n + k;
-        } else {
-            t = e % ntl;
-            k = e / ntl;
-            const int L = L0 + t;
-            addr = (size_t)(L / s) * n * s + (L % s) + (size_t)k * s;
-        }
+    for_line_elems(ntl, n, s > 1, [&](int t, int k) {
+        const int addr = lb[t] + k * s;
         const C v = in[t * pitch + k];
         if (rdst) rdst[addr] = v.x;
         else X[addr] = v;
-    }
+    });
 }
 
 // ------------------------------------------------------------------ DST-I along one axis
@@ -304,45 +316,30 @@ __global__ void __launch_bounds__(256) k_dst1_axis(const T* src, T* dst, int n, 
     C* A = reinterpret_cast<C*>(smem_dst);
     C* B = A + TL * pitch;
     C* tw = B + TL * pitch;
+    int* lb = reinterpret_cast<int*>(tw + L);
     const int L0 = blockIdx.x * TL;
     const int ntl = min(TL, nlines - L0);
     fft_roots<T>(tw, L);
-    for (int e = threadIdx.x; e < ntl * L; e += blockDim.x) {
-        int t, k;
-        if (s == 1) {
-            t = e / L;
-            k = e - t * L;
-        } else {
-            t = e % ntl;
-            k = e / ntl;
-        }
+    line_bases(lb, L0, ntl, n, s);
+    __syncthreads();
+    for_line_elems(ntl, L, s > 1, [&](int t, int k) {
         // position k of the extension: x_k for 1 <= k <= n, -x_{L-k} for n+2 <= k < L, else 0
         const int j = (k >= 1 && k <= n) ? k : (k >= n + 2 ? L - k : 0);
         T v = (T)0;
         if (j) {
-            const int Ln = L0 + t;
-            const T x = src[(size_t)(Ln / s) * n * s + (Ln % s) + (size_t)(j - 1) * s];
+            const T x = src[lb[t] + (j - 1) * s];
             v = (k <= n) ? x : -x;
         }
         C c;
         c.x = v;
         c.y = (T)0;
         A[t * pitch + k] = c;
-    }
+    });
     __syncthreads();
     const C* Y = fft_passes<T, ODD>(A, B, tw, L, ntl, pitch, -1, plan);
-    for (int e = threadIdx.x; e < ntl * n; e += blockDim.x) {
-        int t, k;
-        if (s == 1) {
-            t = e / n;
-            k = e - t * n;
-        } else {
-            t = e % ntl;
-            k = e / ntl;
-        }
-        const int Ln = L0 + t;
-        dst[(size_t)(Ln / s) * n * s + (Ln % s) + (size_t)k * s] = (T)(-0.5) * Y[t * pitch + k + 1].y;
-    }
+    for_line_elems(ntl, n, s > 1, [&](int t, int k) {
+        dst[lb[t] + k * s] = (T)(-0.5) * Y[t * pitch + k + 1].y;
+    });
 }
 
 // ------------------------------------------------------------------ predict planning
@@ -1265,7 +1262,8 @@ static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 // blocks, each running all its lines' passes in turn), at most about 2048 points
 // per block, and both line buffers plus the roots of unity within 64 KiB.
 static inline int lines_per_block(int len, int nlines, size_t csize) {
-    const int cap = (int)((65536 / csize - len) / (2 * (size_t)(len + 1)));
+    // A and B (TL lines of len + 1 entries each), the len roots and TL line offsets
+    const int cap = (int)((65536 - (size_t)len * csize) / (2 * (size_t)(len + 1) * csize + sizeof(int)));
     int TL = std::min(2048 / len, std::max(1, nlines / 512));
     if (TL > cap) TL = cap;
     if (TL < 1) TL = 1;
@@ -1295,7 +1293,7 @@ hipError_t launch_fft_axis(const KModel& m, int a, const T* rsrc, void* X, T* rd
     for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
     const int nlines = m.ntot / n;
     const int TL = lines_per_block(n, nlines, sizeof(typename V2<T>::t));
-    const size_t lds = (2 * (size_t)TL * (n + 1) + n) * sizeof(typename V2<T>::t);
+    const size_t lds = (2 * (size_t)TL * (n + 1) + n) * sizeof(typename V2<T>::t) + (size_t)TL * sizeof(int);
     const FftPlan plan = make_plan(n);
     if (plan_has_odd(plan))
         hipLaunchKernelGGL((k_fft_axis<T, true>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * n)), lds, st, rsrc,
@@ -1519,7 +1517,7 @@ hipError_t launch_dst1_axis(const KModel& m, int a, const T* src, T* dst, hipStr
     for (int b = a + 1; b < m.nx; ++b) s *= m.N[b];
     const int nlines = m.ntot / n;
     const int TL = lines_per_block(L, nlines, sizeof(typename V2<T>::t));
-    const size_t lds = (2 * (size_t)TL * (L + 1) + L) * sizeof(typename V2<T>::t);
+    const size_t lds = (2 * (size_t)TL * (L + 1) + L) * sizeof(typename V2<T>::t) + (size_t)TL * sizeof(int);
     const FftPlan plan = make_plan(L);
     if (plan_has_odd(plan))
         hipLaunchKernelGGL((k_dst1_axis<T, true>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * L)), lds, st, src,
