@@ -502,22 +502,77 @@ __device__ inline void mode_kappa(int s, int n, T* k1, T* k2) {
     *k1 = (2 * s == n) ? (T)0 : kap;
 }
 
-template <typename T>
-__global__ void k_gain(KModel m, const DevDesc* d, const double* coef, typename V2<T>::t* X) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m.ntot) return;
-    T k1[MS] = {0, 0, 0, 0}, k2[MS] = {0, 0, 0, 0};
-    int rem = e;
-    for (int a = m.nx - 1; a >= 0; --a) {
-        const int s = rem % m.N[a];
-        rem /= m.N[a];
-        mode_kappa<T>(s, m.N[a], &k1[a], &k2[a]);
+// Axis 0 of a Fourier predict in one launch: forward transform of each axis-0 line,
+// the per-mode gain, inverse transform.  Axis 0 is the last axis of the
+// forward transform and the first of the inverse one, so the three steps need no
+// other line in between: one pass over the spectrum instead of three.  With nx = 1
+// it is the whole predict (real density in, real density out, in place).
+// LDS: A, B (TL lines of n + 1), the n roots, per line the wavenumbers k1, k2 of
+// axes 1..nx-1, the TL line offsets.
+template <typename T, bool ODD>
+__global__ void __launch_bounds__(256)
+k_fft_gain_axis0(KModel m, const DevDesc* d, const double* coef, const T* rsrc, typename V2<T>::t* X, T* rdst,
+                 FftPlan plan, int TL) {
+    using C = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char smem_fg[];
+    const int n = m.N[0], s = m.ntot / n, nlines = s;
+    const int pitch = n + 1;
+    C* A = reinterpret_cast<C*>(smem_fg);
+    C* B = A + TL * pitch;
+    C* tw = B + TL * pitch;
+    T* lk = reinterpret_cast<T*>(tw + n);   // line t: k1 of axes 1..3 at 6 t, k2 at 6 t + 3
+    int* lb = reinterpret_cast<int*>(lk + 6 * TL);
+    const int L0 = blockIdx.x * TL;
+    const int ntl = min(TL, nlines - L0);
+    fft_roots<T>(tw, n);
+    line_bases(lb, L0, ntl, n, s);
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) {
+        int rem = L0 + t;
+        for (int a = m.nx - 1; a >= 1; --a) {
+            const int sa = rem % m.N[a];
+            rem /= m.N[a];
+            mode_kappa<T>(sa, m.N[a], &lk[6 * t + a - 1], &lk[6 * t + 3 + a - 1]);
+        }
     }
-    const T g = mode_gain<T>(m.integ, d->l, (T)d->h, coef, k1, k2) * (T)(d->etr / (double)m.ntot);
-    typename V2<T>::t v = X[e];
-    v.x *= g;
-    v.y *= g;
-    X[e] = v;
+    __syncthreads();
+    for_line_elems(ntl, n, s > 1, [&](int t, int k) {
+        const int addr = lb[t] + k * s;
+        C v;
+        if (rsrc) {
+            v.x = rsrc[addr];
+            v.y = (T)0;
+        } else {
+            v = X[addr];
+        }
+        A[t * pitch + k] = v;
+    });
+    __syncthreads();
+    C* F = fft_passes<T, ODD>(A, B, tw, n, ntl, pitch, -1, plan);
+    C* G = (F == A) ? B : A;
+    const T scale = (T)(d->etr / (double)m.ntot);
+    const int l = d->l;
+    const T h = (T)d->h;
+    for_line_elems(ntl, n, false, [&](int t, int k) {
+        T k1[MS] = {0, 0, 0, 0}, k2[MS] = {0, 0, 0, 0};
+        mode_kappa<T>(k, n, &k1[0], &k2[0]);
+        for (int a = 1; a < m.nx; ++a) {
+            k1[a] = lk[6 * t + a - 1];
+            k2[a] = lk[6 * t + 3 + a - 1];
+        }
+        const T g = mode_gain<T>(m.integ, l, h, coef, k1, k2) * scale;
+        C v = F[t * pitch + k];
+        v.x *= g;
+        v.y *= g;
+        F[t * pitch + k] = v;
+    });
+    __syncthreads();
+    const C* R = fft_passes<T, ODD>(F, G, tw, n, ntl, pitch, +1, plan);
+    for_line_elems(ntl, n, s > 1, [&](int t, int k) {
+        const int addr = lb[t] + k * s;
+        const C v = R[t * pitch + k];
+        if (rdst) rdst[addr] = v.x;
+        else X[addr] = v;
+    });
 }
 
 // ------------------------------------------------------------------ grid coordinates
@@ -1308,14 +1363,34 @@ template <typename T>
 hipError_t launch_predict_fourier(const KModel& m, DevDesc* d, const double* coef, void* cbuf, T* P,
                                   hipStream_t st) {
     hipError_t e;
-    // forward: last (contiguous) axis first, reading the real density
-    for (int a = m.nx - 1; a >= 0; --a) {
+    // forward: last (contiguous) axis first, reading the real density; axis 0 below
+    for (int a = m.nx - 1; a >= 1; --a) {
         e = launch_fft_axis<T>(m, a, a == m.nx - 1 ? P : nullptr, cbuf, nullptr, -1, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_gain<T>, dim3(cdiv(m.ntot, 256)), dim3(256), 0, st, m, d, coef,
-                       static_cast<typename V2<T>::t*>(cbuf));
-    for (int a = 0; a < m.nx; ++a) {
+    // axis 0: forward, gain, inverse in one launch
+    {
+        using C = typename V2<T>::t;
+        const int n = m.N[0], nlines = m.ntot / n;
+        int TL = lines_per_block(n, nlines, sizeof(C));
+        auto lds_of = [&](int tl) {
+            return (2 * (size_t)tl * (n + 1) + n) * sizeof(C) + (size_t)tl * (6 * sizeof(T) + sizeof(int));
+        };
+        while (TL > 1 && lds_of(TL) > 65536) --TL;
+        const FftPlan plan = make_plan(n);
+        const T* rs = m.nx == 1 ? P : nullptr;
+        T* rd = m.nx == 1 ? P : nullptr;
+        C* Xc = static_cast<C*>(cbuf);
+        if (plan_has_odd(plan))
+            hipLaunchKernelGGL((k_fft_gain_axis0<T, true>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * n)),
+                               lds_of(TL), st, m, d, coef, rs, Xc, rd, plan, TL);
+        else
+            hipLaunchKernelGGL((k_fft_gain_axis0<T, false>), dim3(cdiv(nlines, TL)), dim3(block_threads(TL * n)),
+                               lds_of(TL), st, m, d, coef, rs, Xc, rd, plan, TL);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    for (int a = 1; a < m.nx; ++a) {
         e = launch_fft_axis<T>(m, a, nullptr, cbuf, a == m.nx - 1 ? P : nullptr, +1, st);
         if (e != hipSuccess) return e;
     }
