@@ -148,3 +148,14 @@ def test_batch_refuses_fdm_and_sine_filters(B, ctx):
             assert e.value.status == B.PMF_E_INVALID
         finally:
             B.pmf_destroy(f)
+
+
+@pytest.mark.parametrize("integ", ["exact", "rk4"])
+def test_odd_prime_radices_2d(B, ctx, integ):
+    """Radix-7 and radix-17 passes on both kinds of generic axis kernel in FP64: axis 0
+    (N = 28 = 4 7: forward transform, gain and inverse transform in one launch) and
+    axis 1 (N = 34 = 2 17: a separate axis pass each way), sheared grid."""
+    note(f"case: config2 recipe N=(28,34), {integ} (radix-7 and radix-17 passes on both axis kernels), FP64, 2 cycles")
+    sc = W.config2(K=2, N=28, precision=W.FP64)
+    sc.model = sc.model.with_(N=(28, 34), integrator=W.INT_EXACT if integ == "exact" else W.INT_RK4)
+    run_free(B, ctx, sc, 2, 1e-10, what=f"odd-2d-{integ}")
