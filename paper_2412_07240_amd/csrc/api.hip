@@ -317,8 +317,8 @@ size_t filter_device_bytes(const pmf_model& model) {
     build_kmodel(model, km, Wn);
     const size_t es = model.precision == PMF_FP64 ? sizeof(double) : sizeof(float);
     const size_t ntot = (size_t)km.ntot;
-    int chunk = 1024, nb = (km.ntot + chunk - 1) / chunk;
-    if (nb > MAX_RED_BLOCKS) nb = MAX_RED_BLOCKS;
+    int chunk, nb;
+    red_partition(km.ntot, &chunk, &nb);
     size_t b = 4 * ntot * es;
     if (model.grid == PMF_GRID_FOURIER) b += ntot * es * 2;
     b += (size_t)nb * NPART * sizeof(double) + (size_t)nb * sizeof(double);
@@ -401,12 +401,7 @@ pmf_status pmf_create(pmf_ctx* ctx, const pmf_model* model, const pmf_prior* pri
     build_kmodel(*model, f->km, f->Wnom);
     f->ntot = f->km.ntot;
     f->es = model->precision == PMF_FP64 ? sizeof(double) : sizeof(float);
-    f->chunk = 1024;
-    f->nb = (f->ntot + f->chunk - 1) / f->chunk;
-    if (f->nb > MAX_RED_BLOCKS) {
-        f->nb = MAX_RED_BLOCKS;
-        f->chunk = (f->ntot + f->nb - 1) / f->nb;
-    }
+    red_partition(f->ntot, &f->chunk, &f->nb);
     const hipStream_t st = nullptr;
     bool okalloc = true;
     auto A = [&](size_t bytes) {

@@ -54,7 +54,22 @@ struct pmf_filter {
 
 namespace pmf {
 
-constexpr int MAX_RED_BLOCKS = 2048;   // reduction blocks of 1024 points (more: longer chunks)
+constexpr int MAX_RED_BLOCKS = 2048;   // reduction blocks per filter (more points: longer chunks)
+
+// The reduction partition of a filter's ntot points: about 1024 blocks, each of 256 to
+// 1024 points (one to four per thread of a reduction block), at most MAX_RED_BLOCKS
+// blocks (longer chunks beyond), so that the generic passes of small grids still spread
+// over many compute units.
+inline void red_partition(int ntot, int* chunk, int* nb) {
+    int c = (ntot + 1023) / 1024;
+    c = c < 256 ? 256 : (c > 1024 ? 1024 : c);
+    *chunk = c;
+    *nb = (ntot + c - 1) / c;
+    if (*nb > MAX_RED_BLOCKS) {
+        *nb = MAX_RED_BLOCKS;
+        *chunk = (ntot + *nb - 1) / *nb;
+    }
+}
 
 extern thread_local std::string g_last_error;
 pmf_status fail(pmf_status s, const std::string& msg);
