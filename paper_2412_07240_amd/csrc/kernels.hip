@@ -502,6 +502,26 @@ __device__ inline void mode_kappa(int s, int n, T* k1, T* k2) {
     *k1 = (2 * s == n) ? (T)0 : kap;
 }
 
+// Per-mode gain over the whole spectrum, one thread per mode (the RK4 and Euler gains
+// cost a product over the substeps per mode: spread over as many threads as modes)
+template <typename T>
+__global__ void k_gain(KModel m, const DevDesc* d, const double* coef, typename V2<T>::t* X) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m.ntot) return;
+    T k1[MS] = {0, 0, 0, 0}, k2[MS] = {0, 0, 0, 0};
+    int rem = e;
+    for (int a = m.nx - 1; a >= 0; --a) {
+        const int s = rem % m.N[a];
+        rem /= m.N[a];
+        mode_kappa<T>(s, m.N[a], &k1[a], &k2[a]);
+    }
+    const T g = mode_gain<T>(m.integ, d->l, (T)d->h, coef, k1, k2) * (T)(d->etr / (double)m.ntot);
+    typename V2<T>::t v = X[e];
+    v.x *= g;
+    v.y *= g;
+    X[e] = v;
+}
+
 // Axis 0 of a Fourier predict in one launch: forward transform of each axis-0 line,
 // the per-mode gain, inverse transform.  Axis 0 is the last axis of the
 // forward transform and the first of the inverse one, so the three steps need no
@@ -1363,6 +1383,24 @@ template <typename T>
 hipError_t launch_predict_fourier(const KModel& m, DevDesc* d, const double* coef, void* cbuf, T* P,
                                   hipStream_t st) {
     hipError_t e;
+    // The exact integrator's gain is one exponential per mode: axis 0's forward
+    // transform, the gain and axis 0's inverse transform then run as one launch, and so
+    // do they in 1-D, where the whole spectrum is one short line.  The RK4 and Euler
+    // gains of a multi-dimensional grid take a product over the substeps per mode, which
+    // wants one thread per mode: separate launches.
+    if (m.integ != PMF_INT_EXACT && m.nx > 1) {
+        for (int a = m.nx - 1; a >= 0; --a) {
+            e = launch_fft_axis<T>(m, a, a == m.nx - 1 ? P : nullptr, cbuf, nullptr, -1, st);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_gain<T>, dim3(cdiv(m.ntot, 256)), dim3(256), 0, st, m, d, coef,
+                           static_cast<typename V2<T>::t*>(cbuf));
+        for (int a = 0; a < m.nx; ++a) {
+            e = launch_fft_axis<T>(m, a, nullptr, cbuf, a == m.nx - 1 ? P : nullptr, +1, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipGetLastError();
+    }
     // forward: last (contiguous) axis first, reading the real density; axis 0 below
     for (int a = m.nx - 1; a >= 1; --a) {
         e = launch_fft_axis<T>(m, a, a == m.nx - 1 ? P : nullptr, cbuf, nullptr, -1, st);
