@@ -228,3 +228,29 @@ def test_invalid_arguments_are_rejected(B, ctx):
             B.pmf_update(f, [float("nan")])
     finally:
         B.pmf_destroy(f)
+
+
+def test_large_grid_update_recomputes_likelihood(B, ctx):
+    """A grid of more than 2^21 points (160^3) has reduction chunks longer than the
+    likelihood cache of a block, so the multiply pass evaluates each log-likelihood again
+    instead of reading it back: one update from the prior against the oracle (FP64,
+    diagonal A: separable trigonometric re-interpolation)."""
+    from gpu_common import check_density
+    note("case: 3-D Fourier N=160^3 FP64, one update from the prior (likelihood recomputed per pass)")
+    sc = W.config3(K=1, N=16)
+    m = sc.model.with_(grid=W.FOURIER, N=(160, 160, 160), integrator=W.INT_EXACT, precision=W.FP64,
+                       A=np.diag([-0.3, -0.5, -0.7]), Q=np.diag([0.4, 0.5, 0.6]), meas_kind=W.H_LINEAR, nz=3,
+                       H=np.eye(3), **W.gaussian_noise(0.3 ** 2 * np.eye(3)))
+    prior = W.gaussian_prior(np.zeros(3), 0.5 ** 2 * np.eye(3))
+    z = np.array([0.1, 0.0, -0.1])
+    st = oracle.create(m, prior)
+    st_o, ll_o, *_ = oracle.update(m, st, z)
+    f = B.pmf_create(ctx, m, prior)
+    try:
+        ll = B.pmf_update(f, z, want_loglik=True)
+        _, c, M, t, P = B.pmf_get_state(f)
+        e1, em, _, _ = check_density(m, c, M, P, st_o, 1e-10, what="160^3 update")
+        assert abs(ll - ll_o) <= 1e-9 * max(1.0, abs(ll_o)), (ll, ll_o)
+        note(f"  L1 {e1:.2e}, pointwise {em:.2e} of the peak")
+    finally:
+        B.pmf_destroy(f)
