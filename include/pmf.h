@@ -333,10 +333,7 @@ pmf_status pmf_set_schedule(pmf_ctx* ctx, int nx, int N, int variant);
  * op, fused pair or run of a track is on the device at a time, so a track's ops
  * run in submission
  * order; results equal the direct calls on the same filter (fused pairs: bit for
- * bit equal to pmf_batch_step of the filter alone).  A fused cycle that the fused
- * form cannot take at run time (an RK4 / Euler clamp above 64 substeps, which
- * leaves the filter as it was) is run again through pmf_predict / pmf_update
- * before its completions are posted (then not marked fused).  Admission: a track that
+ * bit equal to pmf_batch_step of the filter alone).  Admission: a track that
  * does not fit the server's device-memory budget waits (its ops are queued)
  * until pmf_server_remove_track frees memory; waiting tracks are admitted in the
  * order they were added.  The server owns its tracks' filters.  A server's

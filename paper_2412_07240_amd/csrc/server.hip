@@ -30,7 +30,6 @@ struct SrvOp {
     double T;
     double z[3];
     Clock::time_point t0;
-    bool generic = false;   // run through pmf_predict / pmf_update even if the track is fusable
 };
 
 struct Track {
@@ -116,27 +115,12 @@ static int waiting_tracks(const pmf_server* s) {
     return n;
 }
 
-// Completions of a flight's ops, with their statuses and log-likelihoods.  Ops
-// marked in rerun (a fused cycle the fused form could not take) go back to the
-// front of their track's FIFO, in order, to run on the generic path: no completion.
-static void post(pmf_server* s, const Flight& fl, const std::vector<int>& status, const std::vector<double>& ll,
-                 const std::vector<char>& rerun) {
+// Completions of a flight's ops, with their statuses and log-likelihoods.
+static void post(pmf_server* s, const Flight& fl, const std::vector<int>& status, const std::vector<double>& ll) {
     const Clock::time_point now = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     const bool fused = fl.dyn >= 0;
-    size_t posted = 0;
-    for (size_t k = fl.ops.size(); k-- > 0;) {
-        if (!rerun[k]) continue;
-        SrvOp op = fl.ops[k].op;
-        op.generic = true;
-        s->tracks[fl.ops[k].track].q.push_front(op);
-    }
     for (size_t i = 0; i < fl.ops.size(); ++i) {
-        if (rerun[i]) {
-            s->tracks[fl.ops[i].track].busy = false;
-            continue;
-        }
-        ++posted;
         pmf_completion c;
         c.tag = fl.ops[i].op.tag;
         c.track = fl.ops[i].track;
@@ -151,7 +135,7 @@ static void post(pmf_server* s, const Flight& fl, const std::vector<int>& status
         else s->single_ops++;
     }
     for (size_t i = 0; i < fl.ops.size(); ++i) mark_ready(s, fl.ops[i].track);
-    s->completed += (long long)posted;
+    s->completed += (long long)fl.ops.size();
     s->cv_done.notify_all();
     s->cv_work.notify_one();
 }
@@ -161,7 +145,6 @@ static void retire(pmf_server* s, Flight& fl, hipError_t ev_state) {
     const size_t n = fl.ops.size();
     std::vector<int> status(n, PMF_OK);
     std::vector<double> ll(n, 0.0);
-    std::vector<char> rerun(n, 0);
     const bool dev_ok = ev_state == hipSuccess;
     if (fl.dyn >= 0) {
         const double* out = dyn_loglik(s->db[fl.dyn]);
@@ -171,11 +154,6 @@ static void retire(pmf_server* s, Flight& fl, hipError_t ev_state) {
             status[2 * j] = st;
             ll[2 * j + 1] = st == PMF_OK ? out[j] : NAN;
             status[2 * j + 1] = st != PMF_OK ? st : (std::isnan(out[j]) ? PMF_E_DEGENERATE : PMF_OK);
-            // a rejected fused cycle: if its RK4 / Euler clamp asked for more substeps
-            // than the fused form holds, the cycle left the filter as it was
-            // (PMF_E_INVALID in its status word): run the pair on the generic path
-            if (st == PMF_OK && std::isnan(out[j]) && (take_status(fl.ops[2 * j + 1].f) & PMF_E_INVALID))
-                rerun[2 * j] = rerun[2 * j + 1] = 1;
         }
     } else {
         // at most one update per run: its log-likelihood is in the track's slot
@@ -189,7 +167,7 @@ static void retire(pmf_server* s, Flight& fl, hipError_t ev_state) {
             }
         }
     }
-    post(s, fl, status, ll, rerun);
+    post(s, fl, status, ll);
 }
 
 // The worker: a loop that retires finished device work (event queries, no
@@ -267,7 +245,7 @@ static void worker_main(pmf_server* s) {
                 t.in_ready = false;
                 if (!t.f || t.busy || t.q.empty()) continue;
                 if (t.fusable && t.q.size() >= 2 && t.q[0].op == PMF_OP_PREDICT && t.q[0].T > 0.0 &&
-                    t.q[1].op == PMF_OP_UPDATE && !t.q[0].generic) {
+                    t.q[1].op == PMF_OP_UPDATE) {
                     auto it = fused.find(t.q[0].T);
                     if (it == fused.end()) {
                         if ((int)fused.size() >= free_sets) {

@@ -327,47 +327,3 @@ def test_full_size_serving_mix_sampled(B, ctx):
         for f in twins:
             B.pmf_destroy(f)
         B.pmf_server_destroy(srv)
-
-
-def test_fused_cycle_beyond_the_substep_limit_runs_on_the_generic_path(B, ctx):
-    """A fusable RK4 track whose interval needs more substeps than the fused form holds
-    (64): the server's fused cycle leaves the filter as it was (PMF_E_INVALID in its
-    status word), and the server then runs the pair through pmf_predict / pmf_update.
-    Both completions are PMF_OK and not fused, and the track ends bit for bit where a
-    twin taken through the same two steps ends (pmf_batch_step, then pmf_predict +
-    pmf_update)."""
-    A = np.array([[-0.2, 0.1], [0.05, -0.3]])
-    m = W.ModelSpec(nx=2, A=A, Q=np.diag([0.5, 0.5]), N=(32, 32), t_nominal=0.05, integrator=W.INT_RK4,
-                    substeps=1, precision=W.FP32, meas_kind=W.H_LINEAR, nz=2, H=np.eye(2),
-                    **W.gaussian_noise(0.3 ** 2 * np.eye(2)))
-    prior = W.gaussian_prior([0.0, 0.0], 0.3 ** 2 * np.eye(2))
-    T = 1.0
-    assert oracle.substeps(m, oracle.create(m, prior), T) > 64   # the case's premise
-    note("case: served RK4 track needing more than 64 substeps (32^2, T = 1): fused, then generic")
-    z = np.array([0.1, -0.05])
-    srv = B.pmf_server_create(ctx, 1 << 34, 4)
-    twin = B.pmf_create(ctx, m, prior)
-    try:
-        tr = B.pmf_server_add_track(srv, m, prior)
-        B.pmf_server_submit_cycle(srv, tr, T, z, tag=0)
-        B.pmf_server_drain(srv)
-        done = {c["tag"]: c for c in B.pmf_server_poll(srv)}
-        assert set(done) == {0, 1}, done
-        assert done[0]["status"] == B.PMF_OK and done[1]["status"] == B.PMF_OK, done
-        assert not done[0]["fused"] and not done[1]["fused"], done
-        st = B.pmf_server_stats_get(srv)
-        assert st["completed"] == st["submitted"] == 2 and st["single_ops"] == 2, st
-        B.pmf_batch_step(ctx, [twin], T, z[None, :])
-        assert B.lib().pmf_sync_status(twin, None) & B.PMF_E_INVALID
-        B.pmf_predict(twin, T)
-        ll = B.pmf_update(twin, z, want_loglik=True)
-        assert np.isfinite(ll) and done[1]["loglik"] == ll, (done[1]["loglik"], ll)
-        _, c1, M1, t1, P1 = B.pmf_get_state(B.pmf_server_filter(srv, tr))
-        _, c2, M2, t2, P2 = B.pmf_get_state(twin)
-        assert t1 == t2 == T
-        np.testing.assert_array_equal(c1, c2)
-        np.testing.assert_array_equal(M1, M2)
-        np.testing.assert_array_equal(P1, P2)
-    finally:
-        B.pmf_destroy(twin)
-        B.pmf_server_destroy(srv)
