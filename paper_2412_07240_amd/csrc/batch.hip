@@ -1839,6 +1839,19 @@ static size_t fused_lds(int maxcplx) {
     return 2 * (size_t)maxcplx * sizeof(float2) + (128 + 128 + 130) * sizeof(float2);
 }
 
+// Orders work on stream st after everything queued so far on the null stream (the
+// host-to-device copies below go there; a launch on a non-blocking stream is not
+// otherwise ordered after them).
+static hipError_t stream_after_null(hipStream_t st) {
+    if (st == nullptr) return hipSuccess;
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, nullptr);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+    if (ev) (void)hipEventDestroy(ev);
+    return e;
+}
+
 // The buffer budget takes the whole 160 KiB of a gfx950 compute unit together with
 // the kernel's static LDS: checked here, so that a change to the static LDS fails
 // with this message rather than as a launch error.
@@ -1905,6 +1918,7 @@ static pmf_status build_cache(pmf_ctx* ctx, pmf_filter* const* filters, int n, d
     if (e == hipSuccess) e = hipMemcpy(c->d_items, sorted.data(), sizeof(BItem) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(c->d_groups, groups.data(), sizeof(GItem) * groups.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = stream_after_null(st);
     for (int i = 0; i < BatchCache::ZSLOTS && e == hipSuccess; ++i) {
         e = hipHostMalloc(reinterpret_cast<void**>(&c->h_z[i]), sizeof(double) * n * nzmax, hipHostMallocMapped);
         if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hz_dev[i]), c->h_z[i], 0);
@@ -1965,12 +1979,13 @@ size_t fused_const_bytes() { return sizeof(FConst); }
 
 // the filter's fused-step constants for interval T in its device record
 // f->dconst (uploaded only when T changed)
-static pmf_status upload_consts(pmf_filter* f, double T) {
+static pmf_status upload_consts(pmf_filter* f, double T, hipStream_t st) {
     if (f->dconst_T == T) return PMF_OK;
     FConst k;
     k.m = f->km;
     k.pa = predict_args(f, T);
-    const hipError_t e = hipMemcpy(f->dconst, &k, sizeof(FConst), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(f->dconst, &k, sizeof(FConst), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = stream_after_null(st);
     if (e != hipSuccess) return hip_fail(e, "fused constants upload");
     f->dconst_T = T;
     return PMF_OK;
@@ -2041,7 +2056,7 @@ pmf_status dyn_run(pmf_ctx* ctx, DynBatch* db, pmf_filter* const* filters, int n
             f->bytes += sizeof(FConst);
             f->dconst_T = -1.0;
         }
-        s = upload_consts(f, T);
+        s = upload_consts(f, T, st);
         if (s != PMF_OK) return s;
         BItem& b = items[i];
         b.P[0] = static_cast<float*>(f->buf[0]);
@@ -2647,11 +2662,13 @@ extern "C" pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* fi
     std::sort(na_seen, na_seen + n);
     if (std::adjacent_find(na_seen, na_seen + n) != na_seen + n) return fail(PMF_E_INVALID, "filter listed twice");
 
+    bool uploaded = false;
     for (int i = 0; i < n; ++i) {
         pmf_filter* f = filters[i];
         e = batch_enter(f);
         if (e != hipSuccess) return hip_fail(e, "batch enter");
-        s = upload_consts(f, T);
+        uploaded = uploaded || f->dconst_T != T;
+        s = upload_consts(f, T, nullptr);   // ordered below without an event (nothing allocated)
         if (s != PMF_OK) return s;
         BItem& b = na_items[i];
         b.P[0] = static_cast<float*>(f->buf[0]);
@@ -2681,6 +2698,11 @@ extern "C" pmf_status pmf_batch_step_noalloc(pmf_ctx* ctx, pmf_filter* const* fi
     FPlan* d_plans = reinterpret_cast<FPlan*>(base + NA_PLANS);
     double* d_z = reinterpret_cast<double*>(base + NA_Z);
     double* d_ll = reinterpret_cast<double*>(base + NA_LL);
+    // constants uploaded above (on the null stream) are in place before the launches
+    if (uploaded && st != nullptr) {
+        e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) return hip_fail(e, "fused constants upload");
+    }
     e = hipMemcpyAsync(d_items, na_sorted, sizeof(BItem) * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_groups, na_groups, sizeof(GItem) * ng, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_z, na_z, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st);
